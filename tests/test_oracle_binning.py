@@ -1,0 +1,140 @@
+"""Pins for the oracle's particle -> (shell, pixel) counting (section 2.3 eq. (5),
+section 2.4 eq. (8) and the subvolume decomposition of section 2.4)."""
+
+import math
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import binning as bn
+from oracle import healpix as hp
+
+
+def _radial_histogram(x, y, z, obs, L, R, edges):
+    """Independent per-shell totals: numpy FP64 r^2 against e^2 (exact Fractions near edges)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    e = np.asarray(edges, dtype=np.float64)
+    tot = np.zeros(len(e) - 1, dtype=np.int64)
+    for sx in range(-R, R + 1):
+        for sy in range(-R, R + 1):
+            for sz in range(-R, R + 1):
+                dx = (x - obs[0]) + sx * L
+                dy = (y - obs[1]) + sy * L
+                dz = (z - obs[2]) + sz * L
+                r2 = dx * dx + dy * dy + dz * dz
+                near = np.zeros(r2.shape, dtype=bool)
+                for ev in e:
+                    near |= np.abs(r2 - ev * ev) <= 1e-9 * ev * ev
+                b = np.searchsorted(e * e, r2[~near], side="right") - 1
+                ok = (b >= 0) & (b < len(e) - 1)
+                tot += np.bincount(b[ok], minlength=len(e) - 1)
+                for i in np.nonzero(near)[0]:
+                    s = bn.exact_shell((dx[i], dy[i], dz[i]), list(e), 0, len(e) - 1)
+                    if s is not None:
+                        tot[s] += 1
+    return tot
+
+
+def test_count_conservation_and_radial_totals():
+    L = 100.0
+    x, y, z = synth.uniform_box(20000, L, seed=1)
+    edges = [10.0, 30.0, 55.0, 80.0, 120.0]
+    R = bn.default_n_rep(edges, L)
+    assert R == 1   # boxes [-100,0) .. [100,200) cover 50 +- 120
+    counts, st = bn.bin_shells(x, y, z, (50.0, 50.0, 50.0), L, R, edges, 8)
+    ref = _radial_histogram(x.numpy(), y.numpy(), z.numpy(), (50.0, 50.0, 50.0), L, R, edges)
+    assert np.array_equal(counts.sum(axis=1), ref)
+    assert counts.sum() == st["instances"]
+
+
+def test_bruteforce_equality_small():
+    L = 10.0
+    x, y, z = synth.uniform_box(60, L, seed=2, dtype=__import__("torch").float32)
+    edges = [0.0, 2.5, 5.0, 7.5, 12.0]
+    for nside in (1, 2, 4):
+        fast, _ = bn.bin_shells(x, y, z, (5.0, 5.0, 5.0), L, 1, edges, nside)
+        brute = bn.bin_shells_bruteforce(x, y, z, (5.0, 5.0, 5.0), L, 1, edges, nside)
+        assert np.array_equal(fast, brute)
+
+
+def test_edge_particles_half_open():
+    # radii 1, 2, 3, 2, 3 against edges 0,1,2,3: r = e_b belongs to shell b (eq. (8) read
+    # half-open), r = e_B is outside -> shells get [0, 1, 2]
+    edges = [0.0, 1.0, 2.0, 3.0]
+    obs = (10.0, 10.0, 10.0)
+    xs = np.array([11.0, 12.0, 13.0, 10.0, 10.0], dtype=np.float64)
+    ys = np.array([10.0, 10.0, 10.0, 10.0, 7.0], dtype=np.float64)
+    zs = np.array([10.0, 10.0, 10.0, 12.0, 10.0], dtype=np.float64)
+    counts, st = bn.bin_shells(xs, ys, zs, obs, 100.0, 0, edges, 2)
+    assert counts.sum(axis=1).tolist() == [0, 1, 2]
+    assert st["flagged"] == 5
+
+
+def test_observer_particle_and_invalid():
+    edges = [0.0, 1.0]
+    xs = np.array([5.0, np.nan, 5.0, np.inf], dtype=np.float64)
+    ys = np.array([5.0, 5.0, 5.0, 5.0], dtype=np.float64)
+    zs = np.array([5.0, 5.0, 5.5, 5.0], dtype=np.float64)
+    counts, st = bn.bin_shells(xs, ys, zs, (5.0, 5.0, 5.0), 10.0, 0, edges, 4)
+    assert st["invalid"] == 2
+    assert counts[0, 0] == 2      # the particle at the observer and the one straight up (z = 1) -> pixel 0
+    assert counts.sum() == 2
+
+
+def test_subvolume_and_chunk_invariance():
+    L = 50.0
+    x, y, z = synth.lognormal_box(30000, L, seed=4, ngrid=16)
+    edges = [5.0, 15.0, 25.0, 40.0]
+    obs = (25.0, 25.0, 25.0)
+    one, _ = bn.bin_shells(x, y, z, obs, L, 1, edges, 4)
+    four, _ = bn.bin_shells(x, y, z, obs, L, 1, edges, 4, threads=4)
+    assert np.array_equal(one, four)
+    parts = sum(bn.bin_shells(x[k::3], y[k::3], z[k::3], obs, L, 1, edges, 4)[0] for k in range(3))
+    assert np.array_equal(one, parts)
+    # a shell range reproduces the corresponding rows
+    mid, _ = bn.bin_shells(x, y, z, obs, L, 1, edges, 4, shell_begin=1, shell_end=3)
+    assert np.array_equal(mid, one[1:3])
+
+
+def test_replication_range_is_sufficient():
+    L = 40.0
+    x, y, z = synth.uniform_box(3000, L, seed=5)
+    edges = [10.0, 35.0, 61.0]
+    R = bn.default_n_rep(edges, L)
+    a, _ = bn.bin_shells(x, y, z, (20.0, 20.0, 20.0), L, R, edges, 2)
+    b, _ = bn.bin_shells(x, y, z, (20.0, 20.0, 20.0), L, R + 1, edges, 2)
+    assert np.array_equal(a, b)
+    c, _ = bn.bin_shells(x, y, z, (20.0, 20.0, 20.0), L, R - 1, edges, 2)
+    assert c.sum() < a.sum()
+
+
+def test_flagged_instances_are_resolved():
+    # particles whose directions sit on pixel boundaries and radii on shell edges
+    obs = (0.0, 0.0, 0.0)
+    pts = []
+    for a in range(-2, 3):
+        for b in range(-2, 3):
+            for c in range(-2, 3):
+                if (a, b, c) != (0, 0, 0):
+                    pts.append((float(a), float(b), float(c)))
+    xs, ys, zs = (np.array(v, dtype=np.float64) for v in zip(*pts))
+    edges = [1.0, math.sqrt(2.0), 2.0, 3.0, 3.5]
+    for nside in (1, 2, 4):
+        counts, st = bn.bin_shells(xs, ys, zs, obs, 1000.0, 0, edges, nside)
+        assert st["flagged"] > 0
+        brute = bn.bin_shells_bruteforce(xs, ys, zs, obs, 1000.0, 0, edges, nside)
+        assert np.array_equal(counts, brute)
+
+
+def test_empty_and_degenerate():
+    e = np.zeros(0)
+    counts, st = bn.bin_shells(e, e, e, (0, 0, 0), 1.0, 0, [0.0, 1.0], 1)
+    assert counts.shape == (1, 12) and counts.sum() == 0
+    with pytest.raises(ValueError):
+        bn.bin_shells(e, e, e, (0, 0, 0), 1.0, 0, [1.0, 1.0], 1)
+    with pytest.raises(ValueError):
+        bn.bin_shells(e, e, e, (0, 0, 0), 1.0, 0, [0.0, 1.0], 0)
