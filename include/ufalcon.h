@@ -1,0 +1,225 @@
+/*
+ * ufalcon — MI355X (gfx950) library for the data-parallel hot path of the
+ * UFalcon multi-lens-plane method (Sgier, Refregier, Amara & Nicola,
+ * "Fast Generation of Covariance Matrices for Weak Lensing", arXiv:1801.05745):
+ * particles -> (radial shell, HEALPix RING pixel) count maps, then the Born
+ * convergence sum kappa[p] = sum_b W_b (n_b[p]/nbar_b - 1), with its adjoint and
+ * batched forms.
+ *
+ * Conventions for every entry point
+ *   - Return value: UFALCON_OK (0) or a negative ufalcon_err code; nothing
+ *     throws across this boundary.  ufalcon_strerror() names a code.
+ *   - "device" pointers are HIP device memory owned by the caller; "host"
+ *     pointers are read before the call returns and may be reused at once.
+ *   - Work is enqueued on `stream` (a hipStream_t, NULL = default stream) and is
+ *     asynchronous; outputs are valid after the stream is synchronised.
+ *   - Conditions found on the device (non-finite inputs, guard-band fallbacks)
+ *     are added to a caller-owned device ufalcon_status.
+ *   - Count maps are uint32 [n_shells][12*nside^2], row-major, and binning
+ *     ADDS to them, so chunks, nested boxes and subvolumes compose; the caller
+ *     zeroes them (ufalcon_fill_u32).
+ *   - Arguments are validated on the host before anything is enqueued; on an
+ *     error return nothing has been enqueued.
+ */
+#ifndef UFALCON_H
+#define UFALCON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *ufalcon_stream_t; /* hipStream_t */
+
+typedef enum ufalcon_err {
+    UFALCON_OK = 0,
+    UFALCON_EINVAL = -1,          /* null pointer, negative size, bad enum value */
+    UFALCON_EUNSORTED_EDGES = -2, /* shell edges not finite, >= 0 and strictly ascending */
+    UFALCON_ENSIDE = -3,          /* nside outside [1, 8192] */
+    UFALCON_EOVERFLOW = -4,       /* a uint32 count cell could exceed 2^32 - 1 */
+    UFALCON_EWORKSPACE = -5,      /* workspace missing or too small */
+    UFALCON_EHIP = -6,            /* a HIP runtime call failed */
+    UFALCON_ETOO_MANY_SHELLS = -7 /* more than UFALCON_MAX_SHELLS shells or UFALCON_MAX_BINS source bins */
+} ufalcon_err;
+
+#define UFALCON_MAX_SHELLS 256
+#define UFALCON_MAX_NSIDE 8192
+#define UFALCON_MAX_BINS 8
+#define UFALCON_NPARAM 4 /* derivative slots: 0 Omega_m, then the source parameters */
+
+typedef enum ufalcon_dtype { UFALCON_F32 = 0, UFALCON_F64 = 1 } ufalcon_dtype;
+
+/* Device-side counters, accumulated by binning calls (zero it to start). */
+typedef struct ufalcon_status {
+    unsigned long long n_instances;  /* particle images counted into a (shell, pixel) cell */
+    unsigned long long n_invalid;    /* particles skipped for a non-finite coordinate */
+    unsigned long long n_guarded;    /* instances decided by the exact path (near a boundary) */
+    unsigned long long n_unresolved; /* instances the exact path could not certify (expected 0) */
+} ufalcon_status;
+
+const char *ufalcon_strerror(int code);
+int ufalcon_version(void);
+
+/* Fill n uint32 words with `value` (a kernel, not a memset: safe inside graph capture). */
+int ufalcon_fill_u32(uint32_t *p, int64_t n, uint32_t value, ufalcon_stream_t stream);
+
+/*
+ * Shell binning (section 2.3 eq. (5): n_p(pix, Delta chi_b), the number of
+ * particles of shell b in pixel pix; section 2.4 eq. (8): shells by comoving
+ * radius with the observer at the box centre; section 2.4: HEALPix RING
+ * pixelisation with 12*nside^2 pixels, subvolume maps summed).
+ *
+ * x, y, z      device SoA positions, n values each, dtype UFALCON_F32 or UFALCON_F64,
+ *              comoving Mpc/h; a particle with a non-finite coordinate is
+ *              skipped and counted in status->n_invalid.
+ * observer     host double[3].
+ * box_L, n_rep periodic images s in {-n_rep..n_rep}^3 of every particle are
+ *              binned: d = fl64(fl64(x - o) + fl64(s * box_L)) per axis
+ *              (n_rep = 0: no replication).
+ * chi_edges    host double[n_shells + 1], finite, >= 0, strictly ascending.
+ * shell range  only shells b in [shell_begin, shell_end) are binned
+ *              (nesting: one source per shell range).
+ * counts       device uint32 [n_shells][12*nside^2]; cell (b, pix) += 1 for every
+ *              instance with chi_b <= |d| < chi_{b+1} (half-open) and RING pixel pix
+ *              of the direction d.
+ * Exactness: every count equals the exact-real function of the FP64 d; FP64
+ * decisions near a boundary are re-taken exactly on the device and counted
+ * in status->n_guarded.
+ * workspace    device, 256-byte aligned, at least ufalcon_bin_shells_workspace_size(0)
+ *              bytes: it lists the guarded instances for the exact pass.  A larger
+ *              one (ufalcon_bin_shells_workspace_size(k) lists k) avoids a second
+ *              walk over all images when more than that many are guarded.  Calls
+ *              sharing a workspace must be stream-ordered.
+ * Errors: EINVAL, EUNSORTED_EDGES, ENSIDE, ETOO_MANY_SHELLS, EWORKSPACE, EOVERFLOW
+ * (host bound on the instances one cell can receive in this call exceeds
+ * 2^32 - 1), EHIP.
+ */
+size_t ufalcon_bin_shells_workspace_size(int64_t max_listed);
+int ufalcon_bin_shells(const void *x, const void *y, const void *z, int64_t n, int dtype,
+                       const double *observer, double box_L, int32_t n_rep,
+                       const double *chi_edges, int32_t n_shells, int32_t shell_begin, int32_t shell_end,
+                       int64_t nside, uint32_t *counts, ufalcon_status *status,
+                       void *workspace, size_t workspace_bytes, ufalcon_stream_t stream);
+
+/* Source redshift distributions for the lensing weights. */
+typedef enum ufalcon_source_kind { UFALCON_SOURCE_DELTA = 0, UFALCON_SOURCE_SMAIL = 1 } ufalcon_source_kind;
+
+typedef struct ufalcon_source {
+    int32_t kind;  /* ufalcon_source_kind */
+    double z_s;    /* DELTA: source redshift (derivative slot 1) */
+    double alpha;  /* SMAIL n(z) ~ z^alpha exp(-(z/z0)^beta) on [0, z_max]: slot 1 */
+    double beta;   /* slot 2 */
+    double z0;     /* slot 3 */
+    double z_max;  /* support end (not differentiated) */
+} ufalcon_source;
+
+/*
+ * Comoving distance chi(z) = (c/H0) int_0^z dz'/E(z') in Mpc/h for flat
+ * LambdaCDM, E = sqrt(Om (1+z)^3 + 1 - Om) (section 2.3: D(z) = (H0/c) chi(z)).
+ * z, chi: device double[n].
+ */
+int ufalcon_comoving_distance(const double *z, int64_t n, double omega_m, double *chi, ufalcon_stream_t stream);
+
+/*
+ * Born lensing weights of each shell for T source bins (section 2.3 eqs. (1)-(3),
+ * (6)): W[t][b] = (3/2) Om int over the shell of (1+z) D(z) q_t(z) dD, with
+ * q = 1 - D/D_s for a delta source (zero behind it) and
+ * q = int_z^{z_max} nhat(z') (1 - D(z)/D(z')) dz' for an n(z).  The comoving
+ * edges stay fixed when Omega_m changes (their redshifts move).
+ * chi_edges host double[n_shells+1]; sources host [T]; W device double[T][n_shells];
+ * dW device double[T][n_shells][UFALCON_NPARAM] (dW/dOmega_m and dW/d source
+ * parameters, forward-mode) or NULL.
+ */
+int ufalcon_lensing_weights(double omega_m, const ufalcon_source *sources, int32_t T,
+                            const double *chi_edges, int32_t n_shells, double *W, double *dW,
+                            ufalcon_stream_t stream);
+
+/* grad_theta[t][k] = sum_b grad_W[t][b] * dW[t][b][k] (device, double). */
+int ufalcon_lensing_weights_vjp(const double *dW, const double *grad_W, int32_t T, int32_t n_shells,
+                                double *grad_theta, ufalcon_stream_t stream);
+
+typedef enum ufalcon_nbar_mode { UFALCON_NBAR_EXACT_VOLUME = 0, UFALCON_NBAR_LOWER_EDGE = 1 } ufalcon_nbar_mode;
+
+/*
+ * 1/nbar_b for shells [shell_begin, shell_end): nbar_b = (n_src / box_L^3) V_b / N_pix
+ * with V_b = (4 pi/3)(chi_{b+1}^3 - chi_b^3) (EXACT_VOLUME) or 4 pi chi_b^2 Delta chi_b
+ * (LOWER_EDGE, eq. (6) literally); section 2.3 eq. (5): rho ~ m_p N / V.
+ * inv_nbar: device double[n_shells]; entries outside the range are not written.
+ */
+int ufalcon_inv_nbar(int64_t n_src, double box_L, const double *chi_edges, int32_t n_shells,
+                     int32_t shell_begin, int32_t shell_end, int64_t nside, int32_t mode,
+                     double *inv_nbar, ufalcon_stream_t stream);
+
+/*
+ * Born convergence (section 2.3 eq. (6)):
+ *   kappa[t][p] = sum_b W[t][b] * (counts[b][p] * inv_nbar[b] - 1)
+ * accumulated in FP64 in shell order, rounded once to out_dtype.
+ * counts device uint32 [n_shells][npix]; W device double[T][n_shells];
+ * inv_nbar device double[n_shells]; kappa device [T][npix] of out_dtype.
+ */
+int ufalcon_born_kappa(const uint32_t *counts, int32_t n_shells, int64_t nside, const double *W,
+                       const double *inv_nbar, int32_t T, void *kappa, int out_dtype, ufalcon_stream_t stream);
+
+/*
+ * Projected overdensity (section 2.3 eq. (7)): the Born sum with weights
+ * Delta chi_b / sum_b Delta chi_b over shells [0, n_shells).  delta device [npix].
+ */
+int ufalcon_overdensity(const uint32_t *counts, int32_t n_shells, int64_t nside, const double *chi_edges,
+                        const double *inv_nbar, void *delta, int out_dtype, ufalcon_stream_t stream);
+
+/*
+ * Adjoint of the Born sum with respect to the weights:
+ *   grad_W[t][b] = sum_p grad_kappa[t][p] * (counts[b][p] * inv_nbar[b] - 1)
+ * as a deterministic two-stage FP64 reduction (fixed order, bitwise
+ * reproducible).  grad_kappa device [T][npix] of grad_dtype; grad_W device
+ * double[T][n_shells]; workspace device, at least
+ * ufalcon_born_kappa_adjoint_workspace_size() bytes.
+ */
+size_t ufalcon_born_kappa_adjoint_workspace_size(int32_t n_shells, int64_t nside, int32_t T);
+int ufalcon_born_kappa_adjoint(const uint32_t *counts, int32_t n_shells, int64_t nside, const double *inv_nbar,
+                               const void *grad_kappa, int grad_dtype, int32_t T, double *grad_W,
+                               void *workspace, size_t workspace_bytes, ufalcon_stream_t stream);
+
+/*
+ * Batched form: many realisations (section 2.2 and 3.2: 150 independent maps
+ * for the covariance) with uneven particle counts and shell sets, binned by
+ * one persistent launch over a work queue of (realisation, tile) items and
+ * reduced by one batched Born launch.  A plan holds device copies of the
+ * descriptors and may hold a captured HIP graph.
+ */
+typedef struct ufalcon_batch_item {
+    const void *x, *y, *z;     /* device positions */
+    int64_t n;                 /* particles */
+    double observer[3];
+    double box_L;
+    int32_t n_rep;
+    int32_t n_shells;          /* shells of this realisation */
+    int32_t shell_begin, shell_end;
+    const double *chi_edges;   /* host double[n_shells+1] (copied into the plan) */
+    uint32_t *counts;          /* device [n_shells][npix] */
+    const double *W;           /* device double[T][n_shells] (for the Born launch) */
+    const double *inv_nbar;    /* device double[n_shells] */
+    void *kappa;               /* device [T][npix] of the plan's out_dtype */
+} ufalcon_batch_item;
+
+typedef struct ufalcon_batch_plan ufalcon_batch_plan;
+
+/* tile: particles per work item (0 = autotuned default); persistent_wgs: workgroups (0 = default). */
+int ufalcon_batch_plan_create(const ufalcon_batch_item *items, int32_t n_items, int dtype, int64_t nside,
+                              int32_t T, int out_dtype, int64_t tile, int32_t persistent_wgs,
+                              ufalcon_batch_plan **plan);
+int ufalcon_batch_plan_destroy(ufalcon_batch_plan *plan);
+/* Zero every count map of the plan. */
+int ufalcon_batch_clear(ufalcon_batch_plan *plan, ufalcon_stream_t stream);
+int ufalcon_bin_shells_batched(ufalcon_batch_plan *plan, ufalcon_status *status, ufalcon_stream_t stream);
+int ufalcon_born_kappa_batched(ufalcon_batch_plan *plan, ufalcon_stream_t stream);
+/* clear + bin + Born for the whole batch as one captured HIP graph (captured on first use, replayed after). */
+int ufalcon_batch_run_graph(ufalcon_batch_plan *plan, ufalcon_status *status, ufalcon_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UFALCON_H */

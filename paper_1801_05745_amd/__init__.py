@@ -1,0 +1,431 @@
+"""Python binding of libufalcon (MI355X / gfx950): shell binning onto HEALPix RING
+count maps and the Born convergence sum with its adjoint (UFalcon, arXiv:1801.05745,
+sections 2.3-2.4).
+
+The functions mirror the C entry points in include/ufalcon.h one to one; they
+only marshal torch tensors (device memory) and the current HIP stream into the
+C-ABI.  Every step of the computation runs in the library's HIP kernels.  There
+is no CPU fallback: without the built library every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libufalcon.so")
+
+F32, F64 = 0, 1
+SOURCE_DELTA, SOURCE_SMAIL = 0, 1
+NBAR_EXACT_VOLUME, NBAR_LOWER_EDGE = 0, 1
+NPARAM = 4
+MAX_SHELLS = 256
+MAX_BINS = 8
+C_OVER_H0 = 2997.92458
+
+_lib = None
+
+
+class UfalconError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _lib.ufalcon_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{where}: {msg} (code {code})")
+
+
+class Status(ctypes.Structure):
+    _fields_ = [("n_instances", ctypes.c_ulonglong), ("n_invalid", ctypes.c_ulonglong),
+                ("n_guarded", ctypes.c_ulonglong), ("n_unresolved", ctypes.c_ulonglong)]
+
+
+class Source(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("z_s", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("beta", ctypes.c_double), ("z0", ctypes.c_double), ("z_max", ctypes.c_double)]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("observer", ctypes.c_double * 3), ("box_L", ctypes.c_double), ("n_rep", ctypes.c_int32),
+                ("n_shells", ctypes.c_int32), ("shell_begin", ctypes.c_int32), ("shell_end", ctypes.c_int32),
+                ("chi_edges", ctypes.POINTER(ctypes.c_double)), ("counts", ctypes.c_void_p),
+                ("W", ctypes.c_void_p), ("inv_nbar", ctypes.c_void_p), ("kappa", ctypes.c_void_p)]
+
+
+_P = ctypes.c_void_p
+_I32, _I64, _D, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+_SIGS = {
+    "ufalcon_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "ufalcon_version": (ctypes.c_int, []),
+    "ufalcon_fill_u32": (ctypes.c_int, [_P, _I64, ctypes.c_uint32, _P]),
+    "ufalcon_bin_shells_workspace_size": (_SZ, [_I64]),
+    "ufalcon_bin_shells": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, ctypes.POINTER(_D), _D, _I32,
+                                          ctypes.POINTER(_D), _I32, _I32, _I32, _I64, _P, _P, _P, _SZ, _P]),
+    "ufalcon_comoving_distance": (ctypes.c_int, [_P, _I64, _D, _P, _P]),
+    "ufalcon_lensing_weights": (ctypes.c_int, [_D, ctypes.POINTER(Source), _I32, ctypes.POINTER(_D), _I32,
+                                               _P, _P, _P]),
+    "ufalcon_lensing_weights_vjp": (ctypes.c_int, [_P, _P, _I32, _I32, _P, _P]),
+    "ufalcon_inv_nbar": (ctypes.c_int, [_I64, _D, ctypes.POINTER(_D), _I32, _I32, _I32, _I64, _I32, _P, _P]),
+    "ufalcon_born_kappa": (ctypes.c_int, [_P, _I32, _I64, _P, _P, _I32, _P, ctypes.c_int, _P]),
+    "ufalcon_overdensity": (ctypes.c_int, [_P, _I32, _I64, ctypes.POINTER(_D), _P, _P, ctypes.c_int, _P]),
+    "ufalcon_born_kappa_adjoint_workspace_size": (_SZ, [_I32, _I64, _I32]),
+    "ufalcon_born_kappa_adjoint": (ctypes.c_int, [_P, _I32, _I64, _P, _P, ctypes.c_int, _I32, _P, _P, _SZ, _P]),
+    "ufalcon_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(BatchItem), _I32, ctypes.c_int, _I64, _I32,
+                                                 ctypes.c_int, _I64, _I32, ctypes.POINTER(_P)]),
+    "ufalcon_batch_plan_destroy": (ctypes.c_int, [_P]),
+    "ufalcon_batch_clear": (ctypes.c_int, [_P, _P]),
+    "ufalcon_bin_shells_batched": (ctypes.c_int, [_P, _P, _P]),
+    "ufalcon_born_kappa_batched": (ctypes.c_int, [_P, _P]),
+    "ufalcon_batch_run_graph": (ctypes.c_int, [_P, _P, _P]),
+}
+
+
+def exported_symbols():
+    """Names of the C entry points this binding expects (one per declaration in ufalcon.h)."""
+    return sorted(_SIGS)
+
+
+def load():
+    """Load libufalcon.so (built in-tree); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise UfalconError(rc, where)
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dtype_code(dt):
+    if dt == torch.float32:
+        return F32
+    if dt == torch.float64:
+        return F64
+    raise TypeError(f"unsupported dtype {dt}")
+
+
+def _host_doubles(vals):
+    vals = [float(v) for v in vals]
+    return (ctypes.c_double * len(vals))(*vals), len(vals)
+
+
+def npix(nside: int) -> int:
+    return 12 * int(nside) * int(nside)
+
+
+# ---------------------------------------------------------------- workspaces
+
+_ws_cache = {}
+
+
+def _workspace(nbytes: int, device, key: str):
+    """A cached device byte buffer of at least nbytes (256-byte aligned by the caching allocator)."""
+    k = (key, str(device))
+    buf = _ws_cache.get(k)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[k] = buf
+    return buf
+
+
+def bin_shells_workspace(max_listed: int = 1 << 20, device="cuda"):
+    lib = load()
+    return _workspace(int(lib.ufalcon_bin_shells_workspace_size(max_listed)), device, "bin")
+
+
+def new_status(device="cuda"):
+    """A zeroed device ufalcon_status (4 x uint64)."""
+    return torch.zeros(4, dtype=torch.int64, device=device)
+
+
+def status_dict(st: torch.Tensor):
+    v = st.cpu().tolist()
+    return {"n_instances": v[0], "n_invalid": v[1], "n_guarded": v[2], "n_unresolved": v[3]}
+
+
+# ---------------------------------------------------------------- entry points
+
+def fill_u32(t: torch.Tensor, value: int = 0):
+    lib = load()
+    assert t.dtype == torch.uint32 and t.is_contiguous() and t.is_cuda
+    _check(lib.ufalcon_fill_u32(_ptr(t), t.numel(), value, _stream(t.device)), "ufalcon_fill_u32")
+    return t
+
+
+def new_counts(n_shells: int, nside: int, device="cuda"):
+    t = torch.empty((n_shells, npix(nside)), dtype=torch.uint32, device=device)
+    return fill_u32(t, 0)
+
+
+def bin_shells(x, y, z, chi_edges, nside, observer=None, box_L=0.0, n_rep=0, shell_begin=0, shell_end=None,
+               counts=None, status=None, workspace=None):
+    """Add the particles' (shell, RING pixel) counts to `counts` (uint32 [n_shells][npix]).
+
+    x, y, z: contiguous float32 or float64 device tensors of equal length.
+    chi_edges: shell edges in Mpc/h (host sequence, n_shells + 1 values).
+    """
+    lib = load()
+    if not (x.dtype == y.dtype == z.dtype) or not (x.numel() == y.numel() == z.numel()):
+        raise ValueError("x, y, z must share dtype and length")
+    for t in (x, y, z):
+        if not (t.is_cuda and t.is_contiguous()):
+            raise ValueError("positions must be contiguous device tensors")
+    e, ne = _host_doubles(chi_edges)
+    n_shells = ne - 1
+    if shell_end is None:
+        shell_end = n_shells
+    if observer is None:
+        observer = (0.5 * box_L,) * 3
+    obs, _ = _host_doubles(observer)
+    if counts is None:
+        counts = new_counts(n_shells, nside, x.device)
+    if counts.dtype != torch.uint32 or not counts.is_contiguous() or counts.numel() != n_shells * npix(nside):
+        raise ValueError("counts must be contiguous uint32 [n_shells][12 nside^2]")
+    if workspace is None:
+        workspace = bin_shells_workspace(device=x.device)
+    rc = lib.ufalcon_bin_shells(_ptr(x), _ptr(y), _ptr(z), x.numel(), _dtype_code(x.dtype), obs, float(box_L),
+                                int(n_rep), e, n_shells, int(shell_begin), int(shell_end), int(nside), _ptr(counts),
+                                _ptr(status), _ptr(workspace), workspace.numel(), _stream(x.device))
+    _check(rc, "ufalcon_bin_shells")
+    return counts
+
+
+def comoving_distance(z: torch.Tensor, omega_m: float):
+    lib = load()
+    z = z.to(torch.float64).contiguous()
+    chi = torch.empty_like(z)
+    _check(lib.ufalcon_comoving_distance(_ptr(z), z.numel(), float(omega_m), _ptr(chi), _stream(z.device)),
+           "ufalcon_comoving_distance")
+    return chi
+
+
+@dataclass
+class SourceSpec:
+    """One source bin: kind "delta" (z_s) or "smail" (alpha, beta, z0, z_max)."""
+    kind: str
+    z_s: float = 0.0
+    alpha: float = 0.0
+    beta: float = 0.0
+    z0: float = 0.0
+    z_max: float = 0.0
+
+    def params(self):
+        """Differentiable parameters in derivative slots 1..3."""
+        if self.kind == "delta":
+            return [self.z_s, 0.0, 0.0]
+        return [self.alpha, self.beta, self.z0]
+
+    def with_params(self, p):
+        if self.kind == "delta":
+            return SourceSpec("delta", z_s=float(p[0]))
+        return SourceSpec("smail", alpha=float(p[0]), beta=float(p[1]), z0=float(p[2]), z_max=self.z_max)
+
+    def c_struct(self):
+        if self.kind == "delta":
+            return Source(SOURCE_DELTA, self.z_s, 0.0, 0.0, 0.0, 0.0)
+        if self.kind == "smail":
+            return Source(SOURCE_SMAIL, 0.0, self.alpha, self.beta, self.z0, self.z_max)
+        raise ValueError(self.kind)
+
+
+def lensing_weights(omega_m, sources, chi_edges, with_derivatives=False, device="cuda"):
+    """W [T][B] (float64, device) and optionally dW [T][B][4] (d/dOmega_m, d/d source parameters)."""
+    lib = load()
+    srcs = (Source * len(sources))(*[s.c_struct() for s in sources])
+    e, ne = _host_doubles(chi_edges)
+    T, B = len(sources), ne - 1
+    W = torch.empty((T, B), dtype=torch.float64, device=device)
+    dW = torch.empty((T, B, NPARAM), dtype=torch.float64, device=device) if with_derivatives else None
+    _check(lib.ufalcon_lensing_weights(float(omega_m), srcs, T, e, B, _ptr(W), _ptr(dW), _stream(W.device)),
+           "ufalcon_lensing_weights")
+    return (W, dW) if with_derivatives else W
+
+
+def lensing_weights_vjp(dW, grad_W):
+    lib = load()
+    T, B, _ = dW.shape
+    out = torch.empty((T, NPARAM), dtype=torch.float64, device=dW.device)
+    gW = grad_W.to(torch.float64).contiguous()
+    _check(lib.ufalcon_lensing_weights_vjp(_ptr(dW), _ptr(gW), T, B, _ptr(out), _stream(dW.device)),
+           "ufalcon_lensing_weights_vjp")
+    return out
+
+
+def inv_nbar(n_src, box_L, chi_edges, nside, mode=NBAR_EXACT_VOLUME, shell_begin=0, shell_end=None, out=None,
+             device="cuda"):
+    """1 / nbar_b (float64 device [n_shells]) for shells [shell_begin, shell_end)."""
+    lib = load()
+    e, ne = _host_doubles(chi_edges)
+    B = ne - 1
+    if shell_end is None:
+        shell_end = B
+    if out is None:
+        out = torch.zeros(B, dtype=torch.float64, device=device)
+    _check(lib.ufalcon_inv_nbar(int(n_src), float(box_L), e, B, int(shell_begin), int(shell_end), int(nside),
+                                int(mode), _ptr(out), _stream(out.device)), "ufalcon_inv_nbar")
+    return out
+
+
+def born_kappa(counts, W, inv_nbar_, out_dtype=torch.float32):
+    """kappa [T][npix] = sum_b W[t][b] (counts[b] * inv_nbar[b] - 1)."""
+    lib = load()
+    B, npx = counts.shape
+    W = W.to(torch.float64).contiguous()
+    if W.dim() == 1:
+        W = W[None, :]
+    T = W.shape[0]
+    nside = int(round((npx / 12) ** 0.5))
+    out = torch.empty((T, npx), dtype=out_dtype, device=counts.device)
+    _check(lib.ufalcon_born_kappa(_ptr(counts), B, nside, _ptr(W), _ptr(inv_nbar_), T, _ptr(out),
+                                  _dtype_code(out_dtype), _stream(counts.device)), "ufalcon_born_kappa")
+    return out
+
+
+def overdensity(counts, chi_edges, inv_nbar_, out_dtype=torch.float32):
+    lib = load()
+    B, npx = counts.shape
+    nside = int(round((npx / 12) ** 0.5))
+    e, _ = _host_doubles(chi_edges)
+    out = torch.empty(npx, dtype=out_dtype, device=counts.device)
+    _check(lib.ufalcon_overdensity(_ptr(counts), B, nside, e, _ptr(inv_nbar_), _ptr(out), _dtype_code(out_dtype),
+                                   _stream(counts.device)), "ufalcon_overdensity")
+    return out
+
+
+def born_kappa_adjoint(counts, inv_nbar_, grad_kappa):
+    """grad_W [T][B] = sum_p grad_kappa[t][p] (counts[b][p] inv_nbar[b] - 1), deterministic."""
+    lib = load()
+    B, npx = counts.shape
+    nside = int(round((npx / 12) ** 0.5))
+    g = grad_kappa.contiguous()
+    if g.dim() == 1:
+        g = g[None, :]
+    T = g.shape[0]
+    nbytes = int(lib.ufalcon_born_kappa_adjoint_workspace_size(B, nside, T))
+    ws = _workspace(nbytes, counts.device, "adjoint")
+    out = torch.empty((T, B), dtype=torch.float64, device=counts.device)
+    _check(lib.ufalcon_born_kappa_adjoint(_ptr(counts), B, nside, _ptr(inv_nbar_), _ptr(g), _dtype_code(g.dtype), T,
+                                          _ptr(out), _ptr(ws), ws.numel(), _stream(counts.device)),
+           "ufalcon_born_kappa_adjoint")
+    return out
+
+
+# ---------------------------------------------------------------- autograd
+
+class BornKappa(torch.autograd.Function):
+    """kappa = Born sum of fixed counts with differentiable weights W [T][B]."""
+
+    @staticmethod
+    def forward(ctx, W, counts, inv_nbar_, out_dtype=torch.float32):
+        ctx.save_for_backward(counts, inv_nbar_)
+        return born_kappa(counts, W, inv_nbar_, out_dtype)
+
+    @staticmethod
+    def backward(ctx, grad_kappa):
+        counts, inv_nbar_ = ctx.saved_tensors
+        return born_kappa_adjoint(counts, inv_nbar_, grad_kappa), None, None, None
+
+
+class LensingWeights(torch.autograd.Function):
+    """W [T][B] from Omega_m (0-d float64) and source parameters [T][3] (float64, host)."""
+
+    @staticmethod
+    def forward(ctx, omega_m, params, sources, chi_edges, device):
+        srcs = [s.with_params(params[t].tolist()) for t, s in enumerate(sources)]
+        W, dW = lensing_weights(float(omega_m), srcs, chi_edges, with_derivatives=True, device=device)
+        ctx.save_for_backward(dW)
+        ctx.host_device = omega_m.device
+        return W
+
+    @staticmethod
+    def backward(ctx, grad_W):
+        (dW,) = ctx.saved_tensors
+        gt = lensing_weights_vjp(dW, grad_W).to(ctx.host_device)
+        return gt[:, 0].sum(), gt[:, 1:], None, None, None
+
+
+# ---------------------------------------------------------------- batched
+
+class BatchPlan:
+    """Many realisations binned by one persistent launch and reduced by one batched Born launch.
+
+    items: list of dicts with keys x, y, z (device), chi_edges (host), box_L, n_rep,
+    observer (optional), shell_begin/shell_end (optional), counts (uint32 device),
+    and for the Born pass W, inv_nbar, kappa (device).
+    """
+
+    def __init__(self, items, nside, T=1, out_dtype=torch.float32, tile=0, persistent_wgs=0):
+        lib = load()
+        self._keep = []
+        arr = (BatchItem * len(items))()
+        dtype = None
+        for k, it in enumerate(items):
+            e, ne = _host_doubles(it["chi_edges"])
+            self._keep.append(e)
+            obs = it.get("observer") or (0.5 * it["box_L"],) * 3
+            x, y, z = it["x"], it["y"], it["z"]
+            dtype = _dtype_code(x.dtype)
+            arr[k].x, arr[k].y, arr[k].z = x.data_ptr(), y.data_ptr(), z.data_ptr()
+            arr[k].n = x.numel()
+            for j in range(3):
+                arr[k].observer[j] = float(obs[j])
+            arr[k].box_L = float(it["box_L"])
+            arr[k].n_rep = int(it.get("n_rep", 0))
+            arr[k].n_shells = ne - 1
+            arr[k].shell_begin = int(it.get("shell_begin", 0))
+            arr[k].shell_end = int(it.get("shell_end", ne - 1))
+            arr[k].chi_edges = e
+            arr[k].counts = it["counts"].data_ptr()
+            arr[k].W = it["W"].data_ptr() if it.get("W") is not None else None
+            arr[k].inv_nbar = it["inv_nbar"].data_ptr() if it.get("inv_nbar") is not None else None
+            arr[k].kappa = it["kappa"].data_ptr() if it.get("kappa") is not None else None
+        self.items = items
+        handle = ctypes.c_void_p()
+        _check(lib.ufalcon_batch_plan_create(arr, len(items), dtype, int(nside), int(T), _dtype_code(out_dtype),
+                                             int(tile), int(persistent_wgs), ctypes.byref(handle)),
+               "ufalcon_batch_plan_create")
+        self.handle = handle
+
+    def clear(self):
+        _check(load().ufalcon_batch_clear(self.handle, _stream()), "ufalcon_batch_clear")
+
+    def bin(self, status=None):
+        _check(load().ufalcon_bin_shells_batched(self.handle, _ptr(status), _stream()), "ufalcon_bin_shells_batched")
+
+    def born(self):
+        _check(load().ufalcon_born_kappa_batched(self.handle, _stream()), "ufalcon_born_kappa_batched")
+
+    def run_graph(self, status=None):
+        _check(load().ufalcon_batch_run_graph(self.handle, _ptr(status), _stream()), "ufalcon_batch_run_graph")
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.ufalcon_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

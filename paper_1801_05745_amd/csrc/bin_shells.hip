@@ -1,0 +1,734 @@
+// Shell binning: particles -> (radial shell, HEALPix RING pixel) count maps,
+// plain and batched.
+//
+// Section 2.3 eq. (5) counts n_p(pix, Delta chi_b), the particles of shell b in
+// pixel pix; section 2.4 eq. (8) assigns shells by comoving radius around an
+// observer at the box centre, and builds the map from independent subvolumes
+// whose maps are summed.  On one GPU the subvolumes are particle tiles: every
+// wavefront streams its particles (coalesced SoA loads), generates their
+// periodic images, and adds one to the count cell of every image in range.
+//
+// Per wavefront the work is split in two phases to keep the 64 lanes busy:
+//   A. each lane walks the images of its particle and tests the squared radius
+//      against the (guard-widened) shell range: cheap FP64 adds and multiplies;
+//      images in range are appended to a per-wave queue in LDS (ballot prefix);
+//   B. whenever 64 queued images are ready, every lane takes one and runs the
+//      FP64 shell search and RING pixelisation, then one global atomic add.
+// Without the queue, phase B would run for every image slot with only the
+// in-range lanes active (about a third for the configurations of interest).
+//
+// Instances whose FP64 decisions fall inside a guard band (a few per 10^8) are
+// not decided here: their vectors go to a list in the caller's workspace and a
+// second kernel decides them exactly (exact.hpp).  Keeping the exact code out of
+// the streaming kernel keeps its register count, and so its occupancy, low.  If
+// the list overflows, a third kernel (which otherwise exits at once) re-walks
+// all images and decides every guarded one exactly, and the list is ignored.
+//
+// The batched form (many realisations, section 3.2's 150 maps) runs the same
+// per-wave core in a persistent kernel whose workgroups pull (realisation,
+// tile) items from an atomic work counter until the queue is empty.
+#include "../../include/ufalcon.h"
+#include "exact.hpp"
+#include "internal.hpp"
+#include "ring.hpp"
+
+#include <algorithm>
+#include <vector>
+
+namespace ufx {
+
+constexpr int kBinBlock = 256;
+constexpr int kBinWaves = kBinBlock / 64;
+constexpr int kQueue = 128;  // < 64 pending + up to 64 new entries
+
+// Workspace layout: this header, then guard_cap entries.
+struct GuardList {
+    unsigned int count;     // guarded instances seen (may exceed the capacity)
+    unsigned int overflow;  // nonzero when some guarded instance was not stored
+    unsigned int next;      // work counter of the persistent kernel
+    unsigned int next_rescue;
+    unsigned int pad[60];
+};
+struct GuardEntry {
+    double dx, dy, dz;
+    int32_t item;
+    int32_t pad;
+};
+constexpr size_t kGuardHeader = sizeof(GuardList);
+static_assert(kGuardHeader == 256, "workspace header is 256 bytes");
+
+// Everything the per-wave core needs about one particle set.
+struct BinCore {
+    const void *x, *y, *z;
+    int64_t n;
+    double ox, oy, oz, L;
+    double lo2, hi2;      // guard-widened [e_b0^2, e_b1^2)
+    int32_t R;            // images {-R..R}^3
+    int32_t nb;           // shells in range
+    int32_t steps;        // binary-search steps over nb + 1 edges
+    int32_t item;         // realisation index (batched) or 0
+    uint32_t *counts;     // row of the first shell in range
+};
+
+struct BinParams {
+    BinCore c;
+    int64_t nside, npix;
+    double eps;           // floor-argument margin
+    ufalcon_status *status;
+    GuardList *guard;     // workspace header
+    int64_t guard_cap;    // entries the workspace holds
+    double e[UFALCON_MAX_SHELLS + 1];  // edges of the range, e_b0 .. e_b1
+};
+
+struct LaneStats {
+    unsigned long long inst = 0, guarded = 0, unresolved = 0, invalid = 0;
+};
+
+struct Shared {
+    GuardList *guard;
+    int64_t guard_cap;
+    int64_t nside, npix;
+    double eps;
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Exact decision for one guarded instance.  Returns bit 0: counted, bit 1: unresolved.
+__device__ __noinline__ int bin_instance_exact(uint32_t *counts, int64_t npix, int64_t nside, const double *e, int nb,
+                                               double dx, double dy, double dz) {
+    const int b = exact_shell(dx, dy, dz, e, nb);
+    if (b < 0 || b >= nb) return 0;
+    int unresolved = 0;
+    const int64_t pix = exact_ring_pixel(nside, dx, dy, dz, &unresolved);
+    if (pix < 0 || pix >= npix) return 2;  // never expected; reported as unresolved, not written
+    atomicAdd(counts + (int64_t)b * npix + pix, 1u);
+    return 1 | (unresolved << 1);
+}
+
+// Streaming mode: count clear instances, list guarded ones.
+// Rescue mode: skip clear instances (already counted), decide guarded ones exactly.
+template <bool kRescue>
+__device__ __forceinline__ void bin_instance(const BinCore &c, const Shared &sh, const double *e_s, const double *e2_s,
+                                             double Nd, double dx, double dy, double dz, LaneStats &st) {
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    bool clear;
+    const int j = fast_shell(e2_s, c.nb, c.steps, r2, clear);
+    if (clear) {
+        if (j < 0 || j >= c.nb) return;
+        int64_t pix;
+        // the range test costs two compares and keeps any logic slip from writing out of bounds
+        if (fast_ring_pixel(sh.nside, Nd, sh.eps, dx, dy, dz, pix) && pix >= 0 && pix < sh.npix) {
+            if (!kRescue) {
+                atomicAdd(c.counts + (int64_t)j * sh.npix + pix, 1u);
+                ++st.inst;
+            }
+            return;
+        }
+    }
+    if (kRescue) {
+        const int r = bin_instance_exact(c.counts, sh.npix, sh.nside, e_s, c.nb, dx, dy, dz);
+        st.inst += r & 1;
+        st.unresolved += (r >> 1) & 1;
+    } else {
+        ++st.guarded;
+        const unsigned int slot = atomicAdd(&sh.guard->count, 1u);
+        if ((int64_t)slot < sh.guard_cap) {
+            GuardEntry *ent = reinterpret_cast<GuardEntry *>(reinterpret_cast<char *>(sh.guard) + kGuardHeader) + slot;
+            ent->dx = dx;
+            ent->dy = dy;
+            ent->dz = dz;
+            ent->item = c.item;
+        } else {
+            atomicOr(&sh.guard->overflow, 1u);
+        }
+    }
+}
+
+// Per-wave core: this wave handles particles base, base + stride, ... (64 at a
+// time) below `end`; queued images persist in (Qx, Qy, Qz, count) across calls
+// and are drained by drain_queue().
+template <typename T, bool kRescue>
+__device__ __forceinline__ void bin_wave_range(const BinCore &c, const Shared &sh, const double *e_s,
+                                               const double *e2_s, int64_t base, int64_t end, int64_t stride,
+                                               double *Qx, double *Qy, double *Qz, int &count, LaneStats &st) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const T *X = static_cast<const T *>(c.x);
+    const T *Y = static_cast<const T *>(c.y);
+    const T *Z = static_cast<const T *>(c.z);
+    const double Nd = (double)sh.nside;
+    for (; base < end; base += stride) {
+        const int64_t i = base + lane;
+        bool valid = false;
+        double bx = 0.0, by = 0.0, bz = 0.0;
+        if (i < end) {
+            const double x = (double)X[i], y = (double)Y[i], z = (double)Z[i];
+            if (isfinite(x) && isfinite(y) && isfinite(z)) {
+                valid = true;
+                bx = x - c.ox;
+                by = y - c.oy;
+                bz = z - c.oz;
+            } else if (!kRescue) {
+                ++st.invalid;
+            }
+        }
+        for (int sx = -c.R; sx <= c.R; ++sx) {
+            const double dx = bx + (double)sx * c.L;
+            for (int sy = -c.R; sy <= c.R; ++sy) {
+                const double dy = by + (double)sy * c.L;
+                for (int sz = -c.R; sz <= c.R; ++sz) {
+                    const double dz = bz + (double)sz * c.L;
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    const bool in = valid && r2 >= c.lo2 && r2 < c.hi2;
+                    const unsigned long long m = __ballot(in);
+                    if (m == 0ull) continue;
+                    const int pos = count + __popcll(m & below);
+                    if (in) {
+                        Qx[pos] = dx;
+                        Qy[pos] = dy;
+                        Qz[pos] = dz;
+                    }
+                    count += __popcll(m);
+                    if (count >= 64) {
+                        wave_lds_sync();
+                        const double ax = Qx[lane], ay = Qy[lane], az = Qz[lane];
+                        const int rest = count - 64;
+                        double rx = 0.0, ry = 0.0, rz = 0.0;
+                        if (lane < rest) {
+                            rx = Qx[64 + lane];
+                            ry = Qy[64 + lane];
+                            rz = Qz[64 + lane];
+                        }
+                        wave_lds_sync();
+                        if (lane < rest) {
+                            Qx[lane] = rx;
+                            Qy[lane] = ry;
+                            Qz[lane] = rz;
+                        }
+                        count = rest;
+                        bin_instance<kRescue>(c, sh, e_s, e2_s, Nd, ax, ay, az, st);
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <bool kRescue>
+__device__ __forceinline__ void drain_queue(const BinCore &c, const Shared &sh, const double *e_s, const double *e2_s,
+                                            double *Qx, double *Qy, double *Qz, int &count, LaneStats &st) {
+    const int lane = threadIdx.x & 63;
+    wave_lds_sync();
+    if (lane < count) bin_instance<kRescue>(c, sh, e_s, e2_s, (double)sh.nside, Qx[lane], Qy[lane], Qz[lane], st);
+    wave_lds_sync();
+    count = 0;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ void flush_stats(ufalcon_status *status, LaneStats &st) {
+    const unsigned long long a = wave_sum(st.inst), b = wave_sum(st.guarded), c = wave_sum(st.unresolved),
+                             d = wave_sum(st.invalid);
+    if (status && (threadIdx.x & 63) == 0) {
+        if (a) atomicAdd(&status->n_instances, a);
+        if (b) atomicAdd(&status->n_guarded, b);
+        if (c) atomicAdd(&status->n_unresolved, c);
+        if (d) atomicAdd(&status->n_invalid, d);
+    }
+}
+
+__device__ __forceinline__ Shared shared_of(const BinParams &p) {
+    return Shared{p.guard, p.guard_cap, p.nside, p.npix, p.eps};
+}
+
+template <typename T, bool kRescue>
+__global__ __launch_bounds__(kBinBlock) void bin_shells_kernel(BinParams p) {
+    if (kRescue && p.guard->overflow == 0u) return;  // uniform: nothing to rescue
+    __shared__ double e_s[UFALCON_MAX_SHELLS + 1];
+    __shared__ double e2_s[UFALCON_MAX_SHELLS + 1];
+    __shared__ double qx[kBinWaves][kQueue], qy[kBinWaves][kQueue], qz[kBinWaves][kQueue];
+    for (int j = threadIdx.x; j <= p.c.nb; j += kBinBlock) {
+        e_s[j] = p.e[j];
+        e2_s[j] = p.e[j] * p.e[j];
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    const Shared sh = shared_of(p);
+    LaneStats st;
+    int count = 0;
+    const int64_t base = (int64_t)blockIdx.x * kBinBlock + w * 64;
+    const int64_t stride = (int64_t)gridDim.x * kBinBlock;
+    bin_wave_range<T, kRescue>(p.c, sh, e_s, e2_s, base, p.c.n, stride, qx[w], qy[w], qz[w], count, st);
+    drain_queue<kRescue>(p.c, sh, e_s, e2_s, qx[w], qy[w], qz[w], count, st);
+    flush_stats(p.status, st);
+}
+
+// Exact decisions for the listed guarded instances (skipped after an overflow).
+__global__ __launch_bounds__(256) void bin_guarded_kernel(BinParams p) {
+    __shared__ double e_s[UFALCON_MAX_SHELLS + 1];
+    for (int j = threadIdx.x; j <= p.c.nb; j += 256) e_s[j] = p.e[j];
+    __syncthreads();
+    if (p.guard->overflow != 0u) return;
+    const unsigned int seen = p.guard->count;
+    const int64_t m = (int64_t)seen < p.guard_cap ? (int64_t)seen : p.guard_cap;
+    const GuardEntry *ent = reinterpret_cast<const GuardEntry *>(reinterpret_cast<const char *>(p.guard) + kGuardHeader);
+    LaneStats st;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < m; k += (int64_t)gridDim.x * 256) {
+        const int r = bin_instance_exact(p.c.counts, p.npix, p.nside, e_s, p.c.nb, ent[k].dx, ent[k].dy, ent[k].dz);
+        st.inst += r & 1;
+        st.unresolved += (r >> 1) & 1;
+    }
+    flush_stats(p.status, st);
+}
+
+__global__ void guard_reset_kernel(GuardList *g) {
+    if (threadIdx.x == 0) {
+        g->count = 0u;
+        g->overflow = 0u;
+        g->next = 0u;
+        g->next_rescue = 0u;
+    }
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // 16-byte stores over the aligned bulk, scalar stores for the ends
+    const int64_t head = (int64_t)(((16u - ((uintptr_t)p & 15u)) & 15u) / 4u);
+    const int64_t h = head < n ? head : n;
+    if (i < h) p[i] = v;
+    uint4 *q = reinterpret_cast<uint4 *>(p + h);
+    const int64_t nv = (n - h) / 4;
+    const uint4 vv = {v, v, v, v};
+    for (int64_t k = i; k < nv; k += stride) q[k] = vv;
+    const int64_t tail0 = h + nv * 4;
+    if (i < n - tail0) p[tail0 + i] = v;
+}
+
+// ------------------------------------------------------------------ batched
+struct BatchItemDev {
+    BinCore c;
+    int32_t edge_off;      // first edge of the range in the plan's edge array
+    int32_t pad;
+    int64_t tile_begin;    // prefix sum of tiles over items
+};
+
+struct BatchParams {
+    const BatchItemDev *items;
+    const double *edges;
+    int32_t n_items;
+    int32_t pad;
+    int64_t total_tiles;
+    int64_t tile;          // particles per work item
+    Shared sh;
+    ufalcon_status *status;
+};
+
+__device__ __forceinline__ int find_item(const BatchItemDev *items, int n_items, int64_t t) {
+    int lo = 0, hi = n_items;  // largest k with tile_begin <= t
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (items[mid].tile_begin <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <typename T, bool kRescue>
+__global__ __launch_bounds__(kBinBlock) void bin_batched_kernel(BatchParams p) {
+    if (kRescue && p.sh.guard->overflow == 0u) return;
+    __shared__ double e_s[UFALCON_MAX_SHELLS + 1];
+    __shared__ double e2_s[UFALCON_MAX_SHELLS + 1];
+    __shared__ double qx[kBinWaves][kQueue], qy[kBinWaves][kQueue], qz[kBinWaves][kQueue];
+    __shared__ int64_t work;
+    __shared__ int cur_item;
+    const int w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) cur_item = -1;
+    LaneStats st;
+    int count = 0;
+    unsigned int *ctr = kRescue ? &p.sh.guard->next_rescue : &p.sh.guard->next;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) work = (int64_t)atomicAdd(ctr, 1u);
+        __syncthreads();
+        const int64_t t = work;
+        if (t >= p.total_tiles) break;  // uniform over the block: every wave exits here
+        const int k = find_item(p.items, p.n_items, t);
+        const BinCore c = p.items[k].c;
+        if (k != cur_item) {
+            __syncthreads();
+            const double *e = p.edges + p.items[k].edge_off;
+            for (int j = threadIdx.x; j <= c.nb; j += kBinBlock) {
+                e_s[j] = e[j];
+                e2_s[j] = e[j] * e[j];
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) cur_item = k;
+        }
+        const int64_t first = (t - p.items[k].tile_begin) * p.tile;
+        const int64_t last = first + p.tile < c.n ? first + p.tile : c.n;
+        bin_wave_range<T, kRescue>(c, p.sh, e_s, e2_s, first + w * 64, last, kBinBlock, qx[w], qy[w], qz[w], count, st);
+        drain_queue<kRescue>(c, p.sh, e_s, e2_s, qx[w], qy[w], qz[w], count, st);
+    }
+    flush_stats(p.status, st);
+}
+
+__global__ __launch_bounds__(256) void bin_batched_guarded_kernel(BatchParams p) {
+    if (p.sh.guard->overflow != 0u) return;
+    const unsigned int seen = p.sh.guard->count;
+    const int64_t m = (int64_t)seen < p.sh.guard_cap ? (int64_t)seen : p.sh.guard_cap;
+    const GuardEntry *ent =
+        reinterpret_cast<const GuardEntry *>(reinterpret_cast<const char *>(p.sh.guard) + kGuardHeader);
+    LaneStats st;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < m; k += (int64_t)gridDim.x * 256) {
+        const GuardEntry g = ent[k];
+        const BatchItemDev &it = p.items[g.item];
+        const int r = bin_instance_exact(it.c.counts, p.sh.npix, p.sh.nside, p.edges + it.edge_off, it.c.nb, g.dx,
+                                         g.dy, g.dz);
+        st.inst += r & 1;
+        st.unresolved += (r >> 1) & 1;
+    }
+    flush_stats(p.status, st);
+}
+
+double cell_instance_bound(int64_t n, double L, int32_t R, const double *e, int32_t b0, int32_t b1, int64_t nside) {
+    const double psi = pixel_diameter_bound(nside);
+    double per = 1.0;
+    const double side = 2.0 * R + 1.0;
+    for (int32_t b = b0; b < b1; ++b) {
+        const double D = (e[b + 1] - e[b]) + e[b + 1] * psi;
+        double k = (R == 0) ? 1.0 : std::floor(D / L) + 1.0;
+        if (k > side) k = side;
+        const double cube = k * k * k;
+        if (cube > per) per = cube;
+    }
+    return (double)n * per;
+}
+
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+// Validate one particle set and fill its core description.
+int fill_core(BinCore &c, double *e_out, const void *x, const void *y, const void *z, int64_t n,
+              const double *observer, double box_L, int32_t n_rep, const double *chi_edges, int32_t n_shells,
+              int32_t shell_begin, int32_t shell_end, int64_t nside, uint32_t *counts) {
+    if (n < 0 || !observer || !counts) return UFALCON_EINVAL;
+    if (n > 0 && (!x || !y || !z)) return UFALCON_EINVAL;
+    int rc = check_edges(chi_edges, n_shells);
+    if (rc) return rc;
+    if ((rc = check_nside(nside))) return rc;
+    if (shell_begin < 0 || shell_begin > shell_end || shell_end > n_shells) return UFALCON_EINVAL;
+    if (n_rep < 0 || n_rep > 64) return UFALCON_EINVAL;
+    if (!std::isfinite(box_L) || (n_rep > 0 && !(box_L > 0.0))) return UFALCON_EINVAL;
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(observer[k])) return UFALCON_EINVAL;
+    if (shell_end > shell_begin &&
+        cell_instance_bound(n, box_L, n_rep, chi_edges, shell_begin, shell_end, nside) > 4294967295.0)
+        return UFALCON_EOVERFLOW;
+    c.x = x;
+    c.y = y;
+    c.z = z;
+    c.n = n;
+    c.ox = observer[0];
+    c.oy = observer[1];
+    c.oz = observer[2];
+    c.L = box_L;
+    c.R = n_rep;
+    c.nb = shell_end - shell_begin;
+    int steps = 0;
+    while ((2 << steps) <= c.nb + 1) ++steps;
+    c.steps = steps;
+    c.item = 0;
+    c.counts = counts + (int64_t)shell_begin * npix_of(nside);
+    for (int j = 0; j <= c.nb; ++j) e_out[j] = chi_edges[shell_begin + j];
+    const double elo = e_out[0], ehi = e_out[c.nb];
+    c.lo2 = elo * elo * (1.0 - 0x1p-36);
+    c.hi2 = ehi * ehi * (1.0 + 0x1p-36);
+    return UFALCON_OK;
+}
+
+int check_workspace(void *workspace, size_t bytes) {
+    if (!workspace || bytes < kGuardHeader || ((uintptr_t)workspace & 255u)) return UFALCON_EWORKSPACE;
+    return UFALCON_OK;
+}
+
+int64_t guard_capacity(size_t bytes) {
+    int64_t cap = (int64_t)((bytes - kGuardHeader) / sizeof(GuardEntry));
+    return cap > 0x7fffffffLL ? 0x7fffffffLL : cap;
+}
+
+template <typename T>
+int launch_bin_t(const BinParams &p, hipStream_t s) {
+    const unsigned grid = blocks_for(p.c.n, kBinBlock, (unsigned)device_cus() * 16u);
+    hipLaunchKernelGGL(guard_reset_kernel, dim3(1), dim3(64), 0, s, p.guard);
+    hipLaunchKernelGGL((bin_shells_kernel<T, false>), dim3(grid), dim3(kBinBlock), 0, s, p);
+    hipLaunchKernelGGL(bin_guarded_kernel, dim3(64), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((bin_shells_kernel<T, true>), dim3(grid), dim3(kBinBlock), 0, s, p);
+    UFX_HIP_CHECK(hipGetLastError());
+    return UFALCON_OK;
+}
+
+}  // namespace ufx
+
+using namespace ufx;
+
+extern "C" const char *ufalcon_strerror(int code) {
+    switch (code) {
+        case UFALCON_OK: return "ok";
+        case UFALCON_EINVAL: return "invalid argument";
+        case UFALCON_EUNSORTED_EDGES: return "shell edges must be finite, >= 0 and strictly ascending";
+        case UFALCON_ENSIDE: return "nside outside [1, 8192]";
+        case UFALCON_EOVERFLOW: return "a uint32 count cell could overflow";
+        case UFALCON_EWORKSPACE: return "workspace missing, misaligned or too small";
+        case UFALCON_EHIP: return "HIP runtime error";
+        case UFALCON_ETOO_MANY_SHELLS: return "too many shells or source bins";
+        default: return "unknown error";
+    }
+}
+
+extern "C" int ufalcon_version(void) { return 100; }
+
+extern "C" size_t ufalcon_bin_shells_workspace_size(int64_t max_listed) {
+    if (max_listed < 0) max_listed = 0;
+    return kGuardHeader + (size_t)max_listed * sizeof(GuardEntry);
+}
+
+extern "C" int ufalcon_fill_u32(uint32_t *p, int64_t n, uint32_t value, ufalcon_stream_t stream) {
+    if (n < 0 || (n > 0 && !p)) return UFALCON_EINVAL;
+    if (n == 0) return UFALCON_OK;
+    const unsigned blocks = blocks_for(n / 4 + 1, 256 * 4, 8192);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks), dim3(256), 0, as_stream(stream), p, n, value);
+    UFX_HIP_CHECK(hipGetLastError());
+    return UFALCON_OK;
+}
+
+extern "C" int ufalcon_bin_shells(const void *x, const void *y, const void *z, int64_t n, int dtype,
+                                  const double *observer, double box_L, int32_t n_rep, const double *chi_edges,
+                                  int32_t n_shells, int32_t shell_begin, int32_t shell_end, int64_t nside,
+                                  uint32_t *counts, ufalcon_status *status, void *workspace, size_t workspace_bytes,
+                                  ufalcon_stream_t stream) {
+    if (dtype != UFALCON_F32 && dtype != UFALCON_F64) return UFALCON_EINVAL;
+    BinParams p;
+    int rc = fill_core(p.c, p.e, x, y, z, n, observer, box_L, n_rep, chi_edges, n_shells, shell_begin, shell_end,
+                       nside, counts);
+    if (rc) return rc;
+    if ((rc = check_workspace(workspace, workspace_bytes))) return rc;
+    p.nside = nside;
+    p.npix = npix_of(nside);
+    p.eps = floor_margin((double)nside);
+    p.status = status;
+    p.guard = static_cast<GuardList *>(workspace);
+    p.guard_cap = guard_capacity(workspace_bytes);
+    if (p.c.n == 0 || p.c.nb == 0) return UFALCON_OK;
+    hipStream_t s = as_stream(stream);
+    return dtype == UFALCON_F32 ? launch_bin_t<float>(p, s) : launch_bin_t<double>(p, s);
+}
+
+// ------------------------------------------------------------------ batch plan
+namespace ufx {
+struct BornItemDev {
+    const uint32_t *counts;  // [B][npix]
+    const double *W;         // [T][B]
+    const double *inv_nbar;  // [B]
+    void *kappa;             // [T][npix]
+    int32_t B;
+    int32_t pad;
+};
+int launch_born_batched(const BornItemDev *items, int32_t n_items, int64_t npix, int32_t T, int out_dtype,
+                        hipStream_t s);
+}  // namespace ufx
+
+struct ufalcon_batch_plan {
+    int dtype, out_dtype;
+    int32_t n_items, T;
+    int64_t nside, npix, tile, total_tiles;
+    int32_t wgs;
+    std::vector<BatchItemDev> host_items;
+    std::vector<uint32_t *> count_ptrs;
+    std::vector<int64_t> count_words;
+    BatchItemDev *d_items = nullptr;
+    double *d_edges = nullptr;
+    BornItemDev *d_born = nullptr;
+    void *d_work = nullptr;  // guard list + work counters
+    size_t work_bytes = 0;
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    ufalcon_status *graph_status = nullptr;
+};
+
+static void free_plan(ufalcon_batch_plan *p) {
+    if (!p) return;
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    if (p->d_items) (void)hipFree(p->d_items);
+    if (p->d_edges) (void)hipFree(p->d_edges);
+    if (p->d_born) (void)hipFree(p->d_born);
+    if (p->d_work) (void)hipFree(p->d_work);
+    delete p;
+}
+
+extern "C" int ufalcon_batch_plan_create(const ufalcon_batch_item *items, int32_t n_items, int dtype, int64_t nside,
+                                         int32_t T, int out_dtype, int64_t tile, int32_t persistent_wgs,
+                                         ufalcon_batch_plan **plan) {
+    if (!items || n_items < 1 || !plan) return UFALCON_EINVAL;
+    if (dtype != UFALCON_F32 && dtype != UFALCON_F64) return UFALCON_EINVAL;
+    if (out_dtype != UFALCON_F32 && out_dtype != UFALCON_F64) return UFALCON_EINVAL;
+    if (T < 0 || T > UFALCON_MAX_BINS) return UFALCON_EINVAL;
+    if (tile < 0 || persistent_wgs < 0) return UFALCON_EINVAL;
+    int rc = check_nside(nside);
+    if (rc) return rc;
+    *plan = nullptr;
+    ufalcon_batch_plan *p = new ufalcon_batch_plan();
+    p->dtype = dtype;
+    p->out_dtype = out_dtype;
+    p->n_items = n_items;
+    p->T = T;
+    p->nside = nside;
+    p->npix = npix_of(nside);
+    p->tile = tile > 0 ? tile : (int64_t)1 << 18;
+    p->tile = (p->tile + 63) / 64 * 64;
+    p->wgs = persistent_wgs > 0 ? persistent_wgs : device_cus() * 8;
+    std::vector<double> edges;
+    std::vector<BornItemDev> born(n_items);
+    int64_t tiles = 0;
+    for (int32_t k = 0; k < n_items; ++k) {
+        const ufalcon_batch_item &it = items[k];
+        BatchItemDev d{};
+        double e[UFALCON_MAX_SHELLS + 1];
+        rc = fill_core(d.c, e, it.x, it.y, it.z, it.n, it.observer, it.box_L, it.n_rep, it.chi_edges, it.n_shells,
+                       it.shell_begin, it.shell_end, nside, it.counts);
+        if (rc) {
+            free_plan(p);
+            return rc;
+        }
+        d.c.item = k;
+        d.edge_off = (int32_t)edges.size();
+        for (int j = 0; j <= d.c.nb; ++j) edges.push_back(e[j]);
+        d.tile_begin = tiles;
+        const int64_t nt = d.c.nb > 0 ? (it.n + p->tile - 1) / p->tile : 0;
+        tiles += nt;
+        p->host_items.push_back(d);
+        p->count_ptrs.push_back(it.counts);
+        p->count_words.push_back((int64_t)it.n_shells * p->npix);
+        born[k].counts = it.counts;
+        born[k].W = it.W;
+        born[k].inv_nbar = it.inv_nbar;
+        born[k].kappa = it.kappa;
+        born[k].B = it.n_shells;
+        if (T > 0 && (!it.W || !it.inv_nbar || !it.kappa)) {
+            free_plan(p);
+            return UFALCON_EINVAL;
+        }
+    }
+    p->total_tiles = tiles;
+    p->work_bytes = kGuardHeader + (size_t)65536 * sizeof(GuardEntry);
+    if (hipMalloc(&p->d_items, sizeof(BatchItemDev) * n_items) != hipSuccess ||
+        hipMalloc(&p->d_edges, sizeof(double) * edges.size()) != hipSuccess ||
+        hipMalloc(&p->d_born, sizeof(BornItemDev) * n_items) != hipSuccess ||
+        hipMalloc(&p->d_work, p->work_bytes) != hipSuccess ||
+        hipMemcpy(p->d_items, p->host_items.data(), sizeof(BatchItemDev) * n_items, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_edges, edges.data(), sizeof(double) * edges.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_born, born.data(), sizeof(BornItemDev) * n_items, hipMemcpyHostToDevice) != hipSuccess) {
+        free_plan(p);
+        return UFALCON_EHIP;
+    }
+    *plan = p;
+    return UFALCON_OK;
+}
+
+extern "C" int ufalcon_batch_plan_destroy(ufalcon_batch_plan *plan) {
+    if (!plan) return UFALCON_EINVAL;
+    free_plan(plan);
+    return UFALCON_OK;
+}
+
+extern "C" int ufalcon_batch_clear(ufalcon_batch_plan *plan, ufalcon_stream_t stream) {
+    if (!plan) return UFALCON_EINVAL;
+    for (int32_t k = 0; k < plan->n_items; ++k) {
+        const int rc = ufalcon_fill_u32(plan->count_ptrs[k], plan->count_words[k], 0u, stream);
+        if (rc) return rc;
+    }
+    return UFALCON_OK;
+}
+
+static BatchParams batch_params(ufalcon_batch_plan *plan, ufalcon_status *status) {
+    BatchParams bp{};
+    bp.items = plan->d_items;
+    bp.edges = plan->d_edges;
+    bp.n_items = plan->n_items;
+    bp.total_tiles = plan->total_tiles;
+    bp.tile = plan->tile;
+    bp.sh.guard = static_cast<GuardList *>(plan->d_work);
+    bp.sh.guard_cap = guard_capacity(plan->work_bytes);
+    bp.sh.nside = plan->nside;
+    bp.sh.npix = plan->npix;
+    bp.sh.eps = floor_margin((double)plan->nside);
+    bp.status = status;
+    return bp;
+}
+
+extern "C" int ufalcon_bin_shells_batched(ufalcon_batch_plan *plan, ufalcon_status *status, ufalcon_stream_t stream) {
+    if (!plan) return UFALCON_EINVAL;
+    if (plan->total_tiles == 0) return UFALCON_OK;
+    const BatchParams bp = batch_params(plan, status);
+    hipStream_t s = as_stream(stream);
+    const unsigned wgs = (unsigned)std::min<int64_t>(plan->wgs, plan->total_tiles);
+    hipLaunchKernelGGL(guard_reset_kernel, dim3(1), dim3(64), 0, s, bp.sh.guard);
+    if (plan->dtype == UFALCON_F32) {
+        hipLaunchKernelGGL((bin_batched_kernel<float, false>), dim3(wgs), dim3(kBinBlock), 0, s, bp);
+        hipLaunchKernelGGL(bin_batched_guarded_kernel, dim3(64), dim3(256), 0, s, bp);
+        hipLaunchKernelGGL((bin_batched_kernel<float, true>), dim3(wgs), dim3(kBinBlock), 0, s, bp);
+    } else {
+        hipLaunchKernelGGL((bin_batched_kernel<double, false>), dim3(wgs), dim3(kBinBlock), 0, s, bp);
+        hipLaunchKernelGGL(bin_batched_guarded_kernel, dim3(64), dim3(256), 0, s, bp);
+        hipLaunchKernelGGL((bin_batched_kernel<double, true>), dim3(wgs), dim3(kBinBlock), 0, s, bp);
+    }
+    UFX_HIP_CHECK(hipGetLastError());
+    return UFALCON_OK;
+}
+
+extern "C" int ufalcon_born_kappa_batched(ufalcon_batch_plan *plan, ufalcon_stream_t stream) {
+    if (!plan || plan->T < 1) return UFALCON_EINVAL;
+    return launch_born_batched(plan->d_born, plan->n_items, plan->npix, plan->T, plan->out_dtype, as_stream(stream));
+}
+
+extern "C" int ufalcon_batch_run_graph(ufalcon_batch_plan *plan, ufalcon_status *status, ufalcon_stream_t stream) {
+    if (!plan) return UFALCON_EINVAL;
+    if (!plan->graph_exec || plan->graph_status != status) {
+        if (plan->graph_exec) {
+            UFX_HIP_CHECK(hipGraphExecDestroy(plan->graph_exec));
+            plan->graph_exec = nullptr;
+        }
+        if (!plan->capture_stream) UFX_HIP_CHECK(hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking));
+        hipStream_t cs = plan->capture_stream;
+        UFX_HIP_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        int rc = ufalcon_batch_clear(plan, cs);
+        if (!rc) rc = ufalcon_bin_shells_batched(plan, status, cs);
+        if (!rc && plan->T > 0) rc = ufalcon_born_kappa_batched(plan, cs);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(cs, &g);
+        if (rc || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc ? rc : UFALCON_EHIP;
+        }
+        const hipError_t ie = hipGraphInstantiate(&plan->graph_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return UFALCON_EHIP;
+        plan->graph_status = status;
+    }
+    UFX_HIP_CHECK(hipGraphLaunch(plan->graph_exec, as_stream(stream)));
+    return UFALCON_OK;
+}

@@ -1,0 +1,58 @@
+// Host-side helpers shared by the ufalcon entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "../../include/ufalcon.h"
+
+namespace ufx {
+
+#define UFX_HIP_CHECK(expr)                            \
+    do {                                               \
+        hipError_t _e = (expr);                        \
+        if (_e != hipSuccess) return UFALCON_EHIP;     \
+    } while (0)
+
+inline hipStream_t as_stream(ufalcon_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline int check_edges(const double *e, int32_t n_shells) {
+    if (!e) return UFALCON_EINVAL;
+    if (n_shells < 1) return UFALCON_EINVAL;
+    if (n_shells > UFALCON_MAX_SHELLS) return UFALCON_ETOO_MANY_SHELLS;
+    for (int32_t j = 0; j <= n_shells; ++j) {
+        if (!std::isfinite(e[j]) || e[j] < 0.0) return UFALCON_EUNSORTED_EDGES;
+        if (j > 0 && !(e[j] > e[j - 1])) return UFALCON_EUNSORTED_EDGES;
+    }
+    return UFALCON_OK;
+}
+
+inline int check_nside(int64_t nside) {
+    return (nside >= 1 && nside <= UFALCON_MAX_NSIDE) ? UFALCON_OK : UFALCON_ENSIDE;
+}
+
+inline int64_t npix_of(int64_t nside) { return 12 * nside * nside; }
+
+// Grid for a flat kernel over `work` items with `per_block` items per block.
+inline unsigned blocks_for(int64_t work, int64_t per_block, unsigned cap = 1u << 20) {
+    int64_t b = (work + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    return (unsigned)(b > (int64_t)cap ? cap : b);
+}
+
+// Upper bound on the number of instances a single (shell, pixel) cell can receive
+// from n particles with images {-R..R}^3 of a box of side L: the cell of shell b
+// has diameter <= (e_{b+1} - e_b) + e_{b+1} * psi(nside) with psi an upper bound
+// on a pixel's angular diameter, and a set of diameter D holds at most
+// (floor(D/L) + 1)^3 lattice translates of one point.
+double cell_instance_bound(int64_t n, double L, int32_t R, const double *e, int32_t b0, int32_t b1, int64_t nside);
+
+// Pixel angular-diameter bound used above (radians).
+inline double pixel_diameter_bound(int64_t nside) {
+    double psi = 4.0 / (double)nside;
+    return psi > M_PI ? M_PI : psi;
+}
+
+}  // namespace ufx

@@ -1,0 +1,89 @@
+"""The C-ABI library loads, exports every entry point that include/ufalcon.h declares,
+and rejects invalid arguments on the host before anything is launched (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1801_05745_amd as uf
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "ufalcon.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ufalcon_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    lib = uf.load()
+    names = declared_functions()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(uf.exported_symbols()) == names
+
+
+def test_strerror_and_version():
+    lib = uf.load()
+    assert lib.ufalcon_version() >= 100
+    for code in range(0, -8, -1):
+        assert lib.ufalcon_strerror(code)
+
+
+D3 = ctypes.c_double * 3
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+
+
+def _bin(n=4, dtype=0, obs=(0.0, 0.0, 0.0), L=1.0, R=0, edges=(0.0, 1.0), b0=0, b1=None, nside=4,
+         counts=FAKE, ws=ctypes.c_void_p(0x1000), ws_bytes=256):
+    lib = uf.load()
+    e = (ctypes.c_double * len(edges))(*edges)
+    B = len(edges) - 1
+    return lib.ufalcon_bin_shells(FAKE, FAKE, FAKE, n, dtype, D3(*obs), L, R, e, B, b0, B if b1 is None else b1,
+                                  nside, counts, None, ws, ws_bytes, None)
+
+
+def test_bin_shells_validation():
+    assert _bin(edges=(1.0, 1.0)) == -2
+    assert _bin(edges=(0.0, float("nan"))) == -2
+    assert _bin(edges=(-1.0, 1.0)) == -2
+    assert _bin(nside=0) == -3
+    assert _bin(nside=9000) == -3
+    assert _bin(dtype=7) == -1
+    assert _bin(n=-1) == -1
+    assert _bin(b0=1, b1=0) == -1
+    assert _bin(R=1, L=-1.0) == -1
+    assert _bin(R=65, L=1.0) == -1
+    assert _bin(obs=(float("inf"), 0.0, 0.0)) == -1
+    assert _bin(counts=None) == -1
+    assert _bin(ws=None) == -5
+    assert _bin(ws_bytes=100) == -5
+    assert _bin(ws=ctypes.c_void_p(0x1010)) == -5        # not 256-byte aligned
+    assert _bin(edges=tuple(float(i) for i in range(300))) == -7
+    # 2^31 particles, 7^3 images that one Nside-1 cell can hold -> a uint32 cell could overflow
+    assert _bin(n=1 << 31, R=3, L=1.0, edges=(0.0, 10.0), nside=1) == -4
+
+
+def test_born_and_weights_validation():
+    lib = uf.load()
+    assert lib.ufalcon_born_kappa(None, 3, 4, FAKE, FAKE, 1, FAKE, 0, None) == -1
+    assert lib.ufalcon_born_kappa(FAKE, 3, 4, FAKE, FAKE, 9, FAKE, 0, None) == -7
+    assert lib.ufalcon_born_kappa(FAKE, 3, 0, FAKE, FAKE, 1, FAKE, 0, None) == -3
+    assert lib.ufalcon_born_kappa(FAKE, 3, 4, FAKE, FAKE, 1, FAKE, 5, None) == -1
+    assert lib.ufalcon_born_kappa_adjoint(FAKE, 3, 4, FAKE, FAKE, 0, 1, FAKE, None, 0, None) == -5
+    assert lib.ufalcon_born_kappa_adjoint(FAKE, 3, 4, FAKE, None, 0, 1, FAKE, FAKE, 1 << 20, None) == -1
+    need = lib.ufalcon_born_kappa_adjoint_workspace_size(3, 4, 1)
+    assert need > 0
+    assert lib.ufalcon_born_kappa_adjoint(FAKE, 3, 4, FAKE, FAKE, 0, 1, FAKE, ctypes.c_void_p(0x1000), need - 8,
+                                          None) == -5
+    src = (uf.Source * 1)(uf.Source(uf.SOURCE_SMAIL, 0.0, 2.0, -1.0, 0.3, 0.5))
+    e = (ctypes.c_double * 3)(0.0, 1.0, 2.0)
+    assert lib.ufalcon_lensing_weights(0.3, src, 1, e, 2, FAKE, None, None) == -1
+    src[0] = uf.Source(uf.SOURCE_DELTA, 0.5, 0, 0, 0, 0)
+    assert lib.ufalcon_lensing_weights(1.5, src, 1, e, 2, FAKE, None, None) == -1
+    assert lib.ufalcon_inv_nbar(10, 1.0, e, 2, 0, 2, 4, uf.NBAR_LOWER_EDGE, FAKE, None) == -1  # chi_0 = 0
+    assert lib.ufalcon_inv_nbar(0, 1.0, e, 2, 0, 2, 4, 0, FAKE, None) == -1

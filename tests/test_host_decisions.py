@@ -1,0 +1,142 @@
+"""The library's device decision code (exact.hpp, ring.hpp), compiled for the host,
+against the oracle's exact resolver.  Runs without a GPU.
+
+The FP64 fast path must either agree with the exact pixel or defer; the
+library's exact path (expansions + double-double) must agree everywhere,
+including exact ties on axis/diagonal directions and |z| = 2/3.
+"""
+
+import ctypes
+import math
+import os
+import random
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import binning as obin
+from oracle import healpix as hp
+
+sys.path.insert(0, os.path.join(os.path.dirname(__file__), "host"))
+import build_shim  # noqa: E402
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build_shim.build())
+        _lib.shim_exact_ring_pixel.restype = ctypes.c_int64
+        _lib.shim_exact_ring_pixel.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                               ctypes.POINTER(ctypes.c_int)]
+        _lib.shim_exact_shell.restype = ctypes.c_int
+        _lib.shim_exact_shell.argtypes = [ctypes.c_double] * 3 + [ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+        _lib.shim_fast_ring_pixel.restype = ctypes.c_int
+        _lib.shim_fast_ring_pixel.argtypes = [ctypes.c_int64] + [ctypes.c_double] * 3 + [ctypes.POINTER(ctypes.c_int64)]
+        _lib.shim_fast_shell.restype = ctypes.c_int
+        _lib.shim_fast_shell.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_double,
+                                         ctypes.POINTER(ctypes.c_int)]
+        _lib.shim_tt.restype = ctypes.c_double
+        _lib.shim_tt.argtypes = [ctypes.c_double, ctypes.c_double]
+    return _lib
+
+
+def exact_pix(nside, v):
+    u = ctypes.c_int(0)
+    p = lib().shim_exact_ring_pixel(nside, v[0], v[1], v[2], ctypes.byref(u))
+    return p, u.value
+
+
+def fast_pix(nside, v):
+    out = ctypes.c_int64(-1)
+    return out.value if lib().shim_fast_ring_pixel(nside, v[0], v[1], v[2], ctypes.byref(out)) else None
+
+
+def _unit(z, phi):
+    st = math.sqrt(max(0.0, 1.0 - z * z))
+    return st * math.cos(phi), st * math.sin(phi), z
+
+
+def adversarial(seed=0, n_random=150):
+    vs = []
+    for a in range(-3, 4):
+        for b in range(-3, 4):
+            for c in range(-3, 4):
+                if (a, b, c) != (0, 0, 0):
+                    vs.append((float(a), float(b), float(c)))
+    # exact ties: (2,2,1) family, z = 2/3 with rational |d|, diagonal cap points
+    vs += [(2.0, 2.0, 1.0), (-2.0, -2.0, 1.0), (2.0, 1.0, 2.0), (1.0, 2.0, -2.0), (4.0, 4.0, 7.0), (3.0, 0.0, 4.0),
+           (0.0, 3.0, -4.0), (12.0, 0.0, 5.0), (1.0, 1.0, 1.0e-300 * 0 + 7.0)]
+    rng = random.Random(seed)
+    for _ in range(n_random):
+        z = rng.choice([2.0 / 3.0, -2.0 / 3.0, 1.0 / 3.0, 0.0, 0.5, 0.9, 0.99])
+        phi = rng.choice([0.0, math.pi / 4, math.pi / 2, math.pi, 3 * math.pi / 2, math.pi / 16, 1.0])
+        x, y, zz = _unit(z, phi)
+        for k in range(-2, 3):
+            vs.append((x, y, zz + k * 2.2e-16))
+            vs.append((x * (1 + k * 1.1e-16), y, zz))
+    for _ in range(n_random):
+        vs.append((rng.gauss(0, 1), rng.gauss(0, 1), rng.gauss(0, 1)))
+    return vs
+
+
+@pytest.mark.parametrize("nside", [1, 2, 4, 5, 16, 64, 1024])
+def test_library_exact_pixel_matches_oracle(nside):
+    for v in adversarial(nside, n_random=60 if nside < 64 else 30):
+        p, unres = exact_pix(nside, v)
+        assert unres == 0
+        assert p == hp.ang2pix_ring(nside, *v), (nside, v)
+
+
+@pytest.mark.parametrize("nside", [1, 4, 64, 1024, 8192])
+def test_library_fast_pixel_agrees_or_defers(nside):
+    deferred = 0
+    for v in adversarial(nside + 1, n_random=100):
+        f = fast_pix(nside, v)
+        if f is None:
+            deferred += 1
+            continue
+        assert f == hp.ang2pix_ring(nside, *v), (nside, v)
+    assert deferred > 0
+
+
+def test_round_trip_through_library_paths():
+    for nside in (1, 2, 3, 8):
+        for p in range(hp.npix(nside)):
+            v = hp.centre_vector(nside, p)
+            assert exact_pix(nside, v)[0] == p
+            f = fast_pix(nside, v)
+            assert f is None or f == p
+
+
+def test_library_tt_double_double():
+    import mpmath
+    rng = random.Random(3)
+    for _ in range(200):
+        dx, dy = rng.gauss(0, 1), rng.gauss(0, 1)
+        with mpmath.workprec(200):
+            phi = mpmath.atan2(dy, dx)
+            if phi < 0:
+                phi += 2 * mpmath.pi
+            want = 2 * phi / mpmath.pi
+        assert abs(lib().shim_tt(dx, dy) - float(want)) <= 4e-16 * max(1.0, float(want))
+
+
+def test_library_shells_exact_and_fast():
+    edges = [0.0, 1.0, math.sqrt(2.0), 2.0, 3.0, 3.5]
+    e = (ctypes.c_double * len(edges))(*edges)
+    e2 = (ctypes.c_double * len(edges))(*[v * v for v in edges])
+    nb = len(edges) - 1
+    rng = random.Random(1)
+    vecs = [(float(a), float(b), float(c)) for a in range(-3, 4) for b in range(-3, 4) for c in range(-3, 4)]
+    vecs += [(rng.uniform(-4, 4), rng.uniform(-4, 4), rng.uniform(-4, 4)) for _ in range(500)]
+    for v in vecs:
+        want = obin.exact_shell(v, edges, 0, nb)
+        got = lib().shim_exact_shell(v[0], v[1], v[2], e, nb)
+        assert (got if got >= 0 else None) == want, v
+        clear = ctypes.c_int(0)
+        j = lib().shim_fast_shell(e2, nb, v[0] * v[0] + v[1] * v[1] + v[2] * v[2], ctypes.byref(clear))
+        if clear.value:
+            assert (j if 0 <= j < nb else None) == want, v
