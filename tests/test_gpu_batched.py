@@ -24,7 +24,7 @@ def _realisations(sizes, shells, L=200.0, nside=16, seed0=0):
         edges = chi_edges_from_z(0.02, 0.09, B)
         R = obin.default_n_rep(edges, L)
         W = uf.lensing_weights(OMEGA_M, [uf.SourceSpec("delta", z_s=0.1)], edges, device=DEV)
-        inb = uf.inv_nbar(n, L, edges, nside, device=DEV)
+        inb = uf.inv_nbar(max(n, 1), L, edges, nside, device=DEV)
         items.append(dict(x=x.to(DEV), y=y.to(DEV), z=z.to(DEV), xh=x, yh=y, zh=z, chi_edges=edges, box_L=L,
                           n_rep=R, counts=uf.new_counts(B, nside, DEV), W=W, inv_nbar=inb,
                           kappa=torch.empty((1, 12 * nside * nside), dtype=torch.float32, device=DEV)))
@@ -52,7 +52,7 @@ def test_batched_matches_oracle_and_plain(ufalcon):
         kp = uf.born_kappa(it["counts"], it["W"], it["inv_nbar"])
         assert torch.equal(kp, it["kappa"])
         Wr = ocos.lensing_weights(it["chi_edges"], OMEGA_M, ocos.DeltaSource(0.1))
-        kr = ocos.kappa(ref, Wr[None, :], ocos.nbar(it["x"].numel() or 1, it["box_L"], it["chi_edges"], nside))
+        kr = ocos.kappa(ref, Wr[None, :], ocos.nbar(max(it["x"].numel(), 1), it["box_L"], it["chi_edges"], nside))
         if it["x"].numel():
             rms = np.sqrt((kr ** 2).mean())
             assert np.abs(it["kappa"].cpu().numpy() - kr).max() <= 1e-5 * rms
