@@ -1,0 +1,261 @@
+"""Throughput of the shell-binning + Born-convergence hot path on one MI355X.
+
+Workload (one step = the whole path over one catalogue resident in HBM):
+  512^3 = 2^27 FP32 particles from a seeded lognormal field (sigma_ln = 1 on a
+  256^3 grid, multinomial placement) in a 1 Gpc/h box, replicated to reach z = 0.5;
+  30 shells over z = 0.1 .. 0.5 (flat LCDM, Omega_m = 0.3); HEALPix Nside 1024;
+  Smail n(z) (alpha 2, beta 1.5, z0 0.3).
+  step = clear counts -> bin shells -> lensing weights (+ derivatives) -> 1/nbar
+         -> Born kappa (FP32 out) -> dL/dkappa for L = sum kappa^2 -> adjoint
+         -> weights VJP (dL/dOmega_m, dL/dz0).
+
+Prints one JSON line.  value = input particles binned per second (whole step).
+The roofline object describes the binning kernel (the dominant one), timed with
+HIP events on the stream it runs on; cpu_baseline times the oracle on one host
+core on a bounded sample of the same catalogue.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particles/s binned to HEALPix shells; kappa maps/s batched vs plain, Δ≤1e-5·RMS"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--order", choices=["shuffled", "cell"], default="shuffled")
+    ap.add_argument("--particles", type=int, default=1 << 27)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 21)
+    ap.add_argument("--batched", action="store_true", help="also time the batched form against plain calls")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="time a plain device copy of known size (for PMC byte-counter scaling)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
+              f"of this path is described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1801_05745_amd as uf
+    import synth
+
+    uf.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    if args.copy_calibration:
+        n = 1 << 28
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}))
+        return
+
+    L, nside, om = 1000.0, 1024, 0.3
+    n = int(args.particles)
+    t0 = time.time()
+    x, y, z = synth.lognormal_box(n, L, seed=0, ngrid=256, dtype=torch.float32, device=dev, order=args.order)
+    zg = torch.linspace(0.1, 0.5, 31, dtype=torch.float64, device=dev)
+    edges = uf.comoving_distance(zg, om).cpu().tolist()
+    B = len(edges) - 1
+    R = 0
+    for oj in (L / 2,) * 3:
+        R = max(R, -math.floor((oj - edges[-1]) / L), math.floor((oj + edges[-1]) / L))
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+
+    src = uf.SourceSpec("smail", alpha=2.0, beta=1.5, z0=0.3, z_max=0.5)
+    counts = torch.empty((B, uf.npix(nside)), dtype=torch.uint32, device=dev)
+    status = uf.new_status(dev)
+    ws = uf.bin_shells_workspace(device=dev)
+    stream = torch.cuda.current_stream(dev)
+    ev_bin0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev_bin1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev_born0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev_born1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    outs = {}
+
+    def step(k=None):
+        uf.fill_u32(counts, 0)
+        if k is not None:
+            ev_bin0[k].record(stream)
+        uf.bin_shells(x, y, z, edges, nside, box_L=L, n_rep=R, counts=counts, status=status, workspace=ws)
+        if k is not None:
+            ev_bin1[k].record(stream)
+        W, dW = uf.lensing_weights(om, [src], edges, with_derivatives=True, device=dev)
+        inb = uf.inv_nbar(n, L, edges, nside, device=dev)
+        if k is not None:
+            ev_born0[k].record(stream)
+        kap = uf.born_kappa(counts, W, inb, out_dtype=torch.float32)
+        if k is not None:
+            ev_born1[k].record(stream)
+        g = kap * 2.0  # dL/dkappa of L = sum kappa^2
+        gW = uf.born_kappa_adjoint(counts, inb, g)
+        gth = uf.lensing_weights_vjp(dW, gW)
+        outs.update(kappa=kap, W=W, gW=gW, gth=gth, inb=inb)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    status.zero_()
+    t1 = time.perf_counter()
+    for k in range(args.steps):
+        step(k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    ms_per_step = 1e3 * wall / args.steps
+    bin_ms = sum(a.elapsed_time(b) for a, b in zip(ev_bin0, ev_bin1)) / args.steps
+    born_ms = sum(a.elapsed_time(b) for a, b in zip(ev_born0, ev_born1)) / args.steps
+    st = uf.status_dict(status)
+    inst_per_step = st["n_instances"] / args.steps
+
+    kap = outs["kappa"].double()
+    rms = float(kap.pow(2).mean().sqrt())
+    max_over_rms = float(kap.abs().max()) / rms
+
+    # algorithmic bytes of one binning launch: positions once + the count map written once
+    bin_bytes = 3 * 4 * n + 4 * B * uf.npix(nside)
+    born_bytes = 4 * B * uf.npix(nside) + 4 * uf.npix(nside)
+    value = n / (ms_per_step / 1e3)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "lognormal lightcone: 2^27 FP32 particles, 1 Gpc/h box replicated to z=0.5 "
+                        f"(images {{-{R}..{R}}}^3), 30 shells z=0.1-0.5, Nside 1024 RING, Smail n(z); "
+                        "bin + weights + Born kappa + adjoint per step",
+            "particles": n, "shells": B, "nside": nside, "order": args.order,
+            "instances_per_step": inst_per_step,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "bin_shells_kernel<float,false>",
+            "achieved": bin_bytes / (bin_ms / 1e3) / 1e9,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": bin_bytes / (bin_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "traffic": None,
+            "launch_ms": bin_ms,
+            "algorithmic_bytes": bin_bytes,
+        },
+        "born": {
+            "launch_ms": born_ms,
+            "achieved_GBs": born_bytes / (born_ms / 1e3) / 1e9,
+            "frac_hbm": born_bytes / (born_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "maps_per_s": 1e3 / born_ms,
+        },
+        "instances_per_s": inst_per_step / (ms_per_step / 1e3),
+        "guarded_per_step": st["n_guarded"] / args.steps,
+        "unresolved": st["n_unresolved"],
+        "kappa_max_over_rms": max_over_rms,
+        "input_generation_s": gen_s,
+    }
+
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(x, y, z, edges, nside, L, R, args.cpu_sample, n)
+
+    if args.batched:
+        line["batched"] = batched_vs_plain(dev)
+
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(x, y, z, edges, nside, L, R, sample, n):
+    """The oracle (plain single-threaded FP64 C loop + exact resolver) on the first
+    `sample` particles of the same catalogue, one host core."""
+    from oracle import binning as obin
+
+    m = min(sample, n)
+    xs, ys, zs = (t[:m].cpu().numpy() for t in (x, y, z))
+    t0 = time.perf_counter()
+    counts, st = obin.bin_shells(xs, ys, zs, (L / 2,) * 3, L, R, edges, nside, threads=1)
+    dt = time.perf_counter() - t0
+    return {"value": m / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {m} particles of the bench catalogue (all {len(edges) - 1} shells, "
+                      f"Nside {nside}, images {{-{R}..{R}}}^3); {st['instances']} instances in {dt:.1f} s",
+            "instances_per_s": st["instances"] / dt}
+
+
+def batched_vs_plain(dev):
+    """Maps/s of 16 realisations (uneven 64M-256M particles, 20-60 shells over z = 0.1-1.0,
+    Nside 1024, delta source z = 1.0): one graph replay against 16 sequences of plain calls."""
+    import torch
+
+    import paper_1801_05745_amd as uf
+    import synth
+
+    L, nside, om = 1000.0, 1024, 0.3
+    M = 1 << 20
+    sizes = synth.randint(16, 64 * M, 256 * M, seed=0, stream=900)
+    shells = synth.randint(16, 20, 60, seed=0, stream=901)
+    items = []
+    for r in range(16):
+        x, y, z = synth.lognormal_box(sizes[r], L, seed=r, ngrid=256, dtype=torch.float32, device=dev)
+        zg = torch.linspace(0.1, 1.0, shells[r] + 1, dtype=torch.float64, device=dev)
+        edges = uf.comoving_distance(zg, om).cpu().tolist()
+        W = uf.lensing_weights(om, [uf.SourceSpec("delta", z_s=1.0)], edges, device=dev)
+        inb = uf.inv_nbar(sizes[r], L, edges, nside, device=dev)
+        items.append(dict(x=x, y=y, z=z, chi_edges=edges, box_L=L, n_rep=2,
+                          counts=torch.empty((shells[r], uf.npix(nside)), dtype=torch.uint32, device=dev),
+                          W=W, inv_nbar=inb,
+                          kappa=torch.empty((1, uf.npix(nside)), dtype=torch.float32, device=dev)))
+    plan = uf.BatchPlan(items, nside, T=1)
+    ws = uf.bin_shells_workspace(device=dev)
+
+    def plain():
+        for it in items:
+            uf.fill_u32(it["counts"], 0)
+            uf.bin_shells(it["x"], it["y"], it["z"], it["chi_edges"], nside, box_L=L, n_rep=2, counts=it["counts"],
+                          workspace=ws)
+            uf.born_kappa(it["counts"], it["W"], it["inv_nbar"])
+
+    def timed(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_plain = timed(plain)
+    t_graph = timed(plan.run_graph)
+    plan.close()
+    return {"maps_per_s_batched": 16 / t_graph, "maps_per_s_plain": 16 / t_plain,
+            "speedup": t_plain / t_graph, "particles": int(sum(sizes)), "shells": shells}
+
+
+if __name__ == "__main__":
+    main()
