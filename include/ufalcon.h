@@ -92,11 +92,20 @@ int ufalcon_fill_u32(uint32_t *p, int64_t n, uint32_t value, ufalcon_stream_t st
  *              one (ufalcon_bin_shells_workspace_size(k) lists k) avoids a second
  *              walk over all images when more than that many are guarded.  Calls
  *              sharing a workspace must be stream-ordered.
+ * Accumulation: with a workspace of at least
+ *              ufalcon_bin_shells_workspace_size_partitioned(n, n_rep, shell_end - shell_begin,
+ *              nside, k) bytes (k = keys per chunk, e.g. n * (2 n_rep + 1)^3), the
+ *              counts are accumulated by the partitioned path (keys emitted, radix-
+ *              partitioned by cell block, counted in LDS; particles are processed in
+ *              device-planned chunks when the keys exceed the workspace); with a
+ *              smaller one, by one global atomic per instance.  Both give identical maps.
  * Errors: EINVAL, EUNSORTED_EDGES, ENSIDE, ETOO_MANY_SHELLS, EWORKSPACE, EOVERFLOW
  * (host bound on the instances one cell can receive in this call exceeds
  * 2^32 - 1), EHIP.
  */
 size_t ufalcon_bin_shells_workspace_size(int64_t max_listed);
+size_t ufalcon_bin_shells_workspace_size_partitioned(int64_t n, int32_t n_rep, int32_t shells_in_range,
+                                                     int64_t nside, int64_t max_keys);
 int ufalcon_bin_shells(const void *x, const void *y, const void *z, int64_t n, int dtype,
                        const double *observer, double box_L, int32_t n_rep,
                        const double *chi_edges, int32_t n_shells, int32_t shell_begin, int32_t shell_end,

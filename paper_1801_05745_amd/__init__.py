@@ -62,6 +62,7 @@ _SIGS = {
     "ufalcon_version": (ctypes.c_int, []),
     "ufalcon_fill_u32": (ctypes.c_int, [_P, _I64, ctypes.c_uint32, _P]),
     "ufalcon_bin_shells_workspace_size": (_SZ, [_I64]),
+    "ufalcon_bin_shells_workspace_size_partitioned": (_SZ, [_I64, _I32, _I32, _I64, _I64]),
     "ufalcon_bin_shells": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, ctypes.POINTER(_D), _D, _I32,
                                           ctypes.POINTER(_D), _I32, _I32, _I32, _I64, _P, _P, _P, _SZ, _P]),
     "ufalcon_comoving_distance": (ctypes.c_int, [_P, _I64, _D, _P, _P]),
@@ -150,8 +151,28 @@ def _workspace(nbytes: int, device, key: str):
 
 
 def bin_shells_workspace(max_listed: int = 1 << 20, device="cuda"):
+    """Workspace for the atomic accumulation path (guard list of max_listed entries)."""
     lib = load()
     return _workspace(int(lib.ufalcon_bin_shells_workspace_size(max_listed)), device, "bin")
+
+
+MAX_PARTITION_KEYS = 0xFFF00000 - (1 << 25)
+
+
+def partition_workspace(n, n_rep, shells_in_range, nside, max_keys=None, device="cuda", cached=True):
+    """Workspace that selects the partitioned accumulation path (keys per chunk: max_keys,
+    default n (2 n_rep + 1)^3, capped below 2^32)."""
+    lib = load()
+    if max_keys is None:
+        max_keys = n * (2 * n_rep + 1) ** 3
+    max_keys = int(min(max_keys, MAX_PARTITION_KEYS))
+    nbytes = int(lib.ufalcon_bin_shells_workspace_size_partitioned(int(n), int(n_rep), int(shells_in_range),
+                                                                  int(nside), max_keys))
+    if nbytes == 0:
+        raise ValueError("no partitioned layout for these sizes")
+    if not cached:
+        return torch.empty(nbytes, dtype=torch.uint8, device=device)
+    return _workspace(nbytes, device, "partition")
 
 
 def new_status(device="cuda"):
@@ -179,11 +200,13 @@ def new_counts(n_shells: int, nside: int, device="cuda"):
 
 
 def bin_shells(x, y, z, chi_edges, nside, observer=None, box_L=0.0, n_rep=0, shell_begin=0, shell_end=None,
-               counts=None, status=None, workspace=None):
+               counts=None, status=None, workspace=None, method="partition"):
     """Add the particles' (shell, RING pixel) counts to `counts` (uint32 [n_shells][npix]).
 
     x, y, z: contiguous float32 or float64 device tensors of equal length.
     chi_edges: shell edges in Mpc/h (host sequence, n_shells + 1 values).
+    method: "partition" (keys + radix partition + LDS histograms) or "atomic"
+    (one global atomic per instance); it only chooses the default workspace.
     """
     lib = load()
     if not (x.dtype == y.dtype == z.dtype) or not (x.numel() == y.numel() == z.numel()):
@@ -203,7 +226,13 @@ def bin_shells(x, y, z, chi_edges, nside, observer=None, box_L=0.0, n_rep=0, she
     if counts.dtype != torch.uint32 or not counts.is_contiguous() or counts.numel() != n_shells * npix(nside):
         raise ValueError("counts must be contiguous uint32 [n_shells][12 nside^2]")
     if workspace is None:
-        workspace = bin_shells_workspace(device=x.device)
+        if method == "partition":
+            workspace = partition_workspace(x.numel(), n_rep, int(shell_end) - int(shell_begin), nside,
+                                            device=x.device)
+        elif method == "atomic":
+            workspace = bin_shells_workspace(device=x.device)
+        else:
+            raise ValueError(method)
     rc = lib.ufalcon_bin_shells(_ptr(x), _ptr(y), _ptr(z), x.numel(), _dtype_code(x.dtype), obs, float(box_L),
                                 int(n_rep), e, n_shells, int(shell_begin), int(shell_end), int(nside), _ptr(counts),
                                 _ptr(status), _ptr(workspace), workspace.numel(), _stream(x.device))

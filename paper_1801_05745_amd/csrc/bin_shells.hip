@@ -27,229 +27,17 @@
 // The batched form (many realisations, section 3.2's 150 maps) runs the same
 // per-wave core in a persistent kernel whose workgroups pull (realisation,
 // tile) items from an atomic work counter until the queue is empty.
-#include "../../include/ufalcon.h"
-#include "exact.hpp"
-#include "internal.hpp"
-#include "ring.hpp"
+#include "binning_core.hpp"
 
 #include <algorithm>
 #include <vector>
 
 namespace ufx {
 
-constexpr int kBinBlock = 256;
-constexpr int kBinWaves = kBinBlock / 64;
-constexpr int kQueue = 128;  // < 64 pending + up to 64 new entries
 
-// Workspace layout: this header, then guard_cap entries.
-struct GuardList {
-    unsigned int count;     // guarded instances seen (may exceed the capacity)
-    unsigned int overflow;  // nonzero when some guarded instance was not stored
-    unsigned int next;      // work counter of the persistent kernel
-    unsigned int next_rescue;
-    unsigned int pad[60];
-};
-struct GuardEntry {
-    double dx, dy, dz;
-    int32_t item;
-    int32_t pad;
-};
-constexpr size_t kGuardHeader = sizeof(GuardList);
-static_assert(kGuardHeader == 256, "workspace header is 256 bytes");
-
-// Everything the per-wave core needs about one particle set.
-struct BinCore {
-    const void *x, *y, *z;
-    int64_t n;
-    double ox, oy, oz, L;
-    double lo2, hi2;      // guard-widened [e_b0^2, e_b1^2)
-    int32_t R;            // images {-R..R}^3
-    int32_t nb;           // shells in range
-    int32_t steps;        // binary-search steps over nb + 1 edges
-    int32_t item;         // realisation index (batched) or 0
-    uint32_t *counts;     // row of the first shell in range
-};
-
-struct BinParams {
-    BinCore c;
-    int64_t nside, npix;
-    double eps;           // floor-argument margin
-    ufalcon_status *status;
-    GuardList *guard;     // workspace header
-    int64_t guard_cap;    // entries the workspace holds
-    double e[UFALCON_MAX_SHELLS + 1];  // edges of the range, e_b0 .. e_b1
-};
-
-struct LaneStats {
-    unsigned long long inst = 0, guarded = 0, unresolved = 0, invalid = 0;
-};
-
-struct Shared {
-    GuardList *guard;
-    int64_t guard_cap;
-    int64_t nside, npix;
-    double eps;
-};
-
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-// Exact decision for one guarded instance.  Returns bit 0: counted, bit 1: unresolved.
-__device__ __noinline__ int bin_instance_exact(uint32_t *counts, int64_t npix, int64_t nside, const double *e, int nb,
-                                               double dx, double dy, double dz) {
-    const int b = exact_shell(dx, dy, dz, e, nb);
-    if (b < 0 || b >= nb) return 0;
-    int unresolved = 0;
-    const int64_t pix = exact_ring_pixel(nside, dx, dy, dz, &unresolved);
-    if (pix < 0 || pix >= npix) return 2;  // never expected; reported as unresolved, not written
-    atomicAdd(counts + (int64_t)b * npix + pix, 1u);
-    return 1 | (unresolved << 1);
-}
-
-// Streaming mode: count clear instances, list guarded ones.
-// Rescue mode: skip clear instances (already counted), decide guarded ones exactly.
-template <bool kRescue>
-__device__ __forceinline__ void bin_instance(const BinCore &c, const Shared &sh, const double *e_s, const double *e2_s,
-                                             double Nd, double dx, double dy, double dz, LaneStats &st) {
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    bool clear;
-    const int j = fast_shell(e2_s, c.nb, c.steps, r2, clear);
-    if (clear) {
-        if (j < 0 || j >= c.nb) return;
-        int64_t pix;
-        // the range test costs two compares and keeps any logic slip from writing out of bounds
-        if (fast_ring_pixel(sh.nside, Nd, sh.eps, dx, dy, dz, pix) && pix >= 0 && pix < sh.npix) {
-            if (!kRescue) {
-                atomicAdd(c.counts + (int64_t)j * sh.npix + pix, 1u);
-                ++st.inst;
-            }
-            return;
-        }
-    }
-    if (kRescue) {
-        const int r = bin_instance_exact(c.counts, sh.npix, sh.nside, e_s, c.nb, dx, dy, dz);
-        st.inst += r & 1;
-        st.unresolved += (r >> 1) & 1;
-    } else {
-        ++st.guarded;
-        const unsigned int slot = atomicAdd(&sh.guard->count, 1u);
-        if ((int64_t)slot < sh.guard_cap) {
-            GuardEntry *ent = reinterpret_cast<GuardEntry *>(reinterpret_cast<char *>(sh.guard) + kGuardHeader) + slot;
-            ent->dx = dx;
-            ent->dy = dy;
-            ent->dz = dz;
-            ent->item = c.item;
-        } else {
-            atomicOr(&sh.guard->overflow, 1u);
-        }
-    }
-}
-
-// Per-wave core: this wave handles particles base, base + stride, ... (64 at a
-// time) below `end`; queued images persist in (Qx, Qy, Qz, count) across calls
-// and are drained by drain_queue().
-template <typename T, bool kRescue>
-__device__ __forceinline__ void bin_wave_range(const BinCore &c, const Shared &sh, const double *e_s,
-                                               const double *e2_s, int64_t base, int64_t end, int64_t stride,
-                                               double *Qx, double *Qy, double *Qz, int &count, LaneStats &st) {
-    const int lane = threadIdx.x & 63;
-    const unsigned long long below = (1ull << lane) - 1ull;
-    const T *X = static_cast<const T *>(c.x);
-    const T *Y = static_cast<const T *>(c.y);
-    const T *Z = static_cast<const T *>(c.z);
-    const double Nd = (double)sh.nside;
-    for (; base < end; base += stride) {
-        const int64_t i = base + lane;
-        bool valid = false;
-        double bx = 0.0, by = 0.0, bz = 0.0;
-        if (i < end) {
-            const double x = (double)X[i], y = (double)Y[i], z = (double)Z[i];
-            if (isfinite(x) && isfinite(y) && isfinite(z)) {
-                valid = true;
-                bx = x - c.ox;
-                by = y - c.oy;
-                bz = z - c.oz;
-            } else if (!kRescue) {
-                ++st.invalid;
-            }
-        }
-        for (int sx = -c.R; sx <= c.R; ++sx) {
-            const double dx = bx + (double)sx * c.L;
-            for (int sy = -c.R; sy <= c.R; ++sy) {
-                const double dy = by + (double)sy * c.L;
-                for (int sz = -c.R; sz <= c.R; ++sz) {
-                    const double dz = bz + (double)sz * c.L;
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    const bool in = valid && r2 >= c.lo2 && r2 < c.hi2;
-                    const unsigned long long m = __ballot(in);
-                    if (m == 0ull) continue;
-                    const int pos = count + __popcll(m & below);
-                    if (in) {
-                        Qx[pos] = dx;
-                        Qy[pos] = dy;
-                        Qz[pos] = dz;
-                    }
-                    count += __popcll(m);
-                    if (count >= 64) {
-                        wave_lds_sync();
-                        const double ax = Qx[lane], ay = Qy[lane], az = Qz[lane];
-                        const int rest = count - 64;
-                        double rx = 0.0, ry = 0.0, rz = 0.0;
-                        if (lane < rest) {
-                            rx = Qx[64 + lane];
-                            ry = Qy[64 + lane];
-                            rz = Qz[64 + lane];
-                        }
-                        wave_lds_sync();
-                        if (lane < rest) {
-                            Qx[lane] = rx;
-                            Qy[lane] = ry;
-                            Qz[lane] = rz;
-                        }
-                        count = rest;
-                        bin_instance<kRescue>(c, sh, e_s, e2_s, Nd, ax, ay, az, st);
-                    }
-                }
-            }
-        }
-    }
-}
-
-template <bool kRescue>
-__device__ __forceinline__ void drain_queue(const BinCore &c, const Shared &sh, const double *e_s, const double *e2_s,
-                                            double *Qx, double *Qy, double *Qz, int &count, LaneStats &st) {
-    const int lane = threadIdx.x & 63;
-    wave_lds_sync();
-    if (lane < count) bin_instance<kRescue>(c, sh, e_s, e2_s, (double)sh.nside, Qx[lane], Qy[lane], Qz[lane], st);
-    wave_lds_sync();
-    count = 0;
-}
-
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__device__ __forceinline__ void flush_stats(ufalcon_status *status, LaneStats &st) {
-    const unsigned long long a = wave_sum(st.inst), b = wave_sum(st.guarded), c = wave_sum(st.unresolved),
-                             d = wave_sum(st.invalid);
-    if (status && (threadIdx.x & 63) == 0) {
-        if (a) atomicAdd(&status->n_instances, a);
-        if (b) atomicAdd(&status->n_guarded, b);
-        if (c) atomicAdd(&status->n_unresolved, c);
-        if (d) atomicAdd(&status->n_invalid, d);
-    }
-}
-
-__device__ __forceinline__ Shared shared_of(const BinParams &p) {
-    return Shared{p.guard, p.guard_cap, p.nside, p.npix, p.eps};
-}
-
-template <typename T, bool kRescue>
+template <typename T, int kMode>
 __global__ __launch_bounds__(kBinBlock) void bin_shells_kernel(BinParams p) {
-    if (kRescue && p.guard->overflow == 0u) return;  // uniform: nothing to rescue
+    if (kMode == kRescue && p.guard->overflow == 0u) return;  // uniform: nothing to rescue
     __shared__ double e_s[UFALCON_MAX_SHELLS + 1];
     __shared__ double e2_s[UFALCON_MAX_SHELLS + 1];
     __shared__ double qx[kBinWaves][kQueue], qy[kBinWaves][kQueue], qz[kBinWaves][kQueue];
@@ -261,11 +49,12 @@ __global__ __launch_bounds__(kBinBlock) void bin_shells_kernel(BinParams p) {
     const int w = threadIdx.x >> 6;
     const Shared sh = shared_of(p);
     LaneStats st;
+    Emitter em{};
     int count = 0;
     const int64_t base = (int64_t)blockIdx.x * kBinBlock + w * 64;
     const int64_t stride = (int64_t)gridDim.x * kBinBlock;
-    bin_wave_range<T, kRescue>(p.c, sh, e_s, e2_s, base, p.c.n, stride, qx[w], qy[w], qz[w], count, st);
-    drain_queue<kRescue>(p.c, sh, e_s, e2_s, qx[w], qy[w], qz[w], count, st);
+    bin_wave_range<T, kMode>(p.c, sh, e_s, e2_s, base, p.c.n, stride, qx[w], qy[w], qz[w], count, st, em);
+    drain_queue<kMode>(p.c, sh, e_s, e2_s, qx[w], qy[w], qz[w], count, st, em);
     flush_stats(p.status, st);
 }
 
@@ -339,9 +128,9 @@ __device__ __forceinline__ int find_item(const BatchItemDev *items, int n_items,
     return lo;
 }
 
-template <typename T, bool kRescue>
+template <typename T, int kMode>
 __global__ __launch_bounds__(kBinBlock) void bin_batched_kernel(BatchParams p) {
-    if (kRescue && p.sh.guard->overflow == 0u) return;
+    if (kMode == kRescue && p.sh.guard->overflow == 0u) return;
     __shared__ double e_s[UFALCON_MAX_SHELLS + 1];
     __shared__ double e2_s[UFALCON_MAX_SHELLS + 1];
     __shared__ double qx[kBinWaves][kQueue], qy[kBinWaves][kQueue], qz[kBinWaves][kQueue];
@@ -350,8 +139,9 @@ __global__ __launch_bounds__(kBinBlock) void bin_batched_kernel(BatchParams p) {
     const int w = threadIdx.x >> 6;
     if (threadIdx.x == 0) cur_item = -1;
     LaneStats st;
+    Emitter em{};
     int count = 0;
-    unsigned int *ctr = kRescue ? &p.sh.guard->next_rescue : &p.sh.guard->next;
+    unsigned int *ctr = kMode == kRescue ? &p.sh.guard->next_rescue : &p.sh.guard->next;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) work = (int64_t)atomicAdd(ctr, 1u);
@@ -372,8 +162,9 @@ __global__ __launch_bounds__(kBinBlock) void bin_batched_kernel(BatchParams p) {
         }
         const int64_t first = (t - p.items[k].tile_begin) * p.tile;
         const int64_t last = first + p.tile < c.n ? first + p.tile : c.n;
-        bin_wave_range<T, kRescue>(c, p.sh, e_s, e2_s, first + w * 64, last, kBinBlock, qx[w], qy[w], qz[w], count, st);
-        drain_queue<kRescue>(c, p.sh, e_s, e2_s, qx[w], qy[w], qz[w], count, st);
+        bin_wave_range<T, kMode>(c, p.sh, e_s, e2_s, first + w * 64, last, kBinBlock, qx[w], qy[w], qz[w], count, st,
+                                 em);
+        drain_queue<kMode>(c, p.sh, e_s, e2_s, qx[w], qy[w], qz[w], count, st, em);
     }
     flush_stats(p.status, st);
 }
@@ -474,14 +265,18 @@ template <typename T>
 int launch_bin_t(const BinParams &p, hipStream_t s) {
     const unsigned grid = blocks_for(p.c.n, kBinBlock, (unsigned)device_cus() * 16u);
     hipLaunchKernelGGL(guard_reset_kernel, dim3(1), dim3(64), 0, s, p.guard);
-    hipLaunchKernelGGL((bin_shells_kernel<T, false>), dim3(grid), dim3(kBinBlock), 0, s, p);
+    hipLaunchKernelGGL((bin_shells_kernel<T, kAtomic>), dim3(grid), dim3(kBinBlock), 0, s, p);
     hipLaunchKernelGGL(bin_guarded_kernel, dim3(64), dim3(256), 0, s, p);
-    hipLaunchKernelGGL((bin_shells_kernel<T, true>), dim3(grid), dim3(kBinBlock), 0, s, p);
+    hipLaunchKernelGGL((bin_shells_kernel<T, kRescue>), dim3(grid), dim3(kBinBlock), 0, s, p);
     UFX_HIP_CHECK(hipGetLastError());
     return UFALCON_OK;
 }
 
 }  // namespace ufx
+
+namespace ufx {
+int try_partitioned(BinParams &p, int dtype, void *workspace, size_t bytes, hipStream_t s, int *rc);
+}
 
 using namespace ufx;
 
@@ -534,6 +329,8 @@ extern "C" int ufalcon_bin_shells(const void *x, const void *y, const void *z, i
     p.guard_cap = guard_capacity(workspace_bytes);
     if (p.c.n == 0 || p.c.nb == 0) return UFALCON_OK;
     hipStream_t s = as_stream(stream);
+    int prc = UFALCON_OK;
+    if (try_partitioned(p, dtype, workspace, workspace_bytes, s, &prc)) return prc;
     return dtype == UFALCON_F32 ? launch_bin_t<float>(p, s) : launch_bin_t<double>(p, s);
 }
 
@@ -688,13 +485,13 @@ extern "C" int ufalcon_bin_shells_batched(ufalcon_batch_plan *plan, ufalcon_stat
     const unsigned wgs = (unsigned)std::min<int64_t>(plan->wgs, plan->total_tiles);
     hipLaunchKernelGGL(guard_reset_kernel, dim3(1), dim3(64), 0, s, bp.sh.guard);
     if (plan->dtype == UFALCON_F32) {
-        hipLaunchKernelGGL((bin_batched_kernel<float, false>), dim3(wgs), dim3(kBinBlock), 0, s, bp);
+        hipLaunchKernelGGL((bin_batched_kernel<float, kAtomic>), dim3(wgs), dim3(kBinBlock), 0, s, bp);
         hipLaunchKernelGGL(bin_batched_guarded_kernel, dim3(64), dim3(256), 0, s, bp);
-        hipLaunchKernelGGL((bin_batched_kernel<float, true>), dim3(wgs), dim3(kBinBlock), 0, s, bp);
+        hipLaunchKernelGGL((bin_batched_kernel<float, kRescue>), dim3(wgs), dim3(kBinBlock), 0, s, bp);
     } else {
-        hipLaunchKernelGGL((bin_batched_kernel<double, false>), dim3(wgs), dim3(kBinBlock), 0, s, bp);
+        hipLaunchKernelGGL((bin_batched_kernel<double, kAtomic>), dim3(wgs), dim3(kBinBlock), 0, s, bp);
         hipLaunchKernelGGL(bin_batched_guarded_kernel, dim3(64), dim3(256), 0, s, bp);
-        hipLaunchKernelGGL((bin_batched_kernel<double, true>), dim3(wgs), dim3(kBinBlock), 0, s, bp);
+        hipLaunchKernelGGL((bin_batched_kernel<double, kRescue>), dim3(wgs), dim3(kBinBlock), 0, s, bp);
     }
     UFX_HIP_CHECK(hipGetLastError());
     return UFALCON_OK;

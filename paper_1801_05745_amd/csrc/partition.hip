@@ -1,0 +1,648 @@
+// Partitioned accumulation of the count maps (the keyed-sort form of the
+// histogram of section 2.3 eq. (5)).
+//
+// Random 32-bit atomics into a GB-sized map run at a fixed ceiling on this GPU
+// (about 2e10 per second), far below what the FP64 pixelisation delivers, so
+// this path never updates the map once per instance.  Instead:
+//   0. count: per group of particles, an upper bound on its in-range images
+//      (squared radius only); plan: split the particles into chunks whose keys
+//      fit the workspace (on the device, no host synchronisation);
+//   per chunk:
+//   1. keys: the binning core emits key = b * npix + pix per instance into a
+//      buffer (waves reserve 1024-slot chunks; a per-workgroup LDS histogram
+//      counts keys per level-1 bucket, key >> s1);
+//   2. level-1 partition by key >> s1 (MSD radix step, <= 1024 buckets);
+//   3. histogram of cell blocks (key >> 14) inside each level-1 bucket;
+//   4. level-2 partition by cell block into a block-ordered buffer;
+//   5. accumulate: one workgroup per 16384-cell block counts its keys with LDS
+//      atomics and adds the block into the map with coalesced 16-byte
+//      read-modify-writes (blocks without keys are skipped).
+// Each partition step works on super-tiles of 32768 keys: a histogram pass, one
+// global reservation per nonempty bucket, then 8192-key sub-tiles sorted in LDS
+// and written as contiguous runs.  Integer counts make the result independent
+// of every order involved.
+#include "binning_core.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace ufx {
+
+constexpr int kBlockShift = 14;                  // cells per accumulation block: 2^14
+constexpr int kBlockCells = 1 << kBlockShift;
+constexpr int kSuper = 32768;                    // keys per partition super-tile
+constexpr int kSub = 8192;                       // keys per LDS-sorted sub-tile
+constexpr int kPartThreads = 256;
+constexpr int kMaxBins = 1024;                   // buckets per partition level
+constexpr int kGroup = 8192;                     // particles per counting group
+constexpr int kAccThreads = 512;
+
+struct PartHeader {
+    unsigned long long reserved;  // key slots reserved by the key pass of the current chunk
+    unsigned int n_chunks;        // chunks the plan produced
+    unsigned int pad0;
+    unsigned long long pad[30];
+};
+static_assert(sizeof(PartHeader) == 256, "partition header is 256 bytes");
+
+struct PartLayout {
+    int s1;                 // level-1 shift
+    int nb1, nb2;           // buckets per level
+    int64_t nblk;           // cell blocks (nb1 * nb2 slots allocated)
+    int64_t ngroups;        // particle groups
+    int kmax;               // chunk iterations launched
+    unsigned long long cap; // key slots per buffer (multiple of kKeyChunk)
+    unsigned long long budget;  // planned keys per chunk
+    size_t off_guard, off_hdr, off_hist1, off_cur1, off_off1, off_tiles1, off_histb, off_offb, off_curb, off_grp,
+        off_chunk, off_keysa, off_keysb, total;
+};
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+constexpr int64_t kPartGuardEntries = 65536;
+
+// Layout for a call; cap_slots = 0 means "as many as the bytes allow".
+static bool plan_layout(PartLayout &L, int64_t n, int64_t ncells, int img_bound, size_t bytes, int64_t want_keys) {
+    if (ncells <= 0 || ncells >= (int64_t)kNoKey) return false;
+    int bits = 0;
+    while (((int64_t)1 << bits) < ncells) ++bits;
+    const int blk_bits = bits > kBlockShift ? bits - kBlockShift : 0;  // log2(#blocks), rounded up
+    int b2 = blk_bits / 2;
+    int b1 = blk_bits - b2;
+    if (b1 > 10 || b2 > 10) return false;
+    L.s1 = kBlockShift + b2;
+    L.nb2 = 1 << b2;
+    L.nb1 = (int)((ncells + ((int64_t)1 << L.s1) - 1) >> L.s1);
+    L.nblk = (int64_t)L.nb1 * L.nb2;
+    L.ngroups = (n + kGroup - 1) / kGroup;
+    size_t o = 0;
+    L.off_guard = o; o = align256(o + kGuardHeader + kPartGuardEntries * sizeof(GuardEntry));
+    L.off_hdr = o; o = align256(o + sizeof(PartHeader));
+    L.off_hist1 = o; o = align256(o + sizeof(uint32_t) * L.nb1);
+    L.off_cur1 = o; o = align256(o + sizeof(uint32_t) * L.nb1);
+    L.off_off1 = o; o = align256(o + sizeof(uint32_t) * (L.nb1 + 1));
+    L.off_tiles1 = o; o = align256(o + sizeof(uint32_t) * (L.nb1 + 1));
+    L.off_histb = o; o = align256(o + sizeof(uint32_t) * L.nblk);
+    L.off_offb = o; o = align256(o + sizeof(uint32_t) * (L.nblk + 1));
+    L.off_curb = o; o = align256(o + sizeof(uint32_t) * L.nblk);
+    L.off_grp = o; o = align256(o + sizeof(uint32_t) * L.ngroups);
+    const int kmax_cap = 4096;
+    L.off_chunk = o; o = align256(o + sizeof(uint32_t) * (kmax_cap + 1));
+    const size_t fixed = o;
+    // slack: every wave of the key pass may leave up to one partly filled chunk
+    const unsigned long long slack = (unsigned long long)kKeyChunk * (unsigned long long)device_cus() * 16ull * kBinWaves;
+    unsigned long long cap;
+    if (want_keys > 0) {
+        cap = (unsigned long long)want_keys + slack;
+    } else {
+        if (bytes < fixed + 512) return false;
+        cap = (bytes - fixed - 512) / (2 * sizeof(uint32_t));
+    }
+    if (cap > 0xFFF00000ull) cap = 0xFFF00000ull;  // offsets are 32-bit
+    cap = cap / kKeyChunk * kKeyChunk;
+    const unsigned long long gmax = (unsigned long long)kGroup * (unsigned long long)img_bound;
+    if (cap < slack + 4 * gmax) return false;
+    L.cap = cap;
+    L.budget = cap - slack;
+    L.off_keysa = fixed;
+    L.off_keysb = align256(fixed + sizeof(uint32_t) * cap);
+    L.total = align256(L.off_keysb + sizeof(uint32_t) * cap);
+    const double est = (double)n * (double)img_bound;
+    double k = std::ceil(est / (double)L.budget);
+    if (k < 1.0) k = 1.0;
+    L.kmax = (int)std::min<double>(k, (double)kmax_cap);
+    return true;
+}
+
+// Geometric bound on the images of one particle of [0, L)^3 that can reach the shell range.
+static int image_bound(const BinCore &c, const double *e, int nb) {
+    if (c.R == 0) return 1;
+    const double o[3] = {c.ox, c.oy, c.oz};
+    const double emin = e[0] * (1.0 - 1e-9), emax = e[nb] * (1.0 + 1e-9);
+    int cnt = 0;
+    for (int sx = -c.R; sx <= c.R; ++sx)
+        for (int sy = -c.R; sy <= c.R; ++sy)
+            for (int sz = -c.R; sz <= c.R; ++sz) {
+                const int s[3] = {sx, sy, sz};
+                double dmin = 0.0, dmax = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const double lo = s[a] * c.L - o[a], hi = lo + c.L;
+                    const double nearest = lo > 0.0 ? lo : (hi < 0.0 ? -hi : 0.0);
+                    const double farthest = std::max(std::fabs(lo), std::fabs(hi));
+                    dmin += nearest * nearest;
+                    dmax += farthest * farthest;
+                }
+                if (std::sqrt(dmin) < emax && std::sqrt(dmax) >= emin) ++cnt;
+            }
+    return cnt > 0 ? cnt : 1;
+}
+
+// ------------------------------------------------------------------ kernels
+
+// 0a. upper bound of in-range images per group of kGroup particles
+template <typename T>
+__global__ __launch_bounds__(256) void count_groups_kernel(BinCore c, uint32_t *grp) {
+    __shared__ unsigned int red[4];
+    const T *X = static_cast<const T *>(c.x);
+    const T *Y = static_cast<const T *>(c.y);
+    const T *Z = static_cast<const T *>(c.z);
+    const int64_t g = blockIdx.x;
+    const int64_t beg = g * kGroup;
+    const int64_t end = beg + kGroup < c.n ? beg + kGroup : c.n;
+    unsigned int cnt = 0;
+    for (int64_t i = beg + threadIdx.x; i < end; i += 256) {
+        const double x = (double)X[i], y = (double)Y[i], z = (double)Z[i];
+        if (!(isfinite(x) && isfinite(y) && isfinite(z))) continue;
+        const double bx = x - c.ox, by = y - c.oy, bz = z - c.oz;
+        for (int sx = -c.R; sx <= c.R; ++sx) {
+            const double dx = bx + (double)sx * c.L;
+            for (int sy = -c.R; sy <= c.R; ++sy) {
+                const double dy = by + (double)sy * c.L;
+                for (int sz = -c.R; sz <= c.R; ++sz) {
+                    const double dz = bz + (double)sz * c.L;
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    cnt += (r2 >= c.lo2 && r2 < c.hi2) ? 1u : 0u;
+                }
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) grp[g] = red[0] + red[1] + red[2] + red[3];
+}
+
+// 0b. chunk plan: chunk k covers groups [chunk[k], chunk[k+1]); every chunk's
+// bound stays below the budget (each group's bound is far below it).
+__global__ __launch_bounds__(1024) void plan_chunks_kernel(const uint32_t *grp, int64_t ngroups,
+                                                           unsigned long long budget, int kmax, uint32_t *chunk,
+                                                           PartHeader *hdr) {
+    __shared__ unsigned long long part[1024];
+    __shared__ unsigned long long carry;
+    for (int k = threadIdx.x; k <= kmax; k += 1024) chunk[k] = k == 0 ? 0u : (uint32_t)ngroups;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    unsigned long long last_c = 0;
+    for (int64_t base = 0; base < ngroups; base += 1024) {
+        const int64_t g = base + threadIdx.x;
+        const unsigned long long v = g < ngroups ? grp[g] : 0ull;
+        part[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan (Hillis-Steele)
+            const unsigned long long t = threadIdx.x >= off ? part[threadIdx.x - off] : 0ull;
+            __syncthreads();
+            part[threadIdx.x] += t;
+            __syncthreads();
+        }
+        const unsigned long long excl = carry + part[threadIdx.x] - v;
+        if (g < ngroups && g > 0) {
+            const unsigned long long c = excl / budget;
+            const unsigned long long prev = (excl - grp[g - 1]) / budget;
+            if (c > prev && c < (unsigned long long)kmax) chunk[c] = (uint32_t)g;
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += part[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        last_c = carry == 0 ? 0ull : (carry - 1) / budget + 1;
+        hdr->n_chunks = (unsigned int)(last_c < (unsigned long long)kmax ? last_c : kmax);
+    }
+}
+
+// per-chunk reset of the histograms and the key counter
+__global__ void reset_chunk_kernel(PartHeader *hdr, uint32_t *hist1, int nb1, uint32_t *histb, int64_t nblk) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nblk; i += stride) histb[i] = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb1; i += stride) hist1[i] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) hdr->reserved = 0ull;
+}
+
+// 1. emit keys for the particles of chunk k
+struct KeyParams {
+    BinParams p;
+    uint32_t *keys;
+    unsigned long long cap;
+    PartHeader *hdr;
+    uint32_t *hist1;
+    int s1, nb1;
+    const uint32_t *chunk;
+    int k, kmax;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBinBlock) void keys_kernel(KeyParams kp) {
+    const BinParams &p = kp.p;
+    __shared__ double e_s[UFALCON_MAX_SHELLS + 1];
+    __shared__ double e2_s[UFALCON_MAX_SHELLS + 1];
+    __shared__ double qx[kBinWaves][kQueue], qy[kBinWaves][kQueue], qz[kBinWaves][kQueue];
+    __shared__ uint32_t hist[kMaxBins];
+    if (kp.k >= (int)kp.hdr->n_chunks && kp.k != kp.kmax - 1) return;  // uniform: empty chunk
+    const int64_t p0 = (int64_t)kp.chunk[kp.k] * kGroup;
+    int64_t p1 = (int64_t)kp.chunk[kp.k + 1] * kGroup;
+    if (p1 > p.c.n) p1 = p.c.n;
+    if (p0 >= p1) return;
+    for (int j = threadIdx.x; j <= p.c.nb; j += kBinBlock) {
+        e_s[j] = p.e[j];
+        e2_s[j] = p.e[j] * p.e[j];
+    }
+    for (int j = threadIdx.x; j < kp.nb1; j += kBinBlock) hist[j] = 0u;
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    const Shared sh = shared_of(p);
+    LaneStats st;
+    Emitter em{};
+    em.keys = kp.keys;
+    em.reserved = &kp.hdr->reserved;
+    em.cap = kp.cap;
+    em.hist = hist;
+    em.shift = kp.s1;
+    em.base = 0;
+    em.fill = kKeyChunk;
+    em.full = false;
+    int count = 0;
+    const int64_t base = p0 + (int64_t)blockIdx.x * kBinBlock + w * 64;
+    const int64_t stride = (int64_t)gridDim.x * kBinBlock;
+    bin_wave_range<T, kEmit>(p.c, sh, e_s, e2_s, base, p1, stride, qx[w], qy[w], qz[w], count, st, em);
+    drain_queue<kEmit>(p.c, sh, e_s, e2_s, qx[w], qy[w], qz[w], count, st, em);
+    close_emitter(em);
+    flush_stats(p.status, st);
+    __syncthreads();
+    for (int j = threadIdx.x; j < kp.nb1; j += kBinBlock)
+        if (hist[j]) atomicAdd(&kp.hist1[j], hist[j]);
+}
+
+// exclusive scan of the level-1 histogram; segment tile prefix for level 2
+__global__ __launch_bounds__(1024) void scan_level1_kernel(const uint32_t *hist1, int nb1, uint32_t *off1,
+                                                           uint32_t *cur1, uint32_t *tiles1) {
+    __shared__ unsigned long long a[1024], b[1024];
+    const int t = threadIdx.x;
+    const unsigned long long h = t < nb1 ? hist1[t] : 0ull;
+    const unsigned long long nt = (h + kSuper - 1) / kSuper;
+    a[t] = h;
+    b[t] = nt;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const unsigned long long x = t >= off ? a[t - off] : 0ull, y = t >= off ? b[t - off] : 0ull;
+        __syncthreads();
+        a[t] += x;
+        b[t] += y;
+        __syncthreads();
+    }
+    if (t < nb1) {
+        off1[t] = (uint32_t)(a[t] - h);
+        cur1[t] = (uint32_t)(a[t] - h);
+        tiles1[t] = (uint32_t)(b[t] - nt);
+    }
+    if (t == nb1 - 1) {
+        off1[nb1] = (uint32_t)a[t];
+        tiles1[nb1] = (uint32_t)b[t];
+    }
+}
+
+// exclusive scan of the block histogram (one workgroup, running carry)
+__global__ __launch_bounds__(1024) void scan_blocks_kernel(const uint32_t *histb, int64_t nblk, uint32_t *offb,
+                                                           uint32_t *curb) {
+    __shared__ unsigned long long a[1024];
+    __shared__ unsigned long long carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nblk; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const unsigned long long h = i < nblk ? histb[i] : 0ull;
+        a[threadIdx.x] = h;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const unsigned long long x = threadIdx.x >= off ? a[threadIdx.x - off] : 0ull;
+            __syncthreads();
+            a[threadIdx.x] += x;
+            __syncthreads();
+        }
+        if (i < nblk) {
+            offb[i] = (uint32_t)(carry + a[threadIdx.x] - h);
+            curb[i] = (uint32_t)(carry + a[threadIdx.x] - h);
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += a[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) offb[nblk] = (uint32_t)carry;
+}
+
+// Shared partition step.  Level 1: one segment keys[0, reserved) (with
+// sentinels), bucket = key >> shift.  Level 2: segment s = level-1 bucket s,
+// bucket = (key >> shift) - s * nbins.  The histogram-only variant adds the
+// super-tile counts into hist_out[s * nbins + bucket].
+struct PartStep {
+    const uint32_t *in;
+    uint32_t *out;
+    int level;
+    int nseg;
+    const uint32_t *seg_off;    // level 2: [nseg + 1]
+    const uint32_t *seg_tiles;  // level 2: [nseg + 1]
+    const PartHeader *hdr;      // level 1: reserved slots
+    unsigned long long cap;
+    int shift, nbins;
+    uint32_t *cursor;           // [nseg * nbins]
+    uint32_t *hist_out;         // histogram-only variant
+};
+
+__device__ __forceinline__ void seg_range(const PartStep &ps, int64_t t, int &seg, int64_t &lo, int64_t &hi) {
+    if (ps.level == 1) {
+        unsigned long long total = ps.hdr->reserved;
+        if (total > ps.cap) total = ps.cap;
+        seg = 0;
+        lo = t * kSuper;
+        hi = lo + kSuper < (int64_t)total ? lo + kSuper : (int64_t)total;
+        return;
+    }
+    int a = 0, b = ps.nseg;  // largest s with seg_tiles[s] <= t
+    while (b - a > 1) {
+        const int mid = (a + b) >> 1;
+        if (ps.seg_tiles[mid] <= t) a = mid; else b = mid;
+    }
+    seg = a;
+    lo = (int64_t)ps.seg_off[a] + (t - ps.seg_tiles[a]) * kSuper;
+    hi = lo + kSuper < (int64_t)ps.seg_off[a + 1] ? lo + kSuper : (int64_t)ps.seg_off[a + 1];
+}
+
+__device__ __forceinline__ int64_t step_tiles(const PartStep &ps) {
+    if (ps.level == 1) {
+        unsigned long long total = ps.hdr->reserved;
+        if (total > ps.cap) total = ps.cap;
+        return (int64_t)((total + kSuper - 1) / kSuper);
+    }
+    return ps.seg_tiles[ps.nseg];
+}
+
+template <bool kHistOnly>
+__global__ __launch_bounds__(kPartThreads) void partition_kernel(PartStep ps, int chunk_k, int kmax) {
+    __shared__ uint32_t cnt[kMaxBins];     // super-tile counts, then sub-tile counts
+    __shared__ uint32_t gbase[kMaxBins];   // global start of this super-tile's run per bucket
+    __shared__ uint32_t run[kMaxBins];     // keys written per bucket so far in this super-tile
+    __shared__ uint32_t soff[kMaxBins];    // sub-tile local offsets
+    __shared__ uint32_t skeys[kSub];
+    __shared__ uint16_t sbins[kSub];
+    __shared__ uint32_t nvalid;
+    if (chunk_k >= (int)ps.hdr->n_chunks && chunk_k != kmax - 1) return;
+    const int tid = threadIdx.x;
+    const int64_t ntiles = step_tiles(ps);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int seg;
+        int64_t lo, hi;
+        seg_range(ps, t, seg, lo, hi);
+        const uint32_t bin0 = (uint32_t)seg * (uint32_t)ps.nbins;
+        for (int b = tid; b < ps.nbins; b += kPartThreads) cnt[b] = 0u;
+        __syncthreads();
+        for (int64_t i = lo + tid; i < hi; i += kPartThreads) {
+            const uint32_t key = ps.in[i];
+            if (key != kNoKey) atomicAdd(&cnt[(key >> ps.shift) - bin0], 1u);
+        }
+        __syncthreads();
+        if (kHistOnly) {
+            for (int b = tid; b < ps.nbins; b += kPartThreads)
+                if (cnt[b]) atomicAdd(&ps.hist_out[bin0 + b], cnt[b]);
+            __syncthreads();
+            continue;
+        }
+        for (int b = tid; b < ps.nbins; b += kPartThreads) {
+            const uint32_t c = cnt[b];
+            gbase[b] = c ? atomicAdd(&ps.cursor[bin0 + b], c) : 0u;
+            run[b] = 0u;
+        }
+        __syncthreads();
+        for (int64_t sub = lo; sub < hi; sub += kSub) {
+            const int64_t shi = sub + kSub < hi ? sub + kSub : hi;
+            for (int b = tid; b < ps.nbins; b += kPartThreads) cnt[b] = 0u;
+            __syncthreads();
+            // rank of every key inside its bucket for this sub-tile
+            constexpr int kPer = kSub / kPartThreads;
+            uint32_t kv[kPer];
+            uint32_t rk[kPer];
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int64_t i = sub + tid + (int64_t)u * kPartThreads;
+                kv[u] = i < shi ? ps.in[i] : kNoKey;
+                rk[u] = kv[u] != kNoKey ? atomicAdd(&cnt[(kv[u] >> ps.shift) - bin0], 1u) : 0u;
+            }
+            __syncthreads();
+            // exclusive scan of the sub-tile counts (bucket order)
+            if (tid == 0) {
+                uint32_t acc = 0;
+                for (int b = 0; b < ps.nbins; ++b) {
+                    soff[b] = acc;
+                    acc += cnt[b];
+                }
+                nvalid = acc;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                if (kv[u] != kNoKey) {
+                    const uint32_t b = (kv[u] >> ps.shift) - bin0;
+                    const uint32_t pos = soff[b] + rk[u];
+                    skeys[pos] = kv[u];
+                    sbins[pos] = (uint16_t)b;
+                }
+            }
+            __syncthreads();
+            const uint32_t nv = nvalid;
+            for (uint32_t s = tid; s < nv; s += kPartThreads) {
+                const uint32_t b = sbins[s];
+                ps.out[(uint64_t)gbase[b] + run[b] + (s - soff[b])] = skeys[s];
+            }
+            __syncthreads();
+            for (int b = tid; b < ps.nbins; b += kPartThreads) run[b] += cnt[b];
+            __syncthreads();
+        }
+    }
+}
+
+// 5. one workgroup per cell block: LDS histogram, then counts += histogram
+__global__ __launch_bounds__(kAccThreads) void accumulate_kernel(const uint32_t *keys, const uint32_t *offb,
+                                                                 int64_t nblk, int64_t ncells, uint32_t *counts,
+                                                                 const PartHeader *hdr, int chunk_k, int kmax) {
+    __shared__ uint32_t h[kBlockCells];
+    if (chunk_k >= (int)hdr->n_chunks && chunk_k != kmax - 1) return;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const uint32_t lo = offb[blk], hi = offb[blk + 1];
+        if (lo == hi) continue;  // uniform over the block
+        for (int j = threadIdx.x; j < kBlockCells; j += kAccThreads) h[j] = 0u;
+        __syncthreads();
+        for (uint32_t i = lo + threadIdx.x; i < hi; i += kAccThreads) atomicAdd(&h[keys[i] & (kBlockCells - 1)], 1u);
+        __syncthreads();
+        const int64_t c0 = blk * kBlockCells;
+        const int64_t cn = c0 + kBlockCells < ncells ? kBlockCells : ncells - c0;  // multiple of 4
+        uint4 *dst = reinterpret_cast<uint4 *>(counts + c0);
+        for (int64_t j = threadIdx.x; j < cn / 4; j += kAccThreads) {
+            uint4 v = dst[j];
+            v.x += h[4 * j];
+            v.y += h[4 * j + 1];
+            v.z += h[4 * j + 2];
+            v.w += h[4 * j + 3];
+            dst[j] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// guarded instances listed by the key passes
+__global__ __launch_bounds__(256) void part_guarded_kernel(BinParams p) {
+    __shared__ double e_s[UFALCON_MAX_SHELLS + 1];
+    for (int j = threadIdx.x; j <= p.c.nb; j += 256) e_s[j] = p.e[j];
+    __syncthreads();
+    if (p.guard->overflow != 0u) return;
+    const unsigned int seen = p.guard->count;
+    const int64_t m = (int64_t)seen < p.guard_cap ? (int64_t)seen : p.guard_cap;
+    const GuardEntry *ent = reinterpret_cast<const GuardEntry *>(reinterpret_cast<const char *>(p.guard) + kGuardHeader);
+    LaneStats st;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < m; k += (int64_t)gridDim.x * 256) {
+        const int r = bin_instance_exact(p.c.counts, p.npix, p.nside, e_s, p.c.nb, ent[k].dx, ent[k].dy, ent[k].dz);
+        st.inst += r & 1;
+        st.unresolved += (r >> 1) & 1;
+    }
+    flush_stats(p.status, st);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBinBlock) void part_rescue_kernel(BinParams p) {
+    if (p.guard->overflow == 0u) return;
+    __shared__ double e_s[UFALCON_MAX_SHELLS + 1];
+    __shared__ double e2_s[UFALCON_MAX_SHELLS + 1];
+    __shared__ double qx[kBinWaves][kQueue], qy[kBinWaves][kQueue], qz[kBinWaves][kQueue];
+    for (int j = threadIdx.x; j <= p.c.nb; j += kBinBlock) {
+        e_s[j] = p.e[j];
+        e2_s[j] = p.e[j] * p.e[j];
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    const Shared sh = shared_of(p);
+    LaneStats st;
+    Emitter em{};
+    int count = 0;
+    bin_wave_range<T, kRescue>(p.c, sh, e_s, e2_s, (int64_t)blockIdx.x * kBinBlock + w * 64, p.c.n,
+                               (int64_t)gridDim.x * kBinBlock, qx[w], qy[w], qz[w], count, st, em);
+    drain_queue<kRescue>(p.c, sh, e_s, e2_s, qx[w], qy[w], qz[w], count, st, em);
+    flush_stats(p.status, st);
+}
+
+__global__ void part_guard_reset_kernel(GuardList *g) {
+    if (threadIdx.x == 0) {
+        g->count = 0u;
+        g->overflow = 0u;
+    }
+}
+
+template <typename T>
+int launch_partitioned(BinParams p, const PartLayout &L, char *ws, hipStream_t s) {
+    GuardList *guard = reinterpret_cast<GuardList *>(ws + L.off_guard);
+    PartHeader *hdr = reinterpret_cast<PartHeader *>(ws + L.off_hdr);
+    uint32_t *hist1 = reinterpret_cast<uint32_t *>(ws + L.off_hist1);
+    uint32_t *cur1 = reinterpret_cast<uint32_t *>(ws + L.off_cur1);
+    uint32_t *off1 = reinterpret_cast<uint32_t *>(ws + L.off_off1);
+    uint32_t *tiles1 = reinterpret_cast<uint32_t *>(ws + L.off_tiles1);
+    uint32_t *histb = reinterpret_cast<uint32_t *>(ws + L.off_histb);
+    uint32_t *offb = reinterpret_cast<uint32_t *>(ws + L.off_offb);
+    uint32_t *curb = reinterpret_cast<uint32_t *>(ws + L.off_curb);
+    uint32_t *grp = reinterpret_cast<uint32_t *>(ws + L.off_grp);
+    uint32_t *chunk = reinterpret_cast<uint32_t *>(ws + L.off_chunk);
+    uint32_t *keysa = reinterpret_cast<uint32_t *>(ws + L.off_keysa);
+    uint32_t *keysb = reinterpret_cast<uint32_t *>(ws + L.off_keysb);
+    p.guard = guard;
+    p.guard_cap = kPartGuardEntries;
+    const int64_t ncells = (int64_t)p.c.nb * p.npix;
+    const unsigned cus = (unsigned)device_cus();
+
+    hipLaunchKernelGGL(part_guard_reset_kernel, dim3(1), dim3(64), 0, s, guard);
+    hipLaunchKernelGGL((count_groups_kernel<T>), dim3((unsigned)L.ngroups), dim3(256), 0, s, p.c, grp);
+    hipLaunchKernelGGL(plan_chunks_kernel, dim3(1), dim3(1024), 0, s, grp, L.ngroups, L.budget, L.kmax, chunk, hdr);
+
+    KeyParams kp;
+    kp.p = p;
+    kp.keys = keysa;
+    kp.cap = L.cap;
+    kp.hdr = hdr;
+    kp.hist1 = hist1;
+    kp.s1 = L.s1;
+    kp.nb1 = L.nb1;
+    kp.chunk = chunk;
+    kp.kmax = L.kmax;
+    const unsigned key_grid = blocks_for(p.c.n, kBinBlock, cus * 16u);
+
+    PartStep l1{};
+    l1.in = keysa;
+    l1.out = keysb;
+    l1.level = 1;
+    l1.nseg = 1;
+    l1.hdr = hdr;
+    l1.cap = L.cap;
+    l1.shift = L.s1;
+    l1.nbins = L.nb1;
+    l1.cursor = cur1;
+
+    PartStep l2{};
+    l2.in = keysb;
+    l2.out = keysa;
+    l2.level = 2;
+    l2.nseg = L.nb1;
+    l2.seg_off = off1;
+    l2.seg_tiles = tiles1;
+    l2.hdr = hdr;
+    l2.cap = L.cap;
+    l2.shift = kBlockShift;
+    l2.nbins = L.nb2;
+    l2.cursor = curb;
+    l2.hist_out = histb;
+
+    const unsigned part_grid = cus * 4u;
+    for (int k = 0; k < L.kmax; ++k) {
+        hipLaunchKernelGGL(reset_chunk_kernel, dim3(blocks_for(L.nblk, 256, 4096)), dim3(256), 0, s, hdr, hist1,
+                           L.nb1, histb, L.nblk);
+        kp.k = k;
+        hipLaunchKernelGGL((keys_kernel<T>), dim3(key_grid), dim3(kBinBlock), 0, s, kp);
+        hipLaunchKernelGGL(scan_level1_kernel, dim3(1), dim3(1024), 0, s, hist1, L.nb1, off1, cur1, tiles1);
+        hipLaunchKernelGGL((partition_kernel<false>), dim3(part_grid), dim3(kPartThreads), 0, s, l1, k, L.kmax);
+        hipLaunchKernelGGL((partition_kernel<true>), dim3(part_grid), dim3(kPartThreads), 0, s, l2, k, L.kmax);
+        hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, histb, L.nblk, offb, curb);
+        hipLaunchKernelGGL((partition_kernel<false>), dim3(part_grid), dim3(kPartThreads), 0, s, l2, k, L.kmax);
+        hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)std::min<int64_t>(L.nblk, cus * 8)), dim3(kAccThreads), 0,
+                           s, keysa, offb, L.nblk, ncells, p.c.counts, hdr, k, L.kmax);
+    }
+    hipLaunchKernelGGL(part_guarded_kernel, dim3(64), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((part_rescue_kernel<T>), dim3(key_grid), dim3(kBinBlock), 0, s, p);
+    UFX_HIP_CHECK(hipGetLastError());
+    return UFALCON_OK;
+}
+
+// Entry from ufalcon_bin_shells: returns 1 if the partitioned path was taken.
+int try_partitioned(BinParams &p, int dtype, void *workspace, size_t bytes, hipStream_t s, int *rc) {
+    const int64_t ncells = (int64_t)p.c.nb * p.npix;
+    PartLayout L;
+    if (!plan_layout(L, p.c.n, ncells, image_bound(p.c, p.e, p.c.nb), bytes, 0)) return 0;
+    if (L.total > bytes) return 0;
+    char *ws = static_cast<char *>(workspace);
+    *rc = dtype == UFALCON_F32 ? launch_partitioned<float>(p, L, ws, s) : launch_partitioned<double>(p, L, ws, s);
+    return 1;
+}
+
+size_t partitioned_workspace_size(int64_t n, int64_t ncells, int img_bound, int64_t max_keys) {
+    PartLayout L;
+    if (!plan_layout(L, n, ncells, img_bound, 0, max_keys)) return 0;
+    return L.total;
+}
+
+}  // namespace ufx
+
+using namespace ufx;
+
+extern "C" size_t ufalcon_bin_shells_workspace_size_partitioned(int64_t n, int32_t n_rep, int32_t shells_in_range,
+                                                                int64_t nside, int64_t max_keys) {
+    if (n < 0 || n_rep < 0 || n_rep > 64 || shells_in_range < 1 || nside < 1 || nside > UFALCON_MAX_NSIDE ||
+        max_keys < 0)
+        return 0;
+    const int side = 2 * n_rep + 1;
+    const int img = side * side * side;
+    const int64_t floor_keys = 4ll * kGroup * img;  // the smallest budget the chunk plan accepts
+    return partitioned_workspace_size(n, (int64_t)shells_in_range * npix_of(nside), img,
+                                      max_keys > floor_keys ? max_keys : floor_keys);
+}

@@ -13,8 +13,12 @@ int shim_exact_shell(double dx, double dy, double dz, const double *e, int nb) {
     return ufx::exact_shell(dx, dy, dz, e, nb);
 }
 int shim_fast_ring_pixel(int64_t nside, double dx, double dy, double dz, int64_t *pix) {
-    return ufx::fast_ring_pixel(nside, (double)nside, ufx::floor_margin((double)nside), dx, dy, dz, *pix) ? 1 : 0;
+    int32_t p = -1;
+    const int ok = ufx::fast_ring_pixel((int32_t)nside, (double)nside, ufx::floor_margin((double)nside), dx, dy, dz, p) ? 1 : 0;
+    *pix = p;
+    return ok;
 }
+double shim_fast_tt(double dx, double dy) { return ufx::fast_tt(dx, dy); }
 int shim_fast_shell(const double *e2, int nb, double r2, int *clear) {
     int steps = 0;
     while ((2 << steps) <= nb + 1) ++steps;

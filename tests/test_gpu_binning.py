@@ -121,3 +121,42 @@ def test_shell_range_and_accumulation(ufalcon):
     # determinism: a second run gives the identical map
     again = uf.bin_shells(xd, yd, zd, edges, 8, box_L=L, n_rep=1)
     assert torch.equal(full, again)
+
+
+def _both_paths(x, y, z, edges, nside, L, R, **kw):
+    xd, yd, zd = x.to(DEV), y.to(DEV), z.to(DEV)
+    out = {}
+    for method in ("atomic", "partition"):
+        st = uf.new_status(DEV)
+        c = uf.bin_shells(xd, yd, zd, edges, nside, box_L=L, n_rep=R, status=st, method=method, **kw)
+        torch.cuda.synchronize()
+        out[method] = (c.cpu().numpy().astype(np.int64), uf.status_dict(st))
+    return out
+
+
+@pytest.mark.parametrize("nside,R", [(4, 1), (64, 1), (16, 2)])
+def test_partitioned_path_matches_atomic_and_oracle(ufalcon, nside, R):
+    L = 100.0
+    x, y, z = synth.lognormal_box(250001, L, seed=11, ngrid=32, dtype=torch.float32)
+    edges = [7.0, 25.0, 50.0, 80.0, 110.0, 150.0][: 3 + R]
+    res = _both_paths(x, y, z, edges, nside, L, R)
+    ref, rst = obin.bin_shells(x, y, z, (50.0,) * 3, L, R, edges, nside, threads=8)
+    for method, (got, st) in res.items():
+        assert np.array_equal(got, ref), method
+        assert st["n_instances"] == int(ref.sum()), method
+
+
+def test_partitioned_path_several_chunks(ufalcon):
+    # keys per chunk far below the instances: the device plan splits the particles
+    L = 100.0
+    n = 1_500_000
+    x, y, z = synth.lognormal_box(n, L, seed=12, ngrid=32, dtype=torch.float32)
+    edges = [10.0, 30.0, 60.0, 99.0, 140.0]
+    R = 2
+    ws = uf.partition_workspace(n, R, len(edges) - 1, 32, max_keys=3_000_000, device=DEV, cached=False)
+    st = uf.new_status(DEV)
+    got = uf.bin_shells(x.to(DEV), y.to(DEV), z.to(DEV), edges, 32, box_L=L, n_rep=R, status=st, workspace=ws)
+    torch.cuda.synchronize()
+    ref, _ = obin.bin_shells(x, y, z, (50.0,) * 3, L, R, edges, 32, threads=8)
+    assert np.array_equal(got.cpu().numpy().astype(np.int64), ref)
+    assert uf.status_dict(st)["n_instances"] == int(ref.sum())

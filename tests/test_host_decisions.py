@@ -40,6 +40,8 @@ def lib():
                                          ctypes.POINTER(ctypes.c_int)]
         _lib.shim_tt.restype = ctypes.c_double
         _lib.shim_tt.argtypes = [ctypes.c_double, ctypes.c_double]
+        _lib.shim_fast_tt.restype = ctypes.c_double
+        _lib.shim_fast_tt.argtypes = [ctypes.c_double, ctypes.c_double]
     return _lib
 
 
@@ -122,6 +124,29 @@ def test_library_tt_double_double():
                 phi += 2 * mpmath.pi
             want = 2 * phi / mpmath.pi
         assert abs(lib().shim_tt(dx, dy) - float(want)) <= 4e-16 * max(1.0, float(want))
+
+
+def test_library_fast_tt_error_bound():
+    # the fast azimuth must stay far inside the floor margin N 2^-38: require |error| < 4e-15
+    import mpmath
+    rng = random.Random(8)
+    pts = [(rng.gauss(0, 1), rng.gauss(0, 1)) for _ in range(3000)]
+    t8 = math.tan(math.pi / 8)
+    pts += [(1.0, t8 * (1 + k * 1e-16)) for k in range(-3, 4)] + [(1.0, 1.0), (-1.0, 1e-300), (1.0, -1e-300),
+                                                                   (0.0, 1.0), (0.0, -1.0), (-1.0, 0.0)]
+    worst = 0.0
+    for dx, dy in pts:
+        with mpmath.workprec(200):
+            phi = mpmath.atan2(dy, dx)
+            if phi < 0:
+                phi += 2 * mpmath.pi
+            want = float(2 * phi / mpmath.pi)
+        got = lib().shim_fast_tt(dx, dy)
+        err = abs(got - want)
+        if want > 3.999999:  # just below the +x axis: 4.0 and the exact value are both within the guard
+            err = min(err, abs(got - 4.0))
+        worst = max(worst, err)
+    assert worst < 4e-15, worst
 
 
 def test_library_shells_exact_and_fast():
