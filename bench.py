@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--order", choices=["shuffled", "cell"], default="shuffled")
+    ap.add_argument("--method", choices=["partition", "atomic"], default="partition",
+                    help="count accumulation: keyed partition + LDS histograms, or one atomic per instance")
     ap.add_argument("--particles", type=int, default=1 << 27)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 21)
@@ -89,7 +91,10 @@ def main():
     src = uf.SourceSpec("smail", alpha=2.0, beta=1.5, z0=0.3, z_max=0.5)
     counts = torch.empty((B, uf.npix(nside)), dtype=torch.uint32, device=dev)
     status = uf.new_status(dev)
-    ws = uf.bin_shells_workspace(device=dev)
+    if args.method == "partition":
+        ws = uf.partition_workspace(n, R, B, nside, device=dev)
+    else:
+        ws = uf.bin_shells_workspace(device=dev)
     stream = torch.cuda.current_stream(dev)
     ev_bin0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ev_bin1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
@@ -156,12 +161,12 @@ def main():
             "workload": "lognormal lightcone: 2^27 FP32 particles, 1 Gpc/h box replicated to z=0.5 "
                         f"(images {{-{R}..{R}}}^3), 30 shells z=0.1-0.5, Nside 1024 RING, Smail n(z); "
                         "bin + weights + Born kappa + adjoint per step",
-            "particles": n, "shells": B, "nside": nside, "order": args.order,
+            "particles": n, "shells": B, "nside": nside, "order": args.order, "accumulation": args.method,
             "instances_per_step": inst_per_step,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "bin_shells_kernel<float,false>",
+            "kernel": "ufalcon_bin_shells (all kernels of the call)",
             "achieved": bin_bytes / (bin_ms / 1e3) / 1e9,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -232,7 +237,7 @@ def batched_vs_plain(dev):
                           W=W, inv_nbar=inb,
                           kappa=torch.empty((1, uf.npix(nside)), dtype=torch.float32, device=dev)))
     plan = uf.BatchPlan(items, nside, T=1)
-    ws = uf.bin_shells_workspace(device=dev)
+    ws = uf.bin_shells_workspace(device=dev)  # the batch plan accumulates with atomics: compare like with like
 
     def plain():
         for it in items:

@@ -215,10 +215,20 @@ typedef struct ufalcon_batch_item {
 
 typedef struct ufalcon_batch_plan ufalcon_batch_plan;
 
-/* tile: particles per work item (0 = autotuned default); persistent_wgs: workgroups (0 = default). */
+typedef enum ufalcon_accumulation {
+    UFALCON_ACCUMULATE_PARTITIONED = 0, /* keys + radix partition + LDS block histograms, item after item */
+    UFALCON_ACCUMULATE_ATOMIC = 1       /* one persistent launch over (realisation, tile), global atomics */
+} ufalcon_accumulation;
+
+/*
+ * tile: particles per work item of the persistent kernel (0 = default);
+ * persistent_wgs: its workgroups (0 = default); accumulation: ufalcon_accumulation.
+ * The partitioned form allocates one device workspace for the largest realisation
+ * at plan creation (never on the binning calls).
+ */
 int ufalcon_batch_plan_create(const ufalcon_batch_item *items, int32_t n_items, int dtype, int64_t nside,
                               int32_t T, int out_dtype, int64_t tile, int32_t persistent_wgs,
-                              ufalcon_batch_plan **plan);
+                              int32_t accumulation, ufalcon_batch_plan **plan);
 int ufalcon_batch_plan_destroy(ufalcon_batch_plan *plan);
 /* Zero every count map of the plan. */
 int ufalcon_batch_clear(ufalcon_batch_plan *plan, ufalcon_stream_t stream);

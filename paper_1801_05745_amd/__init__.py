@@ -75,7 +75,7 @@ _SIGS = {
     "ufalcon_born_kappa_adjoint_workspace_size": (_SZ, [_I32, _I64, _I32]),
     "ufalcon_born_kappa_adjoint": (ctypes.c_int, [_P, _I32, _I64, _P, _P, ctypes.c_int, _I32, _P, _P, _SZ, _P]),
     "ufalcon_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(BatchItem), _I32, ctypes.c_int, _I64, _I32,
-                                                 ctypes.c_int, _I64, _I32, ctypes.POINTER(_P)]),
+                                                 ctypes.c_int, _I64, _I32, _I32, ctypes.POINTER(_P)]),
     "ufalcon_batch_plan_destroy": (ctypes.c_int, [_P]),
     "ufalcon_batch_clear": (ctypes.c_int, [_P, _P]),
     "ufalcon_bin_shells_batched": (ctypes.c_int, [_P, _P, _P]),
@@ -404,7 +404,7 @@ class BatchPlan:
     and for the Born pass W, inv_nbar, kappa (device).
     """
 
-    def __init__(self, items, nside, T=1, out_dtype=torch.float32, tile=0, persistent_wgs=0):
+    def __init__(self, items, nside, T=1, out_dtype=torch.float32, tile=0, persistent_wgs=0, method="partition"):
         lib = load()
         self._keep = []
         arr = (BatchItem * len(items))()
@@ -431,8 +431,9 @@ class BatchPlan:
             arr[k].kappa = it["kappa"].data_ptr() if it.get("kappa") is not None else None
         self.items = items
         handle = ctypes.c_void_p()
+        acc = {"partition": 0, "atomic": 1}[method]
         _check(lib.ufalcon_batch_plan_create(arr, len(items), dtype, int(nside), int(T), _dtype_code(out_dtype),
-                                             int(tile), int(persistent_wgs), ctypes.byref(handle)),
+                                             int(tile), int(persistent_wgs), acc, ctypes.byref(handle)),
                "ufalcon_batch_plan_create")
         self.handle = handle
 

@@ -276,6 +276,7 @@ int launch_bin_t(const BinParams &p, hipStream_t s) {
 
 namespace ufx {
 int try_partitioned(BinParams &p, int dtype, void *workspace, size_t bytes, hipStream_t s, int *rc);
+size_t partitioned_size_for(const BinParams &p);
 }
 
 using namespace ufx;
@@ -361,6 +362,10 @@ struct ufalcon_batch_plan {
     BornItemDev *d_born = nullptr;
     void *d_work = nullptr;  // guard list + work counters
     size_t work_bytes = 0;
+    int accumulation = UFALCON_ACCUMULATE_PARTITIONED;
+    void *d_part = nullptr;  // partitioned-accumulation workspace shared by the items, in turn
+    size_t part_bytes = 0;
+    std::vector<BinParams> item_params;  // per-item parameters for the partitioned path
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     ufalcon_status *graph_status = nullptr;
@@ -374,13 +379,16 @@ static void free_plan(ufalcon_batch_plan *p) {
     if (p->d_edges) (void)hipFree(p->d_edges);
     if (p->d_born) (void)hipFree(p->d_born);
     if (p->d_work) (void)hipFree(p->d_work);
+    if (p->d_part) (void)hipFree(p->d_part);
     delete p;
 }
 
 extern "C" int ufalcon_batch_plan_create(const ufalcon_batch_item *items, int32_t n_items, int dtype, int64_t nside,
                                          int32_t T, int out_dtype, int64_t tile, int32_t persistent_wgs,
-                                         ufalcon_batch_plan **plan) {
+                                         int32_t accumulation, ufalcon_batch_plan **plan) {
     if (!items || n_items < 1 || !plan) return UFALCON_EINVAL;
+    if (accumulation != UFALCON_ACCUMULATE_PARTITIONED && accumulation != UFALCON_ACCUMULATE_ATOMIC)
+        return UFALCON_EINVAL;
     if (dtype != UFALCON_F32 && dtype != UFALCON_F64) return UFALCON_EINVAL;
     if (out_dtype != UFALCON_F32 && out_dtype != UFALCON_F64) return UFALCON_EINVAL;
     if (T < 0 || T > UFALCON_MAX_BINS) return UFALCON_EINVAL;
@@ -398,6 +406,8 @@ extern "C" int ufalcon_batch_plan_create(const ufalcon_batch_item *items, int32_
     p->tile = tile > 0 ? tile : (int64_t)1 << 18;
     p->tile = (p->tile + 63) / 64 * 64;
     p->wgs = persistent_wgs > 0 ? persistent_wgs : device_cus() * 8;
+    p->accumulation = accumulation;
+    size_t part_need = 0;
     std::vector<double> edges;
     std::vector<BornItemDev> born(n_items);
     int64_t tiles = 0;
@@ -412,6 +422,25 @@ extern "C" int ufalcon_batch_plan_create(const ufalcon_batch_item *items, int32_
             return rc;
         }
         d.c.item = k;
+        if (accumulation == UFALCON_ACCUMULATE_PARTITIONED && d.c.nb > 0 && it.n > 0) {
+            BinParams bp;
+            bp.c = d.c;
+            bp.c.item = 0;
+            for (int j = 0; j <= d.c.nb; ++j) bp.e[j] = e[j];
+            bp.nside = nside;
+            bp.npix = p->npix;
+            bp.eps = floor_margin((double)nside);
+            bp.status = nullptr;
+            bp.guard = nullptr;
+            bp.guard_cap = 0;
+            p->item_params.push_back(bp);
+            const size_t need = partitioned_size_for(bp);
+            if (need == 0) {
+                free_plan(p);
+                return UFALCON_EINVAL;
+            }
+            part_need = std::max(part_need, need);
+        }
         d.edge_off = (int32_t)edges.size();
         for (int j = 0; j <= d.c.nb; ++j) edges.push_back(e[j]);
         d.tile_begin = tiles;
@@ -432,6 +461,13 @@ extern "C" int ufalcon_batch_plan_create(const ufalcon_batch_item *items, int32_
     }
     p->total_tiles = tiles;
     p->work_bytes = kGuardHeader + (size_t)65536 * sizeof(GuardEntry);
+    if (part_need > 0) {
+        p->part_bytes = part_need;
+        if (hipMalloc(&p->d_part, part_need) != hipSuccess) {
+            free_plan(p);
+            return UFALCON_EHIP;
+        }
+    }
     if (hipMalloc(&p->d_items, sizeof(BatchItemDev) * n_items) != hipSuccess ||
         hipMalloc(&p->d_edges, sizeof(double) * edges.size()) != hipSuccess ||
         hipMalloc(&p->d_born, sizeof(BornItemDev) * n_items) != hipSuccess ||
@@ -480,6 +516,17 @@ static BatchParams batch_params(ufalcon_batch_plan *plan, ufalcon_status *status
 extern "C" int ufalcon_bin_shells_batched(ufalcon_batch_plan *plan, ufalcon_status *status, ufalcon_stream_t stream) {
     if (!plan) return UFALCON_EINVAL;
     if (plan->total_tiles == 0) return UFALCON_OK;
+    if (plan->accumulation == UFALCON_ACCUMULATE_PARTITIONED) {
+        // realisations in turn through the partitioned pipeline, sharing one workspace
+        for (BinParams bp : plan->item_params) {
+            bp.status = status;
+            int rc = UFALCON_OK;
+            if (!try_partitioned(bp, plan->dtype, plan->d_part, plan->part_bytes, as_stream(stream), &rc))
+                return UFALCON_EWORKSPACE;
+            if (rc) return rc;
+        }
+        return UFALCON_OK;
+    }
     const BatchParams bp = batch_params(plan, status);
     hipStream_t s = as_stream(stream);
     const unsigned wgs = (unsigned)std::min<int64_t>(plan->wgs, plan->total_tiles);

@@ -273,18 +273,30 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_stage1(AdjParams p) {
     }
 }
 
-// Stage 2: grad_W[t][b] = inv_nbar[b] * sum_blocks S1 - sum_blocks S0, blocks in order.
-__global__ void adjoint_stage2(const double *partial, const double *partial0, int64_t G, int32_t T, int32_t B,
-                               const double *inv_nbar, double *grad_W) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= T * B) return;
+// Stage 2: grad_W[t][b] = inv_nbar[b] * sum_blocks S1 - sum_blocks S0.  One workgroup
+// per (t, b); thread j sums blocks j, j + 256, ... in order, then a fixed-shape tree
+// over the 256 partial sums: the same order on every run.
+__global__ __launch_bounds__(256) void adjoint_stage2(const double *partial, const double *partial0, int64_t G,
+                                                      int32_t T, int32_t B, const double *inv_nbar, double *grad_W) {
+    __shared__ double r1[256], r0[256];
+    const int k = blockIdx.x;
     const int t = k / B, b = k % B;
     double s1 = 0.0, s0 = 0.0;
-    for (int64_t i = 0; i < G; ++i) {
+    for (int64_t i = threadIdx.x; i < G; i += 256) {
         s1 += partial[i * (int64_t)T * B + k];
         s0 += partial0[i * T + t];
     }
-    grad_W[k] = inv_nbar[b] * s1 - s0;
+    r1[threadIdx.x] = s1;
+    r0[threadIdx.x] = s0;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            r1[threadIdx.x] += r1[threadIdx.x + off];
+            r0[threadIdx.x] += r0[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad_W[k] = inv_nbar[b] * r1[0] - r0[0];
 }
 
 int64_t adjoint_blocks(int64_t npix) { return (npix + kAdjPixPerBlock - 1) / kAdjPixPerBlock; }
@@ -396,9 +408,8 @@ extern "C" int ufalcon_born_kappa_adjoint(const uint32_t *counts, int32_t n_shel
     hipStream_t s = as_stream(stream);
     rc = grad_dtype == UFALCON_F32 ? launch_adj<float>(p, s) : launch_adj<double>(p, s);
     if (rc) return rc;
-    const int nthreads = T * n_shells;
-    hipLaunchKernelGGL(adjoint_stage2, dim3((nthreads + 255) / 256), dim3(256), 0, s, p.partial, p.partial0, p.G, T,
-                       n_shells, inv_nbar, grad_W);
+    hipLaunchKernelGGL(adjoint_stage2, dim3(T * n_shells), dim3(256), 0, s, p.partial, p.partial0, p.G, T, n_shells,
+                       inv_nbar, grad_W);
     UFX_HIP_CHECK(hipGetLastError());
     return UFALCON_OK;
 }

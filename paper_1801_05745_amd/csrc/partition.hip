@@ -383,6 +383,7 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(PartStep ps, in
     __shared__ uint32_t soff[kMaxBins];    // sub-tile local offsets
     __shared__ uint32_t skeys[kSub];
     __shared__ uint16_t sbins[kSub];
+    __shared__ uint32_t scan_s[kPartThreads];
     __shared__ uint32_t nvalid;
     if (chunk_k >= (int)ps.hdr->n_chunks && chunk_k != kmax - 1) return;
     const int tid = threadIdx.x;
@@ -426,14 +427,34 @@ __global__ __launch_bounds__(kPartThreads) void partition_kernel(PartStep ps, in
                 rk[u] = kv[u] != kNoKey ? atomicAdd(&cnt[(kv[u] >> ps.shift) - bin0], 1u) : 0u;
             }
             __syncthreads();
-            // exclusive scan of the sub-tile counts (bucket order)
-            if (tid == 0) {
-                uint32_t acc = 0;
-                for (int b = 0; b < ps.nbins; ++b) {
-                    soff[b] = acc;
-                    acc += cnt[b];
+            // exclusive scan of the sub-tile counts in bucket order: each thread sums four
+            // consecutive buckets, then a Hillis-Steele scan over the 256 partial sums
+            {
+                constexpr int kPerT = kMaxBins / kPartThreads;
+                uint32_t loc[kPerT];
+                uint32_t sum = 0;
+#pragma unroll
+                for (int u = 0; u < kPerT; ++u) {
+                    const int b = tid * kPerT + u;
+                    loc[u] = b < ps.nbins ? cnt[b] : 0u;
+                    sum += loc[u];
                 }
-                nvalid = acc;
+                scan_s[tid] = sum;
+                __syncthreads();
+                for (int off = 1; off < kPartThreads; off <<= 1) {
+                    const uint32_t v = tid >= off ? scan_s[tid - off] : 0u;
+                    __syncthreads();
+                    scan_s[tid] += v;
+                    __syncthreads();
+                }
+                uint32_t acc = scan_s[tid] - sum;
+#pragma unroll
+                for (int u = 0; u < kPerT; ++u) {
+                    const int b = tid * kPerT + u;
+                    if (b < ps.nbins) soff[b] = acc;
+                    acc += loc[u];
+                }
+                if (tid == kPartThreads - 1) nvalid = scan_s[tid];
             }
             __syncthreads();
 #pragma unroll
@@ -617,12 +638,24 @@ int launch_partitioned(BinParams p, const PartLayout &L, char *ws, hipStream_t s
 // Entry from ufalcon_bin_shells: returns 1 if the partitioned path was taken.
 int try_partitioned(BinParams &p, int dtype, void *workspace, size_t bytes, hipStream_t s, int *rc) {
     const int64_t ncells = (int64_t)p.c.nb * p.npix;
+    if ((uintptr_t)p.c.counts & 15u) return 0;  // the block update uses 16-byte accesses
     PartLayout L;
     if (!plan_layout(L, p.c.n, ncells, image_bound(p.c, p.e, p.c.nb), bytes, 0)) return 0;
     if (L.total > bytes) return 0;
     char *ws = static_cast<char *>(workspace);
     *rc = dtype == UFALCON_F32 ? launch_partitioned<float>(p, L, ws, s) : launch_partitioned<double>(p, L, ws, s);
     return 1;
+}
+
+// Workspace for one particle set with keys for all its images in one chunk (capped at 32-bit offsets).
+size_t partitioned_size_for(const BinParams &p) {
+    const int img = image_bound(p.c, p.e, p.c.nb);
+    const double want = std::min<double>((double)p.c.n * img, 4.0e9);
+    const int64_t floor_keys = 4ll * kGroup * img;
+    PartLayout L;
+    if (!plan_layout(L, p.c.n, (int64_t)p.c.nb * p.npix, img, 0, std::max<int64_t>((int64_t)want, floor_keys)))
+        return 0;
+    return L.total;
 }
 
 size_t partitioned_workspace_size(int64_t n, int64_t ncells, int img_bound, int64_t max_keys) {

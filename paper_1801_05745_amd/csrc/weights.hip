@@ -180,13 +180,15 @@ __device__ double D_of_z_plain(double z, double om, const Rules *r) {
 // z with D(z) = Dt: Newton in plain FP64, then two dual Newton steps that carry
 // the tangents (dz = -(dD/dtheta - dDt) E at the root).
 __device__ dual z_of_D(dual Dt, dual om, const Rules *r) {
-    double z = Dt.v;
-    for (int it = 0; it < 60; ++it) {
+    // start from the second-order expansion D = z - (3/4) Om z^2 inverted, then Newton;
+    // stop once the step is at the rounding level (quadratic convergence takes ~4 steps)
+    double z = Dt.v * (1.0 + 0.75 * om.v * Dt.v);
+    for (int it = 0; it < 40; ++it) {
         const double a = 1.0 + z;
         const double E = sqrt(om.v * a * a * a + 1.0 - om.v);
         const double dz = (D_of_z_plain(z, om.v, r) - Dt.v) * E;
         z -= dz;
-        if (fabs(dz) <= 1e-17 * (1.0 + z)) break;
+        if (fabs(dz) <= 1e-15 * (1.0 + z)) break;
     }
     dual zd = dconst(z);
     for (int it = 0; it < 2; ++it) {

@@ -31,10 +31,11 @@ def _realisations(sizes, shells, L=200.0, nside=16, seed0=0):
     return items
 
 
-def test_batched_matches_oracle_and_plain(ufalcon):
+@pytest.mark.parametrize("method", ["partition", "atomic"])
+def test_batched_matches_oracle_and_plain(ufalcon, method):
     nside = 16
     items = _realisations([70001, 0, 150000, 33333], [5, 3, 9, 4], nside=nside)
-    plan = uf.BatchPlan(items, nside, T=1, tile=8192)
+    plan = uf.BatchPlan(items, nside, T=1, tile=8192, method=method)
     st = uf.new_status(DEV)
     plan.clear()
     plan.bin(st)
@@ -60,10 +61,11 @@ def test_batched_matches_oracle_and_plain(ufalcon):
     plan.close()
 
 
-def test_graph_replays_match_eager(ufalcon):
+@pytest.mark.parametrize("method", ["partition", "atomic"])
+def test_graph_replays_match_eager(ufalcon, method):
     nside = 8
     items = _realisations([40000, 90001, 5000], [4, 6, 3], nside=nside, seed0=10)
-    plan = uf.BatchPlan(items, nside, T=1, tile=4096, persistent_wgs=64)
+    plan = uf.BatchPlan(items, nside, T=1, tile=4096, persistent_wgs=64, method=method)
     plan.clear()
     plan.bin()
     plan.born()
