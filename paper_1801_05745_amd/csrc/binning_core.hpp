@@ -167,7 +167,7 @@ __device__ __forceinline__ void emit_keys(Emitter &em, const BinCore &c, uint32_
     const int room = kKeyChunk - em.fill;
     if (has && rank < room) {
         em.keys[em.base + em.fill + rank] = key;
-        atomicAdd(&em.hist[key >> em.shift], 1u);
+        if (em.hist) atomicAdd(&em.hist[key >> em.shift], 1u);
     }
     if (n <= room) {
         em.fill += n;
@@ -187,7 +187,7 @@ __device__ __forceinline__ void emit_keys(Emitter &em, const BinCore &c, uint32_
     em.base = b;
     if (has && rank >= room) {
         em.keys[b + (rank - room)] = key;
-        atomicAdd(&em.hist[key >> em.shift], 1u);
+        if (em.hist) atomicAdd(&em.hist[key >> em.shift], 1u);
     }
     em.fill = n - room;
 }
@@ -310,5 +310,15 @@ int fill_core(BinCore &c, double *e_out, const void *x, const void *y, const voi
               int32_t shell_begin, int32_t shell_end, int64_t nside, uint32_t *counts);
 int device_cus();
 int64_t guard_capacity(size_t bytes);
+
+// Workgroups of `kernel` that are resident on the whole device at once: a
+// grid-stride kernel launched with more leaves a second, partly empty round.
+template <typename K>
+unsigned resident_grid(K kernel, int threads, unsigned cus) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return cus * (unsigned)per_cu;
+}
 
 }  // namespace ufx

@@ -31,9 +31,8 @@ namespace ufx {
 constexpr int kBlockShift = 14;                  // cells per accumulation block: 2^14
 constexpr int kBlockCells = 1 << kBlockShift;
 constexpr int kSuper = 32768;                    // keys per partition super-tile
-constexpr int kSub = 8192;                       // keys per LDS-sorted sub-tile
 constexpr int kPartThreads = 256;
-constexpr int kMaxBins = 1024;                   // buckets per partition level
+constexpr int kMaxBins = 512;                    // buckets per partition level
 constexpr int kGroup = 8192;                     // particles per counting group
 constexpr int kAccThreads = 512;
 
@@ -53,8 +52,9 @@ struct PartLayout {
     int kmax;               // chunk iterations launched
     unsigned long long cap; // key slots per buffer (multiple of kKeyChunk)
     unsigned long long budget;  // planned keys per chunk
-    size_t off_guard, off_hdr, off_hist1, off_cur1, off_off1, off_tiles1, off_histb, off_offb, off_curb, off_grp,
-        off_chunk, off_keysa, off_keysb, total;
+    int64_t hist_rows;      // super-tile rows of the per-tile histogram
+    size_t off_guard, off_hdr, off_off1, off_tiles1, off_offb, off_tot, off_thist, off_grp, off_chunk, off_keysa,
+        off_keysb, total;
 };
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -69,7 +69,7 @@ static bool plan_layout(PartLayout &L, int64_t n, int64_t ncells, int img_bound,
     const int blk_bits = bits > kBlockShift ? bits - kBlockShift : 0;  // log2(#blocks), rounded up
     int b2 = blk_bits / 2;
     int b1 = blk_bits - b2;
-    if (b1 > 10 || b2 > 10) return false;
+    if (b1 > 9 || b2 > 9) return false;  // <= 512 buckets per level
     L.s1 = kBlockShift + b2;
     L.nb2 = 1 << b2;
     L.nb1 = (int)((ncells + ((int64_t)1 << L.s1) - 1) >> L.s1);
@@ -78,30 +78,34 @@ static bool plan_layout(PartLayout &L, int64_t n, int64_t ncells, int img_bound,
     size_t o = 0;
     L.off_guard = o; o = align256(o + kGuardHeader + kPartGuardEntries * sizeof(GuardEntry));
     L.off_hdr = o; o = align256(o + sizeof(PartHeader));
-    L.off_hist1 = o; o = align256(o + sizeof(uint32_t) * L.nb1);
-    L.off_cur1 = o; o = align256(o + sizeof(uint32_t) * L.nb1);
     L.off_off1 = o; o = align256(o + sizeof(uint32_t) * (L.nb1 + 1));
     L.off_tiles1 = o; o = align256(o + sizeof(uint32_t) * (L.nb1 + 1));
-    L.off_histb = o; o = align256(o + sizeof(uint32_t) * L.nblk);
     L.off_offb = o; o = align256(o + sizeof(uint32_t) * (L.nblk + 1));
-    L.off_curb = o; o = align256(o + sizeof(uint32_t) * L.nblk);
+    L.off_tot = o; o = align256(o + sizeof(uint32_t) * std::max<int64_t>(L.nb1, L.nblk));
     L.off_grp = o; o = align256(o + sizeof(uint32_t) * L.ngroups);
     const int kmax_cap = 4096;
     L.off_chunk = o; o = align256(o + sizeof(uint32_t) * (kmax_cap + 1));
-    const size_t fixed = o;
+    const size_t fixed_head = o;
     // slack: every wave of the key pass may leave up to one partly filled chunk
     const unsigned long long slack = (unsigned long long)kKeyChunk * (unsigned long long)device_cus() * 16ull * kBinWaves;
+    const int wide = std::max(L.nb1, L.nb2);
     unsigned long long cap;
     if (want_keys > 0) {
-        cap = (unsigned long long)want_keys + slack;
+        cap = (unsigned long long)want_keys + slack + kKeyChunk;
     } else {
-        if (bytes < fixed + 512) return false;
-        cap = (bytes - fixed - 512) / (2 * sizeof(uint32_t));
+        // bytes = head + per-tile histogram (~ cap/kSuper rows) + two key buffers
+        const double per_key = 2.0 * sizeof(uint32_t) + (double)wide * sizeof(uint32_t) / kSuper;
+        const size_t extra = sizeof(uint32_t) * (size_t)wide * (L.nb1 + 2) + 4096;
+        if (bytes < fixed_head + extra) return false;
+        cap = (unsigned long long)((double)(bytes - fixed_head - extra) / per_key);
     }
     if (cap > 0xFFF00000ull) cap = 0xFFF00000ull;  // offsets are 32-bit
     cap = cap / kKeyChunk * kKeyChunk;
     const unsigned long long gmax = (unsigned long long)kGroup * (unsigned long long)img_bound;
     if (cap < slack + 4 * gmax) return false;
+    L.hist_rows = (int64_t)(cap / kSuper) + L.nb1 + 2;
+    L.off_thist = o; o = align256(o + sizeof(uint32_t) * (size_t)wide * L.hist_rows);
+    const size_t fixed = o;
     L.cap = cap;
     L.budget = cap - slack;
     L.off_keysa = fixed;
@@ -210,11 +214,8 @@ __global__ __launch_bounds__(1024) void plan_chunks_kernel(const uint32_t *grp, 
     }
 }
 
-// per-chunk reset of the histograms and the key counter
-__global__ void reset_chunk_kernel(PartHeader *hdr, uint32_t *hist1, int nb1, uint32_t *histb, int64_t nblk) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nblk; i += stride) histb[i] = 0u;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb1; i += stride) hist1[i] = 0u;
+// per-chunk reset of the key counter
+__global__ void reset_chunk_kernel(PartHeader *hdr) {
     if (blockIdx.x == 0 && threadIdx.x == 0) hdr->reserved = 0ull;
 }
 
@@ -224,8 +225,6 @@ struct KeyParams {
     uint32_t *keys;
     unsigned long long cap;
     PartHeader *hdr;
-    uint32_t *hist1;
-    int s1, nb1;
     const uint32_t *chunk;
     int k, kmax;
 };
@@ -236,7 +235,6 @@ __global__ __launch_bounds__(kBinBlock) void keys_kernel(KeyParams kp) {
     __shared__ double e_s[UFALCON_MAX_SHELLS + 1];
     __shared__ double e2_s[UFALCON_MAX_SHELLS + 1];
     __shared__ double qx[kBinWaves][kQueue], qy[kBinWaves][kQueue], qz[kBinWaves][kQueue];
-    __shared__ uint32_t hist[kMaxBins];
     if (kp.k >= (int)kp.hdr->n_chunks && kp.k != kp.kmax - 1) return;  // uniform: empty chunk
     const int64_t p0 = (int64_t)kp.chunk[kp.k] * kGroup;
     int64_t p1 = (int64_t)kp.chunk[kp.k + 1] * kGroup;
@@ -246,7 +244,6 @@ __global__ __launch_bounds__(kBinBlock) void keys_kernel(KeyParams kp) {
         e_s[j] = p.e[j];
         e2_s[j] = p.e[j] * p.e[j];
     }
-    for (int j = threadIdx.x; j < kp.nb1; j += kBinBlock) hist[j] = 0u;
     __syncthreads();
     const int w = threadIdx.x >> 6;
     const Shared sh = shared_of(p);
@@ -255,8 +252,8 @@ __global__ __launch_bounds__(kBinBlock) void keys_kernel(KeyParams kp) {
     em.keys = kp.keys;
     em.reserved = &kp.hdr->reserved;
     em.cap = kp.cap;
-    em.hist = hist;
-    em.shift = kp.s1;
+    em.hist = nullptr;
+    em.shift = 0;
     em.base = 0;
     em.fill = kKeyChunk;
     em.full = false;
@@ -267,93 +264,51 @@ __global__ __launch_bounds__(kBinBlock) void keys_kernel(KeyParams kp) {
     drain_queue<kEmit>(p.c, sh, e_s, e2_s, qx[w], qy[w], qz[w], count, st, em);
     close_emitter(em);
     flush_stats(p.status, st);
-    __syncthreads();
-    for (int j = threadIdx.x; j < kp.nb1; j += kBinBlock)
-        if (hist[j]) atomicAdd(&kp.hist1[j], hist[j]);
 }
 
-// exclusive scan of the level-1 histogram; segment tile prefix for level 2
-__global__ __launch_bounds__(1024) void scan_level1_kernel(const uint32_t *hist1, int nb1, uint32_t *off1,
-                                                           uint32_t *cur1, uint32_t *tiles1) {
-    __shared__ unsigned long long a[1024], b[1024];
-    const int t = threadIdx.x;
-    const unsigned long long h = t < nb1 ? hist1[t] : 0ull;
-    const unsigned long long nt = (h + kSuper - 1) / kSuper;
-    a[t] = h;
-    b[t] = nt;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const unsigned long long x = t >= off ? a[t - off] : 0ull, y = t >= off ? b[t - off] : 0ull;
-        __syncthreads();
-        a[t] += x;
-        b[t] += y;
-        __syncthreads();
-    }
-    if (t < nb1) {
-        off1[t] = (uint32_t)(a[t] - h);
-        cur1[t] = (uint32_t)(a[t] - h);
-        tiles1[t] = (uint32_t)(b[t] - nt);
-    }
-    if (t == nb1 - 1) {
-        off1[nb1] = (uint32_t)a[t];
-        tiles1[nb1] = (uint32_t)b[t];
-    }
-}
-
-// exclusive scan of the block histogram (one workgroup, running carry)
-__global__ __launch_bounds__(1024) void scan_blocks_kernel(const uint32_t *histb, int64_t nblk, uint32_t *offb,
-                                                           uint32_t *curb) {
-    __shared__ unsigned long long a[1024];
-    __shared__ unsigned long long carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int64_t base = 0; base < nblk; base += 1024) {
-        const int64_t i = base + threadIdx.x;
-        const unsigned long long h = i < nblk ? histb[i] : 0ull;
-        a[threadIdx.x] = h;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const unsigned long long x = threadIdx.x >= off ? a[threadIdx.x - off] : 0ull;
-            __syncthreads();
-            a[threadIdx.x] += x;
-            __syncthreads();
-        }
-        if (i < nblk) {
-            offb[i] = (uint32_t)(carry + a[threadIdx.x] - h);
-            curb[i] = (uint32_t)(carry + a[threadIdx.x] - h);
-        }
-        __syncthreads();
-        if (threadIdx.x == 1023) carry += a[1023];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) offb[nblk] = (uint32_t)carry;
-}
-
-// Shared partition step.  Level 1: one segment keys[0, reserved) (with
-// sentinels), bucket = key >> shift.  Level 2: segment s = level-1 bucket s,
-// bucket = (key >> shift) - s * nbins.  The histogram-only variant adds the
-// super-tile counts into hist_out[s * nbins + bucket].
+// Partition steps.  Level 1: one segment keys[0, reserved) (with sentinels),
+// bucket = key >> shift.  Level 2: segment s = level-1 bucket s (keys with
+// key >> s1 == s), bucket = (key >> shift) - s * nbins; the global bucket
+// s * nbins + b is the cell block.  Each segment is cut into super-tiles of
+// kSuper keys; tile_hist writes the per-super-tile bucket counts, bucket_scan
+// turns them into per-super-tile write offsets inside each bucket (and bucket
+// totals), bucket_base scans the totals, and scatter writes every key at
+// base[bucket] + offset[tile][bucket] + its rank inside the super-tile, sorting
+// 4096-key sub-tiles in LDS so that each bucket's keys leave as contiguous runs.
+// No global atomics; ranks come from a wave-level multi-split (one ballot per
+// bucket bit).
 struct PartStep {
     const uint32_t *in;
     uint32_t *out;
     int level;
     int nseg;
-    const uint32_t *seg_off;    // level 2: [nseg + 1]
-    const uint32_t *seg_tiles;  // level 2: [nseg + 1]
+    const uint32_t *seg_off;    // level 2: [nseg + 1] segment starts in `in`
+    const uint32_t *seg_tiles;  // level 2: [nseg + 1] first super-tile of each segment
     const PartHeader *hdr;      // level 1: reserved slots
     unsigned long long cap;
-    int shift, nbins;
-    uint32_t *cursor;           // [nseg * nbins]
-    uint32_t *hist_out;         // histogram-only variant
+    int shift, nbins, nbits;
+    uint32_t *tile_hist;        // [ntiles][nbins]: counts, then offsets inside the bucket
+    uint32_t *bucket_tot;       // [nseg * nbins]
+    uint32_t *bucket_base;      // [nseg * nbins + 1] exclusive scan of bucket_tot
+    int64_t max_tiles;          // rows allocated in tile_hist
 };
+
+__device__ __forceinline__ int64_t step_total(const PartStep &ps) {
+    unsigned long long total = ps.hdr->reserved;
+    return (int64_t)(total > ps.cap ? ps.cap : total);
+}
+
+__device__ __forceinline__ int64_t step_tiles(const PartStep &ps) {
+    if (ps.level == 1) return (step_total(ps) + kSuper - 1) / kSuper;
+    return ps.seg_tiles[ps.nseg];
+}
 
 __device__ __forceinline__ void seg_range(const PartStep &ps, int64_t t, int &seg, int64_t &lo, int64_t &hi) {
     if (ps.level == 1) {
-        unsigned long long total = ps.hdr->reserved;
-        if (total > ps.cap) total = ps.cap;
+        const int64_t total = step_total(ps);
         seg = 0;
         lo = t * kSuper;
-        hi = lo + kSuper < (int64_t)total ? lo + kSuper : (int64_t)total;
+        hi = lo + kSuper < total ? lo + kSuper : total;
         return;
     }
     int a = 0, b = ps.nseg;  // largest s with seg_tiles[s] <= t
@@ -366,115 +321,234 @@ __device__ __forceinline__ void seg_range(const PartStep &ps, int64_t t, int &se
     hi = lo + kSuper < (int64_t)ps.seg_off[a + 1] ? lo + kSuper : (int64_t)ps.seg_off[a + 1];
 }
 
-__device__ __forceinline__ int64_t step_tiles(const PartStep &ps) {
-    if (ps.level == 1) {
-        unsigned long long total = ps.hdr->reserved;
-        if (total > ps.cap) total = ps.cap;
-        return (int64_t)((total + kSuper - 1) / kSuper);
+// Lanes of the wave holding the same bucket as this lane (valid lanes only).
+__device__ __forceinline__ unsigned long long match_bucket(uint32_t b, int nbits, bool valid) {
+    unsigned long long m = __ballot(valid);
+    for (int i = 0; i < nbits; ++i) {
+        const bool bit = (b >> i) & 1u;
+        const unsigned long long v = __ballot(bit);
+        m &= bit ? v : ~v;
     }
-    return ps.seg_tiles[ps.nseg];
+    return m;
 }
 
-template <bool kHistOnly>
-__global__ __launch_bounds__(kPartThreads) void partition_kernel(PartStep ps, int chunk_k, int kmax) {
-    __shared__ uint32_t cnt[kMaxBins];     // super-tile counts, then sub-tile counts
-    __shared__ uint32_t gbase[kMaxBins];   // global start of this super-tile's run per bucket
-    __shared__ uint32_t run[kMaxBins];     // keys written per bucket so far in this super-tile
-    __shared__ uint32_t soff[kMaxBins];    // sub-tile local offsets
-    __shared__ uint32_t skeys[kSub];
-    __shared__ uint16_t sbins[kSub];
-    __shared__ uint32_t scan_s[kPartThreads];
-    __shared__ uint32_t nvalid;
+// per-super-tile bucket counts (wave-private LDS histograms, summed); 16 loads
+// in flight per thread
+constexpr int kHistUnroll = 16;
+__global__ __launch_bounds__(kPartThreads) void tile_hist_kernel(PartStep ps, int chunk_k, int kmax) {
+    constexpr int kW = kPartThreads / 64;
+    __shared__ uint32_t wh[kW][kMaxBins];
     if (chunk_k >= (int)ps.hdr->n_chunks && chunk_k != kmax - 1) return;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, w = tid >> 6;
     const int64_t ntiles = step_tiles(ps);
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         int seg;
         int64_t lo, hi;
         seg_range(ps, t, seg, lo, hi);
         const uint32_t bin0 = (uint32_t)seg * (uint32_t)ps.nbins;
-        for (int b = tid; b < ps.nbins; b += kPartThreads) cnt[b] = 0u;
+        for (int b = tid; b < ps.nbins; b += kPartThreads)
+            for (int k = 0; k < kW; ++k) wh[k][b] = 0u;
         __syncthreads();
-        for (int64_t i = lo + tid; i < hi; i += kPartThreads) {
-            const uint32_t key = ps.in[i];
-            if (key != kNoKey) atomicAdd(&cnt[(key >> ps.shift) - bin0], 1u);
+        for (int64_t base = lo; base < hi; base += (int64_t)kPartThreads * kHistUnroll) {
+            uint32_t kk[kHistUnroll];
+#pragma unroll
+            for (int u = 0; u < kHistUnroll; ++u) {
+                const int64_t i = base + (int64_t)u * kPartThreads + tid;
+                kk[u] = i < hi ? ps.in[i] : kNoKey;
+            }
+#pragma unroll
+            for (int u = 0; u < kHistUnroll; ++u)
+                if (kk[u] != kNoKey) atomicAdd(&wh[w][(kk[u] >> ps.shift) - bin0], 1u);
         }
         __syncthreads();
-        if (kHistOnly) {
-            for (int b = tid; b < ps.nbins; b += kPartThreads)
-                if (cnt[b]) atomicAdd(&ps.hist_out[bin0 + b], cnt[b]);
-            __syncthreads();
-            continue;
-        }
+        uint32_t *row = ps.tile_hist + t * (int64_t)ps.nbins;
         for (int b = tid; b < ps.nbins; b += kPartThreads) {
-            const uint32_t c = cnt[b];
-            gbase[b] = c ? atomicAdd(&ps.cursor[bin0 + b], c) : 0u;
-            run[b] = 0u;
+            uint32_t c = 0;
+            for (int k = 0; k < kW; ++k) c += wh[k][b];
+            row[b] = c;
         }
         __syncthreads();
+    }
+}
+
+// one workgroup per global bucket g = seg * nbins + b: exclusive offsets of the
+// bucket's keys over the super-tiles of its segment, and the bucket total
+__global__ __launch_bounds__(256) void bucket_scan_kernel(PartStep ps, int chunk_k, int kmax) {
+    __shared__ uint32_t wsum[4];
+    if (chunk_k >= (int)ps.hdr->n_chunks && chunk_k != kmax - 1) return;
+    const int64_t g = blockIdx.x;
+    const int seg = (int)(g / ps.nbins), b = (int)(g % ps.nbins);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t t0, t1;
+    if (ps.level == 1) {
+        t0 = 0;
+        t1 = step_tiles(ps);
+    } else {
+        t0 = ps.seg_tiles[seg];
+        t1 = ps.seg_tiles[seg + 1];
+    }
+    uint32_t carry = 0;
+    for (int64_t base = t0; base < t1; base += 256) {
+        const int64_t t = base + threadIdx.x;
+        const uint32_t v = t < t1 ? ps.tile_hist[t * (int64_t)ps.nbins + b] : 0u;
+        uint32_t x = v;  // inclusive scan inside the wave
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        uint32_t before = carry;
+        for (int k = 0; k < w; ++k) before += wsum[k];
+        if (t < t1) ps.tile_hist[t * (int64_t)ps.nbins + b] = before + x - v;
+        carry += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ps.bucket_tot[g] = carry;
+}
+
+// exclusive scan of the bucket totals (one workgroup, running carry); for level 1
+// also the first super-tile of every level-2 segment
+__global__ __launch_bounds__(1024) void bucket_base_kernel(const uint32_t *tot, int64_t nbkt, uint32_t *base,
+                                                           uint32_t *tiles, const PartHeader *hdr, int chunk_k,
+                                                           int kmax) {
+    __shared__ unsigned long long a[1024], bt[1024];
+    __shared__ unsigned long long carry, carry_t;
+    if (chunk_k >= (int)hdr->n_chunks && chunk_k != kmax - 1) return;
+    if (threadIdx.x == 0) {
+        carry = 0;
+        carry_t = 0;
+    }
+    __syncthreads();
+    for (int64_t s = 0; s < nbkt; s += 1024) {
+        const int64_t i = s + threadIdx.x;
+        const unsigned long long h = i < nbkt ? tot[i] : 0ull;
+        const unsigned long long nt = (h + kSuper - 1) / kSuper;
+        a[threadIdx.x] = h;
+        bt[threadIdx.x] = nt;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const unsigned long long x = threadIdx.x >= off ? a[threadIdx.x - off] : 0ull;
+            const unsigned long long y = threadIdx.x >= off ? bt[threadIdx.x - off] : 0ull;
+            __syncthreads();
+            a[threadIdx.x] += x;
+            bt[threadIdx.x] += y;
+            __syncthreads();
+        }
+        if (i < nbkt) {
+            base[i] = (uint32_t)(carry + a[threadIdx.x] - h);
+            if (tiles) tiles[i] = (uint32_t)(carry_t + bt[threadIdx.x] - nt);
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) {
+            carry += a[1023];
+            carry_t += bt[1023];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        base[nbkt] = (uint32_t)carry;
+        if (tiles) tiles[nbkt] = (uint32_t)carry_t;
+    }
+}
+
+// scatter: per 8192-key sub-tile, wave-level multi-split ranks plus one LDS
+// atomic per (wave, bucket) group, a bucket-order scan, an LDS sort, then
+// contiguous runs written at base + tile offset + running count.  Key order
+// inside a bucket is irrelevant to the counts, so the nondeterministic order of
+// the group atomics is harmless.
+constexpr int kScatThreads = 512;
+constexpr int kSub = 8192;
+__global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, int chunk_k, int kmax) {
+    constexpr int kW = kScatThreads / 64;
+    constexpr int kPer = kSub / kScatThreads;  // keys per thread per sub-tile
+    static_assert(kMaxBins <= kScatThreads, "one bucket per thread in the scan");
+    static_assert(kSub <= 65536 && kMaxBins <= 65536, "bucket and rank packed in 16-bit halves");
+    __shared__ uint32_t cnt[kMaxBins];       // keys per bucket in the sub-tile
+    __shared__ uint32_t gbase[kMaxBins];     // global start of this super-tile's run per bucket
+    __shared__ uint32_t run[kMaxBins];       // keys of the bucket written by earlier sub-tiles
+    __shared__ uint32_t soff[kMaxBins + 1];  // bucket start inside the sorted sub-tile
+    __shared__ uint32_t skeys[kSub];
+    __shared__ uint32_t wsum[kW];
+    if (chunk_k >= (int)ps.hdr->n_chunks && chunk_k != kmax - 1) return;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int64_t ntiles = step_tiles(ps);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int seg;
+        int64_t lo, hi;
+        seg_range(ps, t, seg, lo, hi);
+        const uint32_t bin0 = (uint32_t)seg * (uint32_t)ps.nbins;
+        if (tid < ps.nbins) {
+            gbase[tid] = ps.bucket_base[bin0 + tid] + ps.tile_hist[t * (int64_t)ps.nbins + tid];
+            run[tid] = 0u;
+        }
         for (int64_t sub = lo; sub < hi; sub += kSub) {
             const int64_t shi = sub + kSub < hi ? sub + kSub : hi;
-            for (int b = tid; b < ps.nbins; b += kPartThreads) cnt[b] = 0u;
-            __syncthreads();
-            // rank of every key inside its bucket for this sub-tile
-            constexpr int kPer = kSub / kPartThreads;
-            uint32_t kv[kPer];
+            if (tid < ps.nbins) cnt[tid] = 0u;
+            __syncthreads();                                                  // 1
+            // rank pass; rk = bucket << 16 | rank inside the bucket, ~0 for no key.
+            // Loads are unconditional at clamped indices so that all of them are in
+            // flight together; a wave with no keys in the sub-tile skips them.
+            const int64_t w0 = sub + (int64_t)w * kPer * 64;  // wave w: keys [w0, w0 + kPer 64)
+            const int rem = (int)(shi - w0 < 0 ? 0 : (shi - w0 < kPer * 64 ? shi - w0 : kPer * 64));
+            const uint32_t *src = ps.in + w0;
             uint32_t rk[kPer];
+            if (rem > 0) {
+                uint32_t kv[kPer];
 #pragma unroll
-            for (int u = 0; u < kPer; ++u) {
-                const int64_t i = sub + tid + (int64_t)u * kPartThreads;
-                kv[u] = i < shi ? ps.in[i] : kNoKey;
-                rk[u] = kv[u] != kNoKey ? atomicAdd(&cnt[(kv[u] >> ps.shift) - bin0], 1u) : 0u;
-            }
-            __syncthreads();
-            // exclusive scan of the sub-tile counts in bucket order: each thread sums four
-            // consecutive buckets, then a Hillis-Steele scan over the 256 partial sums
-            {
-                constexpr int kPerT = kMaxBins / kPartThreads;
-                uint32_t loc[kPerT];
-                uint32_t sum = 0;
+                for (int u = 0; u < kPer; ++u) kv[u] = src[min(u * 64 + lane, rem - 1)];
 #pragma unroll
-                for (int u = 0; u < kPerT; ++u) {
-                    const int b = tid * kPerT + u;
-                    loc[u] = b < ps.nbins ? cnt[b] : 0u;
-                    sum += loc[u];
-                }
-                scan_s[tid] = sum;
-                __syncthreads();
-                for (int off = 1; off < kPartThreads; off <<= 1) {
-                    const uint32_t v = tid >= off ? scan_s[tid - off] : 0u;
-                    __syncthreads();
-                    scan_s[tid] += v;
-                    __syncthreads();
-                }
-                uint32_t acc = scan_s[tid] - sum;
-#pragma unroll
-                for (int u = 0; u < kPerT; ++u) {
-                    const int b = tid * kPerT + u;
-                    if (b < ps.nbins) soff[b] = acc;
-                    acc += loc[u];
-                }
-                if (tid == kPartThreads - 1) nvalid = scan_s[tid];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int u = 0; u < kPer; ++u) {
-                if (kv[u] != kNoKey) {
-                    const uint32_t b = (kv[u] >> ps.shift) - bin0;
-                    const uint32_t pos = soff[b] + rk[u];
-                    skeys[pos] = kv[u];
-                    sbins[pos] = (uint16_t)b;
+                for (int u = 0; u < kPer; ++u) {
+                    const bool valid = u * 64 + lane < rem && kv[u] != kNoKey;
+                    const uint32_t bkt = valid ? (kv[u] >> ps.shift) - bin0 : 0u;
+                    const unsigned long long m = match_bucket(bkt, ps.nbits, valid);
+                    const uint32_t before = (uint32_t)__popcll(m & below);
+                    const int leader = valid ? __ffsll((long long)m) - 1 : 0;
+                    uint32_t gb = 0u;
+                    if (valid && before == 0u) gb = atomicAdd(&cnt[bkt], (uint32_t)__popcll(m));
+                    gb = __shfl(gb, leader, 64);
+                    rk[u] = valid ? bkt << 16 | (gb + before) : ~0u;
                 }
             }
-            __syncthreads();
-            const uint32_t nv = nvalid;
-            for (uint32_t s = tid; s < nv; s += kPartThreads) {
-                const uint32_t b = sbins[s];
-                ps.out[(uint64_t)gbase[b] + run[b] + (s - soff[b])] = skeys[s];
+            __syncthreads();                                                  // 2
+            const uint32_t c = tid < ps.nbins ? cnt[tid] : 0u;
+            uint32_t x = c;  // inclusive scan within the wave, bucket order = thread order
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(x, off, 64);
+                if (lane >= off) x += y;
             }
-            __syncthreads();
-            for (int b = tid; b < ps.nbins; b += kPartThreads) run[b] += cnt[b];
-            __syncthreads();
+            if (lane == 63) wsum[w] = x;
+            __syncthreads();                                                  // 3
+            uint32_t acc = x - c;
+            for (int k = 0; k < w; ++k) acc += wsum[k];
+            if (tid < ps.nbins) soff[tid] = acc;
+            if (tid == kScatThreads - 1) soff[ps.nbins] = acc + c;
+            __syncthreads();                                                  // 4
+            // the keys again (recently read, so served from cache), placed in bucket order
+            if (rem > 0) {
+                uint32_t kv[kPer];
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) kv[u] = src[min(u * 64 + lane, rem - 1)];
+#pragma unroll
+                for (int u = 0; u < kPer; ++u)
+                    if (rk[u] != ~0u) skeys[soff[rk[u] >> 16] + (rk[u] & 0xFFFFu)] = kv[u];
+            }
+            __syncthreads();                                                  // 5
+            const uint32_t nv = soff[ps.nbins];
+            if (nv > 0) {
+                // unrolled, reads at clamped indices, so that the LDS reads overlap
+#pragma unroll 8
+                for (int j = 0; j < kPer; ++j) {
+                    const uint32_t sidx = (uint32_t)(j * kScatThreads + tid);
+                    const uint32_t key = skeys[min(sidx, nv - 1u)];
+                    const uint32_t b = (key >> ps.shift) - bin0;
+                    const uint32_t pos = gbase[b] + run[b] + (sidx - soff[b]);
+                    if (sidx < nv) ps.out[pos] = key;
+                }
+            }
+            __syncthreads();                                                  // 6
+            if (tid < ps.nbins) run[tid] += soff[tid + 1] - soff[tid];
         }
     }
 }
@@ -554,17 +628,24 @@ __global__ void part_guard_reset_kernel(GuardList *g) {
     }
 }
 
+// The whole set fits one chunk: no counting pass, chunk 0 = all groups.
+__global__ void single_chunk_kernel(uint32_t *chunk, int64_t ngroups, PartHeader *hdr) {
+    if (threadIdx.x == 0) {
+        chunk[0] = 0u;
+        chunk[1] = (uint32_t)ngroups;
+        hdr->n_chunks = 1u;
+    }
+}
+
 template <typename T>
-int launch_partitioned(BinParams p, const PartLayout &L, char *ws, hipStream_t s) {
+int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws, hipStream_t s) {
     GuardList *guard = reinterpret_cast<GuardList *>(ws + L.off_guard);
     PartHeader *hdr = reinterpret_cast<PartHeader *>(ws + L.off_hdr);
-    uint32_t *hist1 = reinterpret_cast<uint32_t *>(ws + L.off_hist1);
-    uint32_t *cur1 = reinterpret_cast<uint32_t *>(ws + L.off_cur1);
     uint32_t *off1 = reinterpret_cast<uint32_t *>(ws + L.off_off1);
     uint32_t *tiles1 = reinterpret_cast<uint32_t *>(ws + L.off_tiles1);
-    uint32_t *histb = reinterpret_cast<uint32_t *>(ws + L.off_histb);
     uint32_t *offb = reinterpret_cast<uint32_t *>(ws + L.off_offb);
-    uint32_t *curb = reinterpret_cast<uint32_t *>(ws + L.off_curb);
+    uint32_t *tot = reinterpret_cast<uint32_t *>(ws + L.off_tot);
+    uint32_t *thist = reinterpret_cast<uint32_t *>(ws + L.off_thist);
     uint32_t *grp = reinterpret_cast<uint32_t *>(ws + L.off_grp);
     uint32_t *chunk = reinterpret_cast<uint32_t *>(ws + L.off_chunk);
     uint32_t *keysa = reinterpret_cast<uint32_t *>(ws + L.off_keysa);
@@ -575,21 +656,29 @@ int launch_partitioned(BinParams p, const PartLayout &L, char *ws, hipStream_t s
     const unsigned cus = (unsigned)device_cus();
 
     hipLaunchKernelGGL(part_guard_reset_kernel, dim3(1), dim3(64), 0, s, guard);
-    hipLaunchKernelGGL((count_groups_kernel<T>), dim3((unsigned)L.ngroups), dim3(256), 0, s, p.c, grp);
-    hipLaunchKernelGGL(plan_chunks_kernel, dim3(1), dim3(1024), 0, s, grp, L.ngroups, L.budget, L.kmax, chunk, hdr);
+    if (L.kmax == 1 && (double)p.c.n * (double)img_bound <= (double)L.budget) {
+        // every instance of the set fits the key buffer (positions in the box)
+        hipLaunchKernelGGL(single_chunk_kernel, dim3(1), dim3(64), 0, s, chunk, L.ngroups, hdr);
+    } else {
+        hipLaunchKernelGGL((count_groups_kernel<T>), dim3((unsigned)L.ngroups), dim3(256), 0, s, p.c, grp);
+        hipLaunchKernelGGL(plan_chunks_kernel, dim3(1), dim3(1024), 0, s, grp, L.ngroups, L.budget, L.kmax, chunk,
+                           hdr);
+    }
 
     KeyParams kp;
     kp.p = p;
     kp.keys = keysa;
     kp.cap = L.cap;
     kp.hdr = hdr;
-    kp.hist1 = hist1;
-    kp.s1 = L.s1;
-    kp.nb1 = L.nb1;
     kp.chunk = chunk;
     kp.kmax = L.kmax;
     const unsigned key_grid = blocks_for(p.c.n, kBinBlock, cus * 16u);
 
+    auto bits_of = [](int nb) {
+        int b = 0;
+        while ((1 << b) < nb) ++b;
+        return b;
+    };
     PartStep l1{};
     l1.in = keysa;
     l1.out = keysb;
@@ -599,33 +688,42 @@ int launch_partitioned(BinParams p, const PartLayout &L, char *ws, hipStream_t s
     l1.cap = L.cap;
     l1.shift = L.s1;
     l1.nbins = L.nb1;
-    l1.cursor = cur1;
+    l1.nbits = bits_of(L.nb1);
+    l1.tile_hist = thist;
+    l1.bucket_tot = tot;
+    l1.bucket_base = off1;
+    l1.max_tiles = L.hist_rows;
 
-    PartStep l2{};
+    PartStep l2 = l1;
     l2.in = keysb;
     l2.out = keysa;
     l2.level = 2;
     l2.nseg = L.nb1;
     l2.seg_off = off1;
     l2.seg_tiles = tiles1;
-    l2.hdr = hdr;
-    l2.cap = L.cap;
     l2.shift = kBlockShift;
     l2.nbins = L.nb2;
-    l2.cursor = curb;
-    l2.hist_out = histb;
+    l2.nbits = bits_of(L.nb2);
+    l2.bucket_base = offb;
 
-    const unsigned part_grid = cus * 4u;
+    const unsigned hist_grid = resident_grid(tile_hist_kernel, kPartThreads, cus);
+    const unsigned scat_grid = resident_grid(scatter_kernel, kScatThreads, cus);
     for (int k = 0; k < L.kmax; ++k) {
-        hipLaunchKernelGGL(reset_chunk_kernel, dim3(blocks_for(L.nblk, 256, 4096)), dim3(256), 0, s, hdr, hist1,
-                           L.nb1, histb, L.nblk);
+        hipLaunchKernelGGL(reset_chunk_kernel, dim3(1), dim3(64), 0, s, hdr);
         kp.k = k;
         hipLaunchKernelGGL((keys_kernel<T>), dim3(key_grid), dim3(kBinBlock), 0, s, kp);
-        hipLaunchKernelGGL(scan_level1_kernel, dim3(1), dim3(1024), 0, s, hist1, L.nb1, off1, cur1, tiles1);
-        hipLaunchKernelGGL((partition_kernel<false>), dim3(part_grid), dim3(kPartThreads), 0, s, l1, k, L.kmax);
-        hipLaunchKernelGGL((partition_kernel<true>), dim3(part_grid), dim3(kPartThreads), 0, s, l2, k, L.kmax);
-        hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, histb, L.nblk, offb, curb);
-        hipLaunchKernelGGL((partition_kernel<false>), dim3(part_grid), dim3(kPartThreads), 0, s, l2, k, L.kmax);
+        // level 1: by key >> s1
+        hipLaunchKernelGGL(tile_hist_kernel, dim3(hist_grid), dim3(kPartThreads), 0, s, l1, k, L.kmax);
+        hipLaunchKernelGGL(bucket_scan_kernel, dim3((unsigned)L.nb1), dim3(256), 0, s, l1, k, L.kmax);
+        hipLaunchKernelGGL(bucket_base_kernel, dim3(1), dim3(1024), 0, s, tot, (int64_t)L.nb1, off1, tiles1, hdr, k,
+                           L.kmax);
+        hipLaunchKernelGGL(scatter_kernel, dim3(scat_grid), dim3(kScatThreads), 0, s, l1, k, L.kmax);
+        // level 2: by cell block inside each level-1 bucket
+        hipLaunchKernelGGL(tile_hist_kernel, dim3(hist_grid), dim3(kPartThreads), 0, s, l2, k, L.kmax);
+        hipLaunchKernelGGL(bucket_scan_kernel, dim3((unsigned)L.nblk), dim3(256), 0, s, l2, k, L.kmax);
+        hipLaunchKernelGGL(bucket_base_kernel, dim3(1), dim3(1024), 0, s, tot, L.nblk, offb, (uint32_t *)nullptr, hdr,
+                           k, L.kmax);
+        hipLaunchKernelGGL(scatter_kernel, dim3(scat_grid), dim3(kScatThreads), 0, s, l2, k, L.kmax);
         hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)std::min<int64_t>(L.nblk, cus * 8)), dim3(kAccThreads), 0,
                            s, keysa, offb, L.nblk, ncells, p.c.counts, hdr, k, L.kmax);
     }
@@ -640,10 +738,12 @@ int try_partitioned(BinParams &p, int dtype, void *workspace, size_t bytes, hipS
     const int64_t ncells = (int64_t)p.c.nb * p.npix;
     if ((uintptr_t)p.c.counts & 15u) return 0;  // the block update uses 16-byte accesses
     PartLayout L;
-    if (!plan_layout(L, p.c.n, ncells, image_bound(p.c, p.e, p.c.nb), bytes, 0)) return 0;
+    const int img = image_bound(p.c, p.e, p.c.nb);
+    if (!plan_layout(L, p.c.n, ncells, img, bytes, 0)) return 0;
     if (L.total > bytes) return 0;
     char *ws = static_cast<char *>(workspace);
-    *rc = dtype == UFALCON_F32 ? launch_partitioned<float>(p, L, ws, s) : launch_partitioned<double>(p, L, ws, s);
+    *rc = dtype == UFALCON_F32 ? launch_partitioned<float>(p, L, img, ws, s)
+                               : launch_partitioned<double>(p, L, img, ws, s);
     return 1;
 }
 
