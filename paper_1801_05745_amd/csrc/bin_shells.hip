@@ -263,7 +263,8 @@ int64_t guard_capacity(size_t bytes) {
 
 template <typename T>
 int launch_bin_t(const BinParams &p, hipStream_t s) {
-    const unsigned grid = blocks_for(p.c.n, kBinBlock, (unsigned)device_cus() * 16u);
+    const unsigned grid =
+        blocks_for(p.c.n, kBinBlock, resident_grid(bin_shells_kernel<T, kAtomic>, kBinBlock, (unsigned)device_cus()));
     hipLaunchKernelGGL(guard_reset_kernel, dim3(1), dim3(64), 0, s, p.guard);
     hipLaunchKernelGGL((bin_shells_kernel<T, kAtomic>), dim3(grid), dim3(kBinBlock), 0, s, p);
     hipLaunchKernelGGL(bin_guarded_kernel, dim3(64), dim3(256), 0, s, p);

@@ -230,7 +230,7 @@ struct KeyParams {
 };
 
 template <typename T>
-__global__ __launch_bounds__(kBinBlock) void keys_kernel(KeyParams kp) {
+__global__ __launch_bounds__(kBinBlock, 5) void keys_kernel(KeyParams kp) {
     const BinParams &p = kp.p;
     __shared__ double e_s[UFALCON_MAX_SHELLS + 1];
     __shared__ double e2_s[UFALCON_MAX_SHELLS + 1];
@@ -493,9 +493,8 @@ __global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, i
             const int64_t w0 = sub + (int64_t)w * kPer * 64;  // wave w: keys [w0, w0 + kPer 64)
             const int rem = (int)(shi - w0 < 0 ? 0 : (shi - w0 < kPer * 64 ? shi - w0 : kPer * 64));
             const uint32_t *src = ps.in + w0;
-            uint32_t rk[kPer];
+            uint32_t kv[kPer], rk[kPer];
             if (rem > 0) {
-                uint32_t kv[kPer];
 #pragma unroll
                 for (int u = 0; u < kPer; ++u) kv[u] = src[min(u * 64 + lane, rem - 1)];
 #pragma unroll
@@ -525,11 +524,8 @@ __global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, i
             if (tid < ps.nbins) soff[tid] = acc;
             if (tid == kScatThreads - 1) soff[ps.nbins] = acc + c;
             __syncthreads();                                                  // 4
-            // the keys again (recently read, so served from cache), placed in bucket order
+            // the keys placed in bucket order
             if (rem > 0) {
-                uint32_t kv[kPer];
-#pragma unroll
-                for (int u = 0; u < kPer; ++u) kv[u] = src[min(u * 64 + lane, rem - 1)];
 #pragma unroll
                 for (int u = 0; u < kPer; ++u)
                     if (rk[u] != ~0u) skeys[soff[rk[u] >> 16] + (rk[u] & 0xFFFFu)] = kv[u];
@@ -672,7 +668,8 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
     kp.hdr = hdr;
     kp.chunk = chunk;
     kp.kmax = L.kmax;
-    const unsigned key_grid = blocks_for(p.c.n, kBinBlock, cus * 16u);
+    // one resident round: the particle loop is grid-strided and evenly loaded
+    const unsigned key_grid = blocks_for(p.c.n, kBinBlock, resident_grid(keys_kernel<T>, kBinBlock, cus));
 
     auto bits_of = [](int nb) {
         int b = 0;

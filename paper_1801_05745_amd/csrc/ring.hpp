@@ -66,40 +66,52 @@ UFX_FN double fast_tt(double dx, double dy) {
 
 // Returns true and the pixel when every decision is clear of its boundary.
 // Pixel arithmetic is 32-bit: 12 N^2 < 2^31 for N <= 8192.
+//
+// Written without data-dependent branches: a wave holds belt and cap directions
+// together, so both formulas are evaluated and selected per lane.  Every lane
+// computes exactly the FP64 expressions of its own region (one division serves
+// both: z = dz / r in the belt, 1 - |z| = rho2 / (r (r + |dz|)) in the caps), so
+// the values are those of a branching evaluation.
 UFX_FN bool fast_ring_pixel(int32_t N, double Nd, double eps, double dx, double dy, double dz, int32_t &pix) {
     const double rho2 = dx * dx + dy * dy;
     const double dz2 = dz * dz;
     const double a5 = 5.0 * dz2, a4 = 4.0 * rho2;
-    if (fabs(a5 - a4) <= kRelGuard * (a5 + a4)) return false;   // near |z| = 2/3 (or d = 0)
+    bool ok = fabs(a5 - a4) > kRelGuard * (a5 + a4);  // false near |z| = 2/3 (or d = 0)
+    const bool belt = a5 < a4;
     const double r = sqrt(rho2 + dz2);
     const double tt = fast_tt(dx, dy);
-    if (a5 < a4) {
-        const double z = dz / r;
-        const double t1 = Nd * (0.5 + tt);
-        const double t2 = 0.75 * Nd * z;
-        double fa, fb;
-        if (!clear_of_integer(t1 - t2, eps, fa) || !clear_of_integer(t1 + t2, eps, fb)) return false;
-        const int32_t jp = (int32_t)fa, jm = (int32_t)fb;
-        const int32_t k = N + 1 + jp - jm;                              // ring below z = 2/3, 1 .. 2N+1
-        int32_t q = (jp + jm - N + ((k & 1) ^ 1) + 1) >> 1;             // 0 .. 4N+1
-        q = q >= 4 * N ? q - 4 * N : q;
-        pix = 2 * N * (N - 1) + 4 * N * (k - 1) + q;
-        return true;
-    }
-    double ftt;
-    if (!clear_of_integer(tt, eps, ftt)) return false;
+    const double num = belt ? dz : rho2;
+    const double den0 = belt ? r : r * (r + fabs(dz));
+    const double den = ok ? den0 : 1.0;              // keeps rejected lanes finite
+    const double qd = num / den;                     // z (belt) or 1 - |z| (caps)
+    // belt arguments
+    const double t1 = Nd * (0.5 + tt);
+    const double t2 = 0.75 * Nd * qd;
+    // cap arguments
+    const double ftt = floor(tt);
     const double u = tt - ftt;
-    const double one_minus = rho2 / (r * (r + fabs(dz)));
-    const double sig = Nd * sqrt(3.0 * one_minus);
-    double fp, fm;
-    if (!clear_of_integer(u * sig, eps, fp) || !clear_of_integer((1.0 - u) * sig, eps, fm)) return false;
-    const int32_t k = (int32_t)fp + (int32_t)fm + 1;                    // ring from the pole, 1 .. N
+    const double sig = Nd * sqrt(3.0 * (belt ? 0.0 : qd));
+    const double va = belt ? t1 - t2 : u * sig;
+    const double vb = belt ? t1 + t2 : (1.0 - u) * sig;
+    double fa, fb;
+    ok = ok & clear_of_integer(va, eps, fa);
+    ok = ok & clear_of_integer(vb, eps, fb);
+    ok = ok & (belt | ((tt - ftt) > eps && (ftt + 1.0 - tt) > eps));
+    const int32_t ia = (int32_t)(ok ? fa : 0.0), ib = (int32_t)(ok ? fb : 0.0);
+    // belt: jp = ia, jm = ib, ring k below z = 2/3 in 1 .. 2N+1
+    const int32_t kb = N + 1 + ia - ib;
+    int32_t qb = (ia + ib - N + ((kb & 1) ^ 1) + 1) >> 1;            // 0 .. 4N+1
+    qb = qb >= 4 * N ? qb - 4 * N : qb;
+    const int32_t pix_b = 2 * N * (N - 1) + 4 * N * (kb - 1) + qb;
+    // caps: ring k from the pole in 1 .. N, q = floor(tt k) mod 4k
+    const int32_t kc = belt ? 1 : ia + ib + 1;                       // (belt lanes: a harmless 1)
     double fq;
-    if (!clear_of_integer(tt * (double)k, eps, fq)) return false;
-    int32_t q = (int32_t)fq;                                            // 0 .. 4k-1 when clear
-    q = q >= 4 * k ? q - 4 * k : q;
-    pix = dz > 0.0 ? 2 * k * (k - 1) + q : 12 * N * N - 2 * k * (k + 1) + q;
-    return true;
+    ok = ok & (belt | clear_of_integer(tt * (double)kc, eps, fq));
+    int32_t qc = (int32_t)(ok && !belt ? fq : 0.0);                  // 0 .. 4k-1 when clear
+    qc = qc >= 4 * kc ? qc - 4 * kc : qc;
+    const int32_t pix_c = dz > 0.0 ? 2 * kc * (kc - 1) + qc : 12 * N * N - 2 * kc * (kc + 1) + qc;
+    pix = belt ? pix_b : pix_c;
+    return ok;
 }
 
 // Largest j in [-1, nb] with e2[j] <= r2 (e2 ascending, j = -1 below e2[0]);
