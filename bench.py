@@ -10,9 +10,13 @@ Workload (one step = the whole path over one catalogue resident in HBM):
          -> weights VJP (dL/dOmega_m, dL/dz0).
 
 Prints one JSON line.  value = input particles binned per second (whole step).
-The roofline object describes the binning kernel (the dominant one), timed with
-HIP events on the stream it runs on; cpu_baseline times the oracle on one host
-core on a bounded sample of the same catalogue.
+The roofline object describes the dominant kernel, the FP64 decision pass of
+the binning call (keys_kernel: shell and RING pixel of every image), timed with
+HIP events that the library records on the stream the kernel runs on; it is
+bound by FP64 vector arithmetic.  roofline_hbm gives the whole binning call
+against HBM bandwidth (the fraction of the HBM roofline the task asks for) and
+born the Born pass.  cpu_baseline times the oracle on one host core on a
+bounded sample of the same catalogue.
 """
 
 from __future__ import annotations
@@ -29,6 +33,55 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particles/s binned to HEALPix shells; kappa maps/s batched vs plain, Δ≤1e-5·RMS"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # vector FP64: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+
+# Algorithmic FP64 operations of the decision pass, counted from the operations
+# the fast path performs (add, multiply, divide, square root, floor: 1; FMA: 2):
+#   per image tested:   d_z = (x_z - o_z) + s_z L and r^2 against the range -> 4
+#   per decided instance: radius and shell guards, then the RING pixel
+#   (rho^2, z, |z| = 2/3 test, sqrt, azimuth with one division and a degree-9
+#   polynomial, the shared division, floors with their guards)      -> 80
+FLOPS_PER_IMAGE = 4
+FLOPS_PER_INSTANCE = 80
+
+# HBM bytes of one keys_kernel launch on this workload, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the same
+# counters read for a 1 GiB device copy (FETCH_SIZE reads half: x2.0;
+# WRITE_SIZE exact: x1.0).  Valid only for the kernel sources they were taken
+# on: the sha1 of csrc/ and include/ at that time is kept, and a mismatch
+# reports traffic null.
+PMC_TRAFFIC = {
+    "kernel": "keys_kernel<float>",
+    "fetch_kib": None,
+    "write_kib": None,
+    "fetch_scale": 2.0,
+    "write_scale": 1.0,
+    "sources_sha1": None,
+    "profile": "profiles/keys_kernel_lognormal512_z05_nside1024_pmc.md",
+}
+
+
+def sources_sha1():
+    """sha1 over the library sources (csrc/*.hip, csrc/*.hpp, include/ufalcon.h)."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha1()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1801_05745_amd", "csrc", "*.hip")) +
+                   glob.glob(os.path.join(ROOT, "paper_1801_05745_amd", "csrc", "*.hpp")) +
+                   [os.path.join(ROOT, "include", "ufalcon.h")])
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    t = PMC_TRAFFIC
+    if t["fetch_kib"] is None or t["sources_sha1"] != sources_sha1():
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
 def parse():
@@ -41,7 +94,7 @@ def parse():
                     help="count accumulation: keyed partition + LDS histograms, or one atomic per instance")
     ap.add_argument("--particles", type=int, default=1 << 27)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 21)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 23)
     ap.add_argument("--batched", action="store_true", help="also time the batched form against plain calls")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of known size (for PMC byte-counter scaling)")
@@ -96,6 +149,7 @@ def main():
     else:
         ws = uf.bin_shells_workspace(device=dev)
     stream = torch.cuda.current_stream(dev)
+    timers = [uf.PhaseTimer(dev) for _ in range(args.steps)]
     ev_bin0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ev_bin1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ev_born0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
@@ -106,7 +160,8 @@ def main():
         uf.fill_u32(counts, 0)
         if k is not None:
             ev_bin0[k].record(stream)
-        uf.bin_shells(x, y, z, edges, nside, box_L=L, n_rep=R, counts=counts, status=status, workspace=ws)
+        uf.bin_shells(x, y, z, edges, nside, box_L=L, n_rep=R, counts=counts, status=status, workspace=ws,
+                      timer=timers[k] if k is not None else None)
         if k is not None:
             ev_bin1[k].record(stream)
         W, dW = uf.lensing_weights(om, [src], edges, with_derivatives=True, device=dev)
@@ -140,6 +195,15 @@ def main():
     rms = float(kap.pow(2).mean().sqrt())
     max_over_rms = float(kap.abs().max()) / rms
 
+    # per-phase milliseconds of the binning call, from the events the library
+    # recorded on the stream its kernels ran on
+    ph = [t.read() for t in timers]
+    phases = {name: sum(p[name] for p in ph) / len(ph) for name in uf.PHASES}
+    decide_ms = phases["decide"]
+    images = n * (2 * R + 1) ** 3
+    flops = FLOPS_PER_IMAGE * images + FLOPS_PER_INSTANCE * inst_per_step
+    traffic = measured_traffic()
+
     # algorithmic bytes of one binning launch: positions once + the count map written once
     bin_bytes = 3 * 4 * n + 4 * B * uf.npix(nside)
     born_bytes = 4 * B * uf.npix(nside) + 4 * uf.npix(nside)
@@ -165,15 +229,29 @@ def main():
             "instances_per_step": inst_per_step,
         },
         "roofline": {
+            "bound": "alu",
+            "kernel": "keys_kernel (FP64 shell + RING pixel decision of every image)",
+            "achieved": flops / (decide_ms / 1e3) / 1e12,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": flops / (decide_ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+            "traffic": traffic,
+            "launch_ms": decide_ms,
+            "algorithmic_flops": flops,
+            "flops_per_image": FLOPS_PER_IMAGE,
+            "flops_per_instance": FLOPS_PER_INSTANCE,
+            "images": images,
+        },
+        "roofline_hbm": {
             "bound": "hbm",
             "kernel": "ufalcon_bin_shells (all kernels of the call)",
             "achieved": bin_bytes / (bin_ms / 1e3) / 1e9,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": bin_bytes / (bin_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-            "traffic": None,
             "launch_ms": bin_ms,
             "algorithmic_bytes": bin_bytes,
+            "phases_ms": phases,
         },
         "born": {
             "launch_ms": born_ms,
@@ -236,8 +314,8 @@ def batched_vs_plain(dev):
                           counts=torch.empty((shells[r], uf.npix(nside)), dtype=torch.uint32, device=dev),
                           W=W, inv_nbar=inb,
                           kappa=torch.empty((1, uf.npix(nside)), dtype=torch.float32, device=dev)))
-    plan = uf.BatchPlan(items, nside, T=1)
-    ws = uf.bin_shells_workspace(device=dev)  # the batch plan accumulates with atomics: compare like with like
+    plan = uf.BatchPlan(items, nside, T=1)  # partitioned accumulation, like the plain calls below
+    ws = uf.partition_workspace(max(sizes), 2, max(shells), nside, device=dev)
 
     def plain():
         for it in items:

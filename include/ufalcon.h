@@ -112,6 +112,45 @@ int ufalcon_bin_shells(const void *x, const void *y, const void *z, int64_t n, i
                        int64_t nside, uint32_t *counts, ufalcon_status *status,
                        void *workspace, size_t workspace_bytes, ufalcon_stream_t stream);
 
+/*
+ * Phase timing of a binning call (diagnostics: results do not depend on it).
+ * A timer owns HIP events created on the device current at
+ * ufalcon_phase_timer_create.  ufalcon_bin_shells_timed takes the same
+ * arguments as ufalcon_bin_shells plus a timer, and records the timer's events
+ * on `stream` between the phases of the call:
+ *   SETUP       guard-list reset and chunk plan
+ *   DECIDE      shell and RING-pixel decisions of every image (the key pass of
+ *               partitioned accumulation, or the atomic pass)
+ *   PARTITION   the two radix partition levels of the keys
+ *   ACCUMULATE  per-cell-block LDS histograms added into `counts`
+ *   EXACT       exact decisions of guarded instances (and the rescue pass)
+ * ufalcon_phase_timer_read waits for the last recorded event and writes the
+ * milliseconds of each phase, summed over chunks, to ms[UFALCON_NPHASES].
+ * A timer serves one call at a time; each timed call replaces the previous
+ * record.  Errors: EINVAL (null timer / ms, or read before any timed call),
+ * EOVERFLOW (more than UFALCON_TIMER_EVENTS events were needed: the record is
+ * incomplete), EHIP.
+ */
+#define UFALCON_TIMER_EVENTS 256
+enum {
+    UFALCON_PHASE_SETUP = 0,
+    UFALCON_PHASE_DECIDE = 1,
+    UFALCON_PHASE_PARTITION = 2,
+    UFALCON_PHASE_ACCUMULATE = 3,
+    UFALCON_PHASE_EXACT = 4,
+    UFALCON_NPHASES = 5
+};
+typedef struct ufalcon_phase_timer ufalcon_phase_timer;
+int ufalcon_phase_timer_create(ufalcon_phase_timer **timer);
+int ufalcon_phase_timer_destroy(ufalcon_phase_timer *timer);
+int ufalcon_bin_shells_timed(const void *x, const void *y, const void *z, int64_t n, int dtype,
+                             const double *observer, double box_L, int32_t n_rep,
+                             const double *chi_edges, int32_t n_shells, int32_t shell_begin, int32_t shell_end,
+                             int64_t nside, uint32_t *counts, ufalcon_status *status,
+                             void *workspace, size_t workspace_bytes, ufalcon_stream_t stream,
+                             ufalcon_phase_timer *timer);
+int ufalcon_phase_timer_read(ufalcon_phase_timer *timer, double *ms);
+
 /* Source redshift distributions for the lensing weights. */
 typedef enum ufalcon_source_kind { UFALCON_SOURCE_DELTA = 0, UFALCON_SOURCE_SMAIL = 1 } ufalcon_source_kind;
 

@@ -65,6 +65,12 @@ _SIGS = {
     "ufalcon_bin_shells_workspace_size_partitioned": (_SZ, [_I64, _I32, _I32, _I64, _I64]),
     "ufalcon_bin_shells": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, ctypes.POINTER(_D), _D, _I32,
                                           ctypes.POINTER(_D), _I32, _I32, _I32, _I64, _P, _P, _P, _SZ, _P]),
+    "ufalcon_bin_shells_timed": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, ctypes.POINTER(_D), _D, _I32,
+                                                ctypes.POINTER(_D), _I32, _I32, _I32, _I64, _P, _P, _P, _SZ, _P,
+                                                _P]),
+    "ufalcon_phase_timer_create": (ctypes.c_int, [ctypes.POINTER(_P)]),
+    "ufalcon_phase_timer_destroy": (ctypes.c_int, [_P]),
+    "ufalcon_phase_timer_read": (ctypes.c_int, [_P, ctypes.POINTER(_D)]),
     "ufalcon_comoving_distance": (ctypes.c_int, [_P, _I64, _D, _P, _P]),
     "ufalcon_lensing_weights": (ctypes.c_int, [_D, ctypes.POINTER(Source), _I32, ctypes.POINTER(_D), _I32,
                                                _P, _P, _P]),
@@ -199,14 +205,51 @@ def new_counts(n_shells: int, nside: int, device="cuda"):
     return fill_u32(t, 0)
 
 
+PHASES = ("setup", "decide", "partition", "accumulate", "exact")
+
+
+class PhaseTimer:
+    """HIP events that a timed binning call records between its phases
+    (setup, decide, partition, accumulate, exact); read() waits for the last
+    one and returns the milliseconds of each phase, summed over chunks."""
+
+    def __init__(self, device="cuda"):
+        lib = load()
+        with torch.cuda.device(torch.device(device)):
+            h = ctypes.c_void_p()
+            _check(lib.ufalcon_phase_timer_create(ctypes.byref(h)), "ufalcon_phase_timer_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def read(self):
+        ms = (ctypes.c_double * len(PHASES))()
+        _check(load().ufalcon_phase_timer_read(self._h, ms), "ufalcon_phase_timer_read")
+        return dict(zip(PHASES, list(ms)))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            load().ufalcon_phase_timer_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def bin_shells(x, y, z, chi_edges, nside, observer=None, box_L=0.0, n_rep=0, shell_begin=0, shell_end=None,
-               counts=None, status=None, workspace=None, method="partition"):
+               counts=None, status=None, workspace=None, method="partition", timer=None):
     """Add the particles' (shell, RING pixel) counts to `counts` (uint32 [n_shells][npix]).
 
     x, y, z: contiguous float32 or float64 device tensors of equal length.
     chi_edges: shell edges in Mpc/h (host sequence, n_shells + 1 values).
     method: "partition" (keys + radix partition + LDS histograms) or "atomic"
     (one global atomic per instance); it only chooses the default workspace.
+    timer: optional PhaseTimer that records the phases of this call.
     """
     lib = load()
     if not (x.dtype == y.dtype == z.dtype) or not (x.numel() == y.numel() == z.numel()):
@@ -233,10 +276,13 @@ def bin_shells(x, y, z, chi_edges, nside, observer=None, box_L=0.0, n_rep=0, she
             workspace = bin_shells_workspace(device=x.device)
         else:
             raise ValueError(method)
-    rc = lib.ufalcon_bin_shells(_ptr(x), _ptr(y), _ptr(z), x.numel(), _dtype_code(x.dtype), obs, float(box_L),
-                                int(n_rep), e, n_shells, int(shell_begin), int(shell_end), int(nside), _ptr(counts),
-                                _ptr(status), _ptr(workspace), workspace.numel(), _stream(x.device))
-    _check(rc, "ufalcon_bin_shells")
+    args = (_ptr(x), _ptr(y), _ptr(z), x.numel(), _dtype_code(x.dtype), obs, float(box_L), int(n_rep), e, n_shells,
+            int(shell_begin), int(shell_end), int(nside), _ptr(counts), _ptr(status), _ptr(workspace),
+            workspace.numel(), _stream(x.device))
+    if timer is None:
+        _check(lib.ufalcon_bin_shells(*args), "ufalcon_bin_shells")
+    else:
+        _check(lib.ufalcon_bin_shells_timed(*args, timer.handle), "ufalcon_bin_shells_timed")
     return counts
 
 

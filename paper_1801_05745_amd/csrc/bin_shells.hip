@@ -262,13 +262,17 @@ int64_t guard_capacity(size_t bytes) {
 }
 
 template <typename T>
-int launch_bin_t(const BinParams &p, hipStream_t s) {
+int launch_bin_t(const BinParams &p, hipStream_t s, ufalcon_phase_timer *timer) {
     const unsigned grid =
         blocks_for(p.c.n, kBinBlock, resident_grid(bin_shells_kernel<T, kAtomic>, kBinBlock, (unsigned)device_cus()));
+    timer_start(timer, s);
     hipLaunchKernelGGL(guard_reset_kernel, dim3(1), dim3(64), 0, s, p.guard);
+    timer_mark(timer, UFALCON_PHASE_SETUP, s);
     hipLaunchKernelGGL((bin_shells_kernel<T, kAtomic>), dim3(grid), dim3(kBinBlock), 0, s, p);
+    timer_mark(timer, UFALCON_PHASE_DECIDE, s);
     hipLaunchKernelGGL(bin_guarded_kernel, dim3(64), dim3(256), 0, s, p);
     hipLaunchKernelGGL((bin_shells_kernel<T, kRescue>), dim3(grid), dim3(kBinBlock), 0, s, p);
+    timer_mark(timer, UFALCON_PHASE_EXACT, s);
     UFX_HIP_CHECK(hipGetLastError());
     return UFALCON_OK;
 }
@@ -276,7 +280,8 @@ int launch_bin_t(const BinParams &p, hipStream_t s) {
 }  // namespace ufx
 
 namespace ufx {
-int try_partitioned(BinParams &p, int dtype, void *workspace, size_t bytes, hipStream_t s, int *rc);
+int try_partitioned(BinParams &p, int dtype, void *workspace, size_t bytes, hipStream_t s, int *rc,
+                    ufalcon_phase_timer *timer);
 size_t partitioned_size_for(const BinParams &p);
 }
 
@@ -312,11 +317,11 @@ extern "C" int ufalcon_fill_u32(uint32_t *p, int64_t n, uint32_t value, ufalcon_
     return UFALCON_OK;
 }
 
-extern "C" int ufalcon_bin_shells(const void *x, const void *y, const void *z, int64_t n, int dtype,
-                                  const double *observer, double box_L, int32_t n_rep, const double *chi_edges,
-                                  int32_t n_shells, int32_t shell_begin, int32_t shell_end, int64_t nside,
-                                  uint32_t *counts, ufalcon_status *status, void *workspace, size_t workspace_bytes,
-                                  ufalcon_stream_t stream) {
+static int bin_shells_entry(const void *x, const void *y, const void *z, int64_t n, int dtype,
+                            const double *observer, double box_L, int32_t n_rep, const double *chi_edges,
+                            int32_t n_shells, int32_t shell_begin, int32_t shell_end, int64_t nside, uint32_t *counts,
+                            ufalcon_status *status, void *workspace, size_t workspace_bytes, ufalcon_stream_t stream,
+                            ufalcon_phase_timer *timer) {
     if (dtype != UFALCON_F32 && dtype != UFALCON_F64) return UFALCON_EINVAL;
     BinParams p;
     int rc = fill_core(p.c, p.e, x, y, z, n, observer, box_L, n_rep, chi_edges, n_shells, shell_begin, shell_end,
@@ -329,11 +334,33 @@ extern "C" int ufalcon_bin_shells(const void *x, const void *y, const void *z, i
     p.status = status;
     p.guard = static_cast<GuardList *>(workspace);
     p.guard_cap = guard_capacity(workspace_bytes);
-    if (p.c.n == 0 || p.c.nb == 0) return UFALCON_OK;
     hipStream_t s = as_stream(stream);
+    if (p.c.n == 0 || p.c.nb == 0) {
+        timer_start(timer, s);  // an empty record: every phase reads 0 ms
+        return UFALCON_OK;
+    }
     int prc = UFALCON_OK;
-    if (try_partitioned(p, dtype, workspace, workspace_bytes, s, &prc)) return prc;
-    return dtype == UFALCON_F32 ? launch_bin_t<float>(p, s) : launch_bin_t<double>(p, s);
+    if (try_partitioned(p, dtype, workspace, workspace_bytes, s, &prc, timer)) return prc;
+    return dtype == UFALCON_F32 ? launch_bin_t<float>(p, s, timer) : launch_bin_t<double>(p, s, timer);
+}
+
+extern "C" int ufalcon_bin_shells(const void *x, const void *y, const void *z, int64_t n, int dtype,
+                                  const double *observer, double box_L, int32_t n_rep, const double *chi_edges,
+                                  int32_t n_shells, int32_t shell_begin, int32_t shell_end, int64_t nside,
+                                  uint32_t *counts, ufalcon_status *status, void *workspace, size_t workspace_bytes,
+                                  ufalcon_stream_t stream) {
+    return bin_shells_entry(x, y, z, n, dtype, observer, box_L, n_rep, chi_edges, n_shells, shell_begin, shell_end,
+                            nside, counts, status, workspace, workspace_bytes, stream, nullptr);
+}
+
+extern "C" int ufalcon_bin_shells_timed(const void *x, const void *y, const void *z, int64_t n, int dtype,
+                                        const double *observer, double box_L, int32_t n_rep, const double *chi_edges,
+                                        int32_t n_shells, int32_t shell_begin, int32_t shell_end, int64_t nside,
+                                        uint32_t *counts, ufalcon_status *status, void *workspace,
+                                        size_t workspace_bytes, ufalcon_stream_t stream, ufalcon_phase_timer *timer) {
+    if (!timer) return UFALCON_EINVAL;
+    return bin_shells_entry(x, y, z, n, dtype, observer, box_L, n_rep, chi_edges, n_shells, shell_begin, shell_end,
+                            nside, counts, status, workspace, workspace_bytes, stream, timer);
 }
 
 // ------------------------------------------------------------------ batch plan
@@ -522,7 +549,7 @@ extern "C" int ufalcon_bin_shells_batched(ufalcon_batch_plan *plan, ufalcon_stat
         for (BinParams bp : plan->item_params) {
             bp.status = status;
             int rc = UFALCON_OK;
-            if (!try_partitioned(bp, plan->dtype, plan->d_part, plan->part_bytes, as_stream(stream), &rc))
+            if (!try_partitioned(bp, plan->dtype, plan->d_part, plan->part_bytes, as_stream(stream), &rc, nullptr))
                 return UFALCON_EWORKSPACE;
             if (rc) return rc;
         }

@@ -42,6 +42,10 @@ inline unsigned blocks_for(int64_t work, int64_t per_block, unsigned cap = 1u <<
     return (unsigned)(b > (int64_t)cap ? cap : b);
 }
 
+// Record the end of a phase on the timer (no-op for a null timer).  Defined in timer.hip.
+void timer_start(ufalcon_phase_timer *t, hipStream_t s);
+void timer_mark(ufalcon_phase_timer *t, int phase, hipStream_t s);
+
 // Upper bound on the number of instances a single (shell, pixel) cell can receive
 // from n particles with images {-R..R}^3 of a box of side L: the cell of shell b
 // has diameter <= (e_{b+1} - e_b) + e_{b+1} * psi(nside) with psi an upper bound

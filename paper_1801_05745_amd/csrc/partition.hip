@@ -634,7 +634,8 @@ __global__ void single_chunk_kernel(uint32_t *chunk, int64_t ngroups, PartHeader
 }
 
 template <typename T>
-int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws, hipStream_t s) {
+int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws, hipStream_t s,
+                       ufalcon_phase_timer *timer) {
     GuardList *guard = reinterpret_cast<GuardList *>(ws + L.off_guard);
     PartHeader *hdr = reinterpret_cast<PartHeader *>(ws + L.off_hdr);
     uint32_t *off1 = reinterpret_cast<uint32_t *>(ws + L.off_off1);
@@ -651,6 +652,7 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
     const int64_t ncells = (int64_t)p.c.nb * p.npix;
     const unsigned cus = (unsigned)device_cus();
 
+    timer_start(timer, s);
     hipLaunchKernelGGL(part_guard_reset_kernel, dim3(1), dim3(64), 0, s, guard);
     if (L.kmax == 1 && (double)p.c.n * (double)img_bound <= (double)L.budget) {
         // every instance of the set fits the key buffer (positions in the box)
@@ -660,6 +662,8 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
         hipLaunchKernelGGL(plan_chunks_kernel, dim3(1), dim3(1024), 0, s, grp, L.ngroups, L.budget, L.kmax, chunk,
                            hdr);
     }
+
+    timer_mark(timer, UFALCON_PHASE_SETUP, s);
 
     KeyParams kp;
     kp.p = p;
@@ -709,6 +713,7 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
         hipLaunchKernelGGL(reset_chunk_kernel, dim3(1), dim3(64), 0, s, hdr);
         kp.k = k;
         hipLaunchKernelGGL((keys_kernel<T>), dim3(key_grid), dim3(kBinBlock), 0, s, kp);
+        timer_mark(timer, UFALCON_PHASE_DECIDE, s);
         // level 1: by key >> s1
         hipLaunchKernelGGL(tile_hist_kernel, dim3(hist_grid), dim3(kPartThreads), 0, s, l1, k, L.kmax);
         hipLaunchKernelGGL(bucket_scan_kernel, dim3((unsigned)L.nb1), dim3(256), 0, s, l1, k, L.kmax);
@@ -721,17 +726,21 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
         hipLaunchKernelGGL(bucket_base_kernel, dim3(1), dim3(1024), 0, s, tot, L.nblk, offb, (uint32_t *)nullptr, hdr,
                            k, L.kmax);
         hipLaunchKernelGGL(scatter_kernel, dim3(scat_grid), dim3(kScatThreads), 0, s, l2, k, L.kmax);
+        timer_mark(timer, UFALCON_PHASE_PARTITION, s);
         hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)std::min<int64_t>(L.nblk, cus * 8)), dim3(kAccThreads), 0,
                            s, keysa, offb, L.nblk, ncells, p.c.counts, hdr, k, L.kmax);
+        timer_mark(timer, UFALCON_PHASE_ACCUMULATE, s);
     }
     hipLaunchKernelGGL(part_guarded_kernel, dim3(64), dim3(256), 0, s, p);
     hipLaunchKernelGGL((part_rescue_kernel<T>), dim3(key_grid), dim3(kBinBlock), 0, s, p);
+    timer_mark(timer, UFALCON_PHASE_EXACT, s);
     UFX_HIP_CHECK(hipGetLastError());
     return UFALCON_OK;
 }
 
 // Entry from ufalcon_bin_shells: returns 1 if the partitioned path was taken.
-int try_partitioned(BinParams &p, int dtype, void *workspace, size_t bytes, hipStream_t s, int *rc) {
+int try_partitioned(BinParams &p, int dtype, void *workspace, size_t bytes, hipStream_t s, int *rc,
+                    ufalcon_phase_timer *timer) {
     const int64_t ncells = (int64_t)p.c.nb * p.npix;
     if ((uintptr_t)p.c.counts & 15u) return 0;  // the block update uses 16-byte accesses
     PartLayout L;
@@ -739,8 +748,8 @@ int try_partitioned(BinParams &p, int dtype, void *workspace, size_t bytes, hipS
     if (!plan_layout(L, p.c.n, ncells, img, bytes, 0)) return 0;
     if (L.total > bytes) return 0;
     char *ws = static_cast<char *>(workspace);
-    *rc = dtype == UFALCON_F32 ? launch_partitioned<float>(p, L, img, ws, s)
-                               : launch_partitioned<double>(p, L, img, ws, s);
+    *rc = dtype == UFALCON_F32 ? launch_partitioned<float>(p, L, img, ws, s, timer)
+                               : launch_partitioned<double>(p, L, img, ws, s, timer);
     return 1;
 }
 

@@ -87,3 +87,15 @@ def test_born_and_weights_validation():
     assert lib.ufalcon_lensing_weights(1.5, src, 1, e, 2, FAKE, None, None) == -1
     assert lib.ufalcon_inv_nbar(10, 1.0, e, 2, 0, 2, 4, uf.NBAR_LOWER_EDGE, FAKE, None) == -1  # chi_0 = 0
     assert lib.ufalcon_inv_nbar(0, 1.0, e, 2, 0, 2, 4, 0, FAKE, None) == -1
+
+
+def test_phase_timer_validation():
+    lib = uf.load()
+    ms = (ctypes.c_double * 5)()
+    assert lib.ufalcon_phase_timer_read(None, ms) == -1
+    assert lib.ufalcon_phase_timer_create(None) == -1
+    assert lib.ufalcon_phase_timer_destroy(None) == 0
+    e = (ctypes.c_double * 2)(0.0, 1.0)
+    # a timed call without a timer is rejected before any validation or launch
+    assert lib.ufalcon_bin_shells_timed(FAKE, FAKE, FAKE, 4, 0, D3(0.0, 0.0, 0.0), 1.0, 0, e, 1, 0, 1, 4, FAKE,
+                                        None, ctypes.c_void_p(0x1000), 256, None, None) == -1

@@ -160,3 +160,23 @@ def test_partitioned_path_several_chunks(ufalcon):
     ref, _ = obin.bin_shells(x, y, z, (50.0,) * 3, L, R, edges, 32, threads=8)
     assert np.array_equal(got.cpu().numpy().astype(np.int64), ref)
     assert uf.status_dict(st)["n_instances"] == int(ref.sum())
+
+
+@pytest.mark.parametrize("method", ["partition", "atomic"])
+def test_phase_timer_records_phases_without_changing_counts(ufalcon, method):
+    L = 100.0
+    x, y, z = synth.lognormal_box(200003, L, seed=5, ngrid=32, dtype=torch.float32)
+    edges = [5.0, 20.0, 40.0, 61.0, 90.0]
+    plain, _ = _gpu_counts(x, y, z, edges, 16, L, 1, method=method)
+    timer = uf.PhaseTimer(DEV)
+    timed, st = _gpu_counts(x, y, z, edges, 16, L, 1, method=method, timer=timer)
+    ms = timer.read()
+    assert np.array_equal(plain, timed)
+    assert set(ms) == set(uf.PHASES)
+    assert all(v >= 0.0 for v in ms.values())
+    assert ms["decide"] > 0.0
+    if method == "atomic":
+        assert ms["partition"] == 0.0 and ms["accumulate"] == 0.0
+    else:
+        assert ms["partition"] > 0.0 and ms["accumulate"] > 0.0
+    timer.close()
