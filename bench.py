@@ -52,11 +52,11 @@ FLOPS_PER_INSTANCE = 80
 # reports traffic null.
 PMC_TRAFFIC = {
     "kernel": "keys_kernel<float>",
-    "fetch_kib": None,
-    "write_kib": None,
+    "fetch_kib": 786897.8,
+    "write_kib": 5066878.8,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
-    "sources_sha1": None,
+    "sources_sha1": "6f86d456c53f1d11f88c156bf894df3198802b67",
     "profile": "profiles/keys_kernel_lognormal512_z05_nside1024_pmc.md",
 }
 
