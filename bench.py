@@ -293,7 +293,8 @@ def cpu_baseline(x, y, z, edges, nside, L, R, sample, n):
 
 def batched_vs_plain(dev):
     """Maps/s of 16 realisations (uneven 64M-256M particles, 20-60 shells over z = 0.1-1.0,
-    Nside 1024, delta source z = 1.0): one graph replay against 16 sequences of plain calls."""
+    Nside 1024, delta source z = 1.0): one graph replay of the autotuned batch plan against
+    16 sequences of plain calls (partitioned accumulation, one shared workspace)."""
     import torch
 
     import paper_1801_05745_amd as uf
@@ -304,6 +305,7 @@ def batched_vs_plain(dev):
     sizes = synth.randint(16, 64 * M, 256 * M, seed=0, stream=900)
     shells = synth.randint(16, 20, 60, seed=0, stream=901)
     items = []
+    t0 = time.time()
     for r in range(16):
         x, y, z = synth.lognormal_box(sizes[r], L, seed=r, ngrid=256, dtype=torch.float32, device=dev)
         zg = torch.linspace(0.1, 1.0, shells[r] + 1, dtype=torch.float64, device=dev)
@@ -314,7 +316,14 @@ def batched_vs_plain(dev):
                           counts=torch.empty((shells[r], uf.npix(nside)), dtype=torch.uint32, device=dev),
                           W=W, inv_nbar=inb,
                           kappa=torch.empty((1, uf.npix(nside)), dtype=torch.float32, device=dev)))
-    plan = uf.BatchPlan(items, nside, T=1)  # partitioned accumulation, like the plain calls below
+        print(f"batched: realisation {r} generated ({sizes[r]} particles, {shells[r]} shells)", file=sys.stderr,
+              flush=True)
+    gen_s = time.time() - t0
+    t0 = time.time()
+    tuning = uf.autotune_batch(items, nside, T=1, sample_items=2)
+    tune_s = time.time() - t0
+    print(f"batched: autotuned in {tune_s:.1f} s -> {tuning['method']}", file=sys.stderr, flush=True)
+    plan = uf.BatchPlan(items, nside, T=1, method="auto")
     ws = uf.partition_workspace(max(sizes), 2, max(shells), nside, device=dev)
 
     def plain():
@@ -322,7 +331,7 @@ def batched_vs_plain(dev):
             uf.fill_u32(it["counts"], 0)
             uf.bin_shells(it["x"], it["y"], it["z"], it["chi_edges"], nside, box_L=L, n_rep=2, counts=it["counts"],
                           workspace=ws)
-            uf.born_kappa(it["counts"], it["W"], it["inv_nbar"])
+            it["kappa"].copy_(uf.born_kappa(it["counts"], it["W"], it["inv_nbar"]))
 
     def timed(fn, reps=2):
         fn()
@@ -334,10 +343,17 @@ def batched_vs_plain(dev):
         return (time.perf_counter() - t0) / reps
 
     t_plain = timed(plain)
+    print(f"batched: plain {t_plain:.3f} s per batch", file=sys.stderr, flush=True)
     t_graph = timed(plan.run_graph)
+    print(f"batched: graph {t_graph:.3f} s per batch", file=sys.stderr, flush=True)
     plan.close()
     return {"maps_per_s_batched": 16 / t_graph, "maps_per_s_plain": 16 / t_plain,
-            "speedup": t_plain / t_graph, "particles": int(sum(sizes)), "shells": shells}
+            "speedup": t_plain / t_graph, "particles": int(sum(sizes)), "shells": shells,
+            "tuning": {"method": tuning["method"], "tile": tuning["tile"],
+                       "persistent_wgs": tuning["persistent_wgs"],
+                       "candidates_ms": [round(c["ms"], 2) for c in tuning["candidates"]],
+                       "tune_s": tune_s, "sample_items": 2},
+            "input_generation_s": gen_s}
 
 
 if __name__ == "__main__":

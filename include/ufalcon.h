@@ -256,12 +256,14 @@ typedef struct ufalcon_batch_plan ufalcon_batch_plan;
 
 typedef enum ufalcon_accumulation {
     UFALCON_ACCUMULATE_PARTITIONED = 0, /* keys + radix partition + LDS block histograms, item after item */
-    UFALCON_ACCUMULATE_ATOMIC = 1       /* one persistent launch over (realisation, tile), global atomics */
+    UFALCON_ACCUMULATE_ATOMIC = 1,      /* one persistent launch over (realisation, tile), global atomics */
+    UFALCON_ACCUMULATE_AUTO = 2         /* the autotuner's choice for this batch shape (else PARTITIONED) */
 } ufalcon_accumulation;
 
 /*
- * tile: particles per work item of the persistent kernel (0 = default);
- * persistent_wgs: its workgroups (0 = default); accumulation: ufalcon_accumulation.
+ * tile: particles per work item of the persistent kernel (0 = default, or the
+ * autotuner's choice under UFALCON_ACCUMULATE_AUTO); persistent_wgs: its
+ * workgroups (0 likewise); accumulation: ufalcon_accumulation.
  * The partitioned form allocates one device workspace for the largest realisation
  * at plan creation (never on the binning calls).
  */
@@ -275,6 +277,38 @@ int ufalcon_bin_shells_batched(ufalcon_batch_plan *plan, ufalcon_status *status,
 int ufalcon_born_kappa_batched(ufalcon_batch_plan *plan, ufalcon_stream_t stream);
 /* clear + bin + Born for the whole batch as one captured HIP graph (captured on first use, replayed after). */
 int ufalcon_batch_run_graph(ufalcon_batch_plan *plan, ufalcon_status *status, ufalcon_stream_t stream);
+
+/*
+ * Autotuner of the batched form.  Times clear + bin + Born of the first
+ * min(n_items, sample_items) realisations (sample_items <= 0: all) under each
+ * candidate configuration: partitioned accumulation, and the persistent atomic
+ * kernel with tile in {2^16, 2^18, 2^20} particles and {4, 8, 16} workgroups
+ * per compute unit.  Each candidate runs once to warm up and once timed (HIP
+ * events on `stream`; the call synchronises).  The fastest is written to
+ * *tuning and recorded in a process-wide cache keyed by the batch shape
+ * (device, dtype, nside, T, number of realisations, log2 of the particle
+ * total, largest n_rep); ufalcon_batch_plan_create with
+ * UFALCON_ACCUMULATE_AUTO, tile 0 and persistent_wgs 0 takes the cached
+ * choice.  The cache is the library's only global state (mutex-guarded).
+ * Side effects: the sampled realisations' counts and kappa are overwritten;
+ * plans are created and freed (device allocations happen here, never in the
+ * binning calls of a plan).
+ */
+#define UFALCON_TUNE_MAX 16
+typedef struct ufalcon_batch_tuning {
+    int32_t accumulation;     /* chosen ufalcon_accumulation (PARTITIONED or ATOMIC) */
+    int32_t persistent_wgs;   /* chosen workgroups (ATOMIC) */
+    int64_t tile;             /* chosen particles per work item (ATOMIC) */
+    int32_t n_tried;          /* candidates timed */
+    int32_t best;             /* index of the chosen candidate */
+    double ms[UFALCON_TUNE_MAX];            /* time of each candidate, in the order listed above */
+    int32_t cand_accumulation[UFALCON_TUNE_MAX];
+    int32_t cand_wgs[UFALCON_TUNE_MAX];
+    int64_t cand_tile[UFALCON_TUNE_MAX];
+} ufalcon_batch_tuning;
+int ufalcon_batch_autotune(const ufalcon_batch_item *items, int32_t n_items, int dtype, int64_t nside, int32_t T,
+                           int out_dtype, int32_t sample_items, ufalcon_batch_tuning *tuning,
+                           ufalcon_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -55,6 +55,13 @@ class BatchItem(ctypes.Structure):
                 ("W", ctypes.c_void_p), ("inv_nbar", ctypes.c_void_p), ("kappa", ctypes.c_void_p)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("accumulation", ctypes.c_int32), ("persistent_wgs", ctypes.c_int32), ("tile", ctypes.c_int64),
+                ("n_tried", ctypes.c_int32), ("best", ctypes.c_int32), ("ms", ctypes.c_double * 16),
+                ("cand_accumulation", ctypes.c_int32 * 16), ("cand_wgs", ctypes.c_int32 * 16),
+                ("cand_tile", ctypes.c_int64 * 16)]
+
+
 _P = ctypes.c_void_p
 _I32, _I64, _D, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
 _SIGS = {
@@ -87,6 +94,8 @@ _SIGS = {
     "ufalcon_bin_shells_batched": (ctypes.c_int, [_P, _P, _P]),
     "ufalcon_born_kappa_batched": (ctypes.c_int, [_P, _P]),
     "ufalcon_batch_run_graph": (ctypes.c_int, [_P, _P, _P]),
+    "ufalcon_batch_autotune": (ctypes.c_int, [ctypes.POINTER(BatchItem), _I32, ctypes.c_int, _I64, _I32, ctypes.c_int,
+                                              _I32, _P, _P]),
 }
 
 
@@ -442,6 +451,51 @@ class LensingWeights(torch.autograd.Function):
 
 # ---------------------------------------------------------------- batched
 
+def _batch_items(items):
+    """ctypes array of ufalcon_batch_item for the binding's item dicts (plus the host
+    buffers that must outlive the call)."""
+    keep = []
+    arr = (BatchItem * len(items))()
+    dtype = None
+    for k, it in enumerate(items):
+        e, ne = _host_doubles(it["chi_edges"])
+        keep.append(e)
+        obs = it.get("observer") or (0.5 * it["box_L"],) * 3
+        x, y, z = it["x"], it["y"], it["z"]
+        dtype = _dtype_code(x.dtype)
+        arr[k].x, arr[k].y, arr[k].z = x.data_ptr(), y.data_ptr(), z.data_ptr()
+        arr[k].n = x.numel()
+        for j in range(3):
+            arr[k].observer[j] = float(obs[j])
+        arr[k].box_L = float(it["box_L"])
+        arr[k].n_rep = int(it.get("n_rep", 0))
+        arr[k].n_shells = ne - 1
+        arr[k].shell_begin = int(it.get("shell_begin", 0))
+        arr[k].shell_end = int(it.get("shell_end", ne - 1))
+        arr[k].chi_edges = e
+        arr[k].counts = it["counts"].data_ptr()
+        arr[k].W = it["W"].data_ptr() if it.get("W") is not None else None
+        arr[k].inv_nbar = it["inv_nbar"].data_ptr() if it.get("inv_nbar") is not None else None
+        arr[k].kappa = it["kappa"].data_ptr() if it.get("kappa") is not None else None
+    return arr, dtype, keep
+
+
+def autotune_batch(items, nside, T=1, out_dtype=torch.float32, sample_items=0):
+    """Time the batched form's candidate configurations on (the first sample_items of)
+    these realisations and record the fastest for BatchPlan(method="auto").  Overwrites
+    the sampled realisations' counts and kappa.  Returns the tuning record as a dict."""
+    lib = load()
+    arr, dtype, keep = _batch_items(items)
+    tun = Tuning()
+    _check(lib.ufalcon_batch_autotune(arr, len(items), dtype, int(nside), int(T), _dtype_code(out_dtype),
+                                      int(sample_items), ctypes.byref(tun), _stream()), "ufalcon_batch_autotune")
+    names = {0: "partition", 1: "atomic"}
+    cands = [{"method": names[tun.cand_accumulation[i]], "tile": int(tun.cand_tile[i]),
+              "persistent_wgs": int(tun.cand_wgs[i]), "ms": float(tun.ms[i])} for i in range(tun.n_tried)]
+    return {"method": names[tun.accumulation], "tile": int(tun.tile), "persistent_wgs": int(tun.persistent_wgs),
+            "best": int(tun.best), "candidates": cands}
+
+
 class BatchPlan:
     """Many realisations binned by one persistent launch and reduced by one batched Born launch.
 
@@ -452,32 +506,10 @@ class BatchPlan:
 
     def __init__(self, items, nside, T=1, out_dtype=torch.float32, tile=0, persistent_wgs=0, method="partition"):
         lib = load()
-        self._keep = []
-        arr = (BatchItem * len(items))()
-        dtype = None
-        for k, it in enumerate(items):
-            e, ne = _host_doubles(it["chi_edges"])
-            self._keep.append(e)
-            obs = it.get("observer") or (0.5 * it["box_L"],) * 3
-            x, y, z = it["x"], it["y"], it["z"]
-            dtype = _dtype_code(x.dtype)
-            arr[k].x, arr[k].y, arr[k].z = x.data_ptr(), y.data_ptr(), z.data_ptr()
-            arr[k].n = x.numel()
-            for j in range(3):
-                arr[k].observer[j] = float(obs[j])
-            arr[k].box_L = float(it["box_L"])
-            arr[k].n_rep = int(it.get("n_rep", 0))
-            arr[k].n_shells = ne - 1
-            arr[k].shell_begin = int(it.get("shell_begin", 0))
-            arr[k].shell_end = int(it.get("shell_end", ne - 1))
-            arr[k].chi_edges = e
-            arr[k].counts = it["counts"].data_ptr()
-            arr[k].W = it["W"].data_ptr() if it.get("W") is not None else None
-            arr[k].inv_nbar = it["inv_nbar"].data_ptr() if it.get("inv_nbar") is not None else None
-            arr[k].kappa = it["kappa"].data_ptr() if it.get("kappa") is not None else None
+        arr, dtype, self._keep = _batch_items(items)
         self.items = items
         handle = ctypes.c_void_p()
-        acc = {"partition": 0, "atomic": 1}[method]
+        acc = {"partition": 0, "atomic": 1, "auto": 2}[method]
         _check(lib.ufalcon_batch_plan_create(arr, len(items), dtype, int(nside), int(T), _dtype_code(out_dtype),
                                              int(tile), int(persistent_wgs), acc, ctypes.byref(handle)),
                "ufalcon_batch_plan_create")

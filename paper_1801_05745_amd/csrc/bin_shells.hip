@@ -30,6 +30,9 @@
 #include "binning_core.hpp"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 namespace ufx {
@@ -281,7 +284,7 @@ int launch_bin_t(const BinParams &p, hipStream_t s, ufalcon_phase_timer *timer) 
 
 namespace ufx {
 int try_partitioned(BinParams &p, int dtype, void *workspace, size_t bytes, hipStream_t s, int *rc,
-                    ufalcon_phase_timer *timer);
+                    ufalcon_phase_timer *timer, const PartHooks *hooks = nullptr);
 size_t partitioned_size_for(const BinParams &p);
 }
 
@@ -391,8 +394,16 @@ struct ufalcon_batch_plan {
     void *d_work = nullptr;  // guard list + work counters
     size_t work_bytes = 0;
     int accumulation = UFALCON_ACCUMULATE_PARTITIONED;
-    void *d_part = nullptr;  // partitioned-accumulation workspace shared by the items, in turn
+    // partitioned accumulation: two lanes (the caller's stream and aux_stream),
+    // each with its own workspace; realisations alternate between them, and the
+    // key pass of realisation k waits for that of k-1 (keys_done[k-1]), so one
+    // realisation's partition and accumulation overlap the next one's key pass
+    void *d_part = nullptr;  // workspace of lane 0
+    void *d_part2 = nullptr; // workspace of lane 1
     size_t part_bytes = 0;
+    hipStream_t aux_stream = nullptr;
+    hipEvent_t fork_event = nullptr, join_event = nullptr;
+    std::vector<hipEvent_t> keys_done;
     std::vector<BinParams> item_params;  // per-item parameters for the partitioned path
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -408,13 +419,69 @@ static void free_plan(ufalcon_batch_plan *p) {
     if (p->d_born) (void)hipFree(p->d_born);
     if (p->d_work) (void)hipFree(p->d_work);
     if (p->d_part) (void)hipFree(p->d_part);
+    if (p->d_part2) (void)hipFree(p->d_part2);
+    for (hipEvent_t e : p->keys_done)
+        if (e) (void)hipEventDestroy(e);
+    if (p->fork_event) (void)hipEventDestroy(p->fork_event);
+    if (p->join_event) (void)hipEventDestroy(p->join_event);
+    if (p->aux_stream) (void)hipStreamDestroy(p->aux_stream);
     delete p;
 }
+
+// ------------------------------------------------------------------ autotune cache
+namespace {
+struct TuneKey {
+    int device, dtype;
+    int64_t nside;
+    int32_t T, n_items, log2n, max_rep;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(device, dtype, nside, T, n_items, log2n, max_rep) <
+               std::tie(o.device, o.dtype, o.nside, o.T, o.n_items, o.log2n, o.max_rep);
+    }
+};
+struct TuneChoice {
+    int32_t accumulation, wgs;
+    int64_t tile;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneChoice> g_tune;  // the library's only global state
+
+TuneKey tune_key(const ufalcon_batch_item *items, int32_t n_items, int dtype, int64_t nside, int32_t T) {
+    TuneKey k{};
+    if (hipGetDevice(&k.device) != hipSuccess) k.device = -1;
+    k.dtype = dtype;
+    k.nside = nside;
+    k.T = T;
+    k.n_items = n_items;
+    int64_t total = 0;
+    int32_t max_rep = 0;
+    for (int32_t i = 0; i < n_items; ++i) {
+        total += items[i].n > 0 ? items[i].n : 0;
+        max_rep = std::max(max_rep, items[i].n_rep);
+    }
+    int l = 0;
+    while (l < 62 && ((int64_t)1 << (l + 1)) <= total) ++l;
+    k.log2n = l;
+    k.max_rep = max_rep;
+    return k;
+}
+}  // namespace
 
 extern "C" int ufalcon_batch_plan_create(const ufalcon_batch_item *items, int32_t n_items, int dtype, int64_t nside,
                                          int32_t T, int out_dtype, int64_t tile, int32_t persistent_wgs,
                                          int32_t accumulation, ufalcon_batch_plan **plan) {
     if (!items || n_items < 1 || !plan) return UFALCON_EINVAL;
+    if (accumulation == UFALCON_ACCUMULATE_AUTO) {
+        accumulation = UFALCON_ACCUMULATE_PARTITIONED;
+        const TuneKey key = tune_key(items, n_items, dtype, nside, T);
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        const auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            accumulation = it->second.accumulation;
+            if (tile == 0) tile = it->second.tile;
+            if (persistent_wgs == 0) persistent_wgs = it->second.wgs;
+        }
+    }
     if (accumulation != UFALCON_ACCUMULATE_PARTITIONED && accumulation != UFALCON_ACCUMULATE_ATOMIC)
         return UFALCON_EINVAL;
     if (dtype != UFALCON_F32 && dtype != UFALCON_F64) return UFALCON_EINVAL;
@@ -491,7 +558,17 @@ extern "C" int ufalcon_batch_plan_create(const ufalcon_batch_item *items, int32_
     p->work_bytes = kGuardHeader + (size_t)65536 * sizeof(GuardEntry);
     if (part_need > 0) {
         p->part_bytes = part_need;
-        if (hipMalloc(&p->d_part, part_need) != hipSuccess) {
+        bool ok = hipMalloc(&p->d_part, part_need) == hipSuccess;
+        if (ok && p->item_params.size() > 1) {
+            ok = hipMalloc(&p->d_part2, part_need) == hipSuccess &&
+                 hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&p->fork_event, hipEventDisableTiming) == hipSuccess &&
+                 hipEventCreateWithFlags(&p->join_event, hipEventDisableTiming) == hipSuccess;
+            p->keys_done.assign(p->item_params.size(), nullptr);
+            for (size_t i = 0; ok && i < p->keys_done.size(); ++i)
+                ok = hipEventCreateWithFlags(&p->keys_done[i], hipEventDisableTiming) == hipSuccess;
+        }
+        if (!ok) {
             free_plan(p);
             return UFALCON_EHIP;
         }
@@ -545,14 +622,35 @@ extern "C" int ufalcon_bin_shells_batched(ufalcon_batch_plan *plan, ufalcon_stat
     if (!plan) return UFALCON_EINVAL;
     if (plan->total_tiles == 0) return UFALCON_OK;
     if (plan->accumulation == UFALCON_ACCUMULATE_PARTITIONED) {
-        // realisations in turn through the partitioned pipeline, sharing one workspace
-        for (BinParams bp : plan->item_params) {
+        hipStream_t s0 = as_stream(stream);
+        const size_t m = plan->item_params.size();
+        if (m == 1) {
+            BinParams bp = plan->item_params[0];
             bp.status = status;
             int rc = UFALCON_OK;
-            if (!try_partitioned(bp, plan->dtype, plan->d_part, plan->part_bytes, as_stream(stream), &rc, nullptr))
+            if (!try_partitioned(bp, plan->dtype, plan->d_part, plan->part_bytes, s0, &rc, nullptr))
+                return UFALCON_EWORKSPACE;
+            return rc;
+        }
+        // two lanes: fork the aux stream from the caller's, alternate realisations,
+        // chain the key passes, join at the end (also valid under stream capture)
+        UFX_HIP_CHECK(hipEventRecord(plan->fork_event, s0));
+        UFX_HIP_CHECK(hipStreamWaitEvent(plan->aux_stream, plan->fork_event, 0));
+        for (size_t k = 0; k < m; ++k) {
+            BinParams bp = plan->item_params[k];
+            bp.status = status;
+            PartHooks hooks;
+            hooks.wait_keys = k > 0 ? plan->keys_done[k - 1] : nullptr;
+            hooks.done_keys = plan->keys_done[k];
+            hipStream_t sk = (k & 1) ? plan->aux_stream : s0;
+            void *ws = (k & 1) ? plan->d_part2 : plan->d_part;
+            int rc = UFALCON_OK;
+            if (!try_partitioned(bp, plan->dtype, ws, plan->part_bytes, sk, &rc, nullptr, &hooks))
                 return UFALCON_EWORKSPACE;
             if (rc) return rc;
         }
+        UFX_HIP_CHECK(hipEventRecord(plan->join_event, plan->aux_stream));
+        UFX_HIP_CHECK(hipStreamWaitEvent(s0, plan->join_event, 0));
         return UFALCON_OK;
     }
     const BatchParams bp = batch_params(plan, status);
@@ -602,5 +700,74 @@ extern "C" int ufalcon_batch_run_graph(ufalcon_batch_plan *plan, ufalcon_status 
         plan->graph_status = status;
     }
     UFX_HIP_CHECK(hipGraphLaunch(plan->graph_exec, as_stream(stream)));
+    return UFALCON_OK;
+}
+
+extern "C" int ufalcon_batch_autotune(const ufalcon_batch_item *items, int32_t n_items, int dtype, int64_t nside,
+                                      int32_t T, int out_dtype, int32_t sample_items, ufalcon_batch_tuning *tuning,
+                                      ufalcon_stream_t stream) {
+    if (!items || n_items < 1 || !tuning) return UFALCON_EINVAL;
+    const int32_t m = sample_items > 0 ? std::min(sample_items, n_items) : n_items;
+    *tuning = ufalcon_batch_tuning{};
+    struct Cand {
+        int32_t acc, wgs;
+        int64_t tile;
+    };
+    std::vector<Cand> cands;
+    cands.push_back({UFALCON_ACCUMULATE_PARTITIONED, 0, 0});
+    const int cus = device_cus();
+    for (int64_t t : {(int64_t)1 << 16, (int64_t)1 << 18, (int64_t)1 << 20})
+        for (int w : {4, 8, 16}) cands.push_back({UFALCON_ACCUMULATE_ATOMIC, cus * w, t});
+    hipStream_t s = as_stream(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return UFALCON_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return UFALCON_EHIP;
+    }
+    int rc = UFALCON_OK;
+    double best = 0.0;
+    int bi = -1;
+    for (size_t i = 0; i < cands.size() && !rc; ++i) {
+        const Cand &c = cands[i];
+        ufalcon_batch_plan *plan = nullptr;
+        rc = ufalcon_batch_plan_create(items, m, dtype, nside, T, out_dtype, c.tile, c.wgs, c.acc, &plan);
+        if (rc) break;
+        auto run = [&]() {
+            int r = ufalcon_batch_clear(plan, stream);
+            if (!r) r = ufalcon_bin_shells_batched(plan, nullptr, stream);
+            if (!r && T > 0) r = ufalcon_born_kappa_batched(plan, stream);
+            return r;
+        };
+        rc = run();  // warm-up
+        float ms = 0.0f;
+        if (!rc && hipEventRecord(e0, s) != hipSuccess) rc = UFALCON_EHIP;
+        if (!rc) rc = run();
+        if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = UFALCON_EHIP;
+        if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = UFALCON_EHIP;
+        ufalcon_batch_plan_destroy(plan);
+        if (rc) break;
+        tuning->ms[i] = ms;
+        tuning->cand_accumulation[i] = c.acc;
+        tuning->cand_wgs[i] = c.wgs;
+        tuning->cand_tile[i] = c.tile;
+        tuning->n_tried = (int32_t)i + 1;
+        if (bi < 0 || ms < best) {
+            best = ms;
+            bi = (int)i;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    tuning->best = bi;
+    tuning->accumulation = cands[bi].acc;
+    tuning->persistent_wgs = cands[bi].wgs;
+    tuning->tile = cands[bi].tile;
+    const TuneKey key = tune_key(items, n_items, dtype, nside, T);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[key] = TuneChoice{cands[bi].acc, cands[bi].wgs, cands[bi].tile};
     return UFALCON_OK;
 }

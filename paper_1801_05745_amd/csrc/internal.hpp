@@ -42,6 +42,14 @@ inline unsigned blocks_for(int64_t work, int64_t per_block, unsigned cap = 1u <<
     return (unsigned)(b > (int64_t)cap ? cap : b);
 }
 
+// Cross-stream ordering hooks of a partitioned binning call (batched pipelines):
+// the first key pass waits for `wait_keys`, and `done_keys` is recorded after
+// the last one.  Null events are skipped.
+struct PartHooks {
+    hipEvent_t wait_keys = nullptr;
+    hipEvent_t done_keys = nullptr;
+};
+
 // Record the end of a phase on the timer (no-op for a null timer).  Defined in timer.hip.
 void timer_start(ufalcon_phase_timer *t, hipStream_t s);
 void timer_mark(ufalcon_phase_timer *t, int phase, hipStream_t s);

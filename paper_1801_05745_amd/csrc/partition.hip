@@ -635,7 +635,7 @@ __global__ void single_chunk_kernel(uint32_t *chunk, int64_t ngroups, PartHeader
 
 template <typename T>
 int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws, hipStream_t s,
-                       ufalcon_phase_timer *timer) {
+                       ufalcon_phase_timer *timer, const PartHooks *hooks) {
     GuardList *guard = reinterpret_cast<GuardList *>(ws + L.off_guard);
     PartHeader *hdr = reinterpret_cast<PartHeader *>(ws + L.off_hdr);
     uint32_t *off1 = reinterpret_cast<uint32_t *>(ws + L.off_off1);
@@ -712,7 +712,9 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
     for (int k = 0; k < L.kmax; ++k) {
         hipLaunchKernelGGL(reset_chunk_kernel, dim3(1), dim3(64), 0, s, hdr);
         kp.k = k;
+        if (k == 0 && hooks && hooks->wait_keys) UFX_HIP_CHECK(hipStreamWaitEvent(s, hooks->wait_keys, 0));
         hipLaunchKernelGGL((keys_kernel<T>), dim3(key_grid), dim3(kBinBlock), 0, s, kp);
+        if (k == L.kmax - 1 && hooks && hooks->done_keys) UFX_HIP_CHECK(hipEventRecord(hooks->done_keys, s));
         timer_mark(timer, UFALCON_PHASE_DECIDE, s);
         // level 1: by key >> s1
         hipLaunchKernelGGL(tile_hist_kernel, dim3(hist_grid), dim3(kPartThreads), 0, s, l1, k, L.kmax);
@@ -740,7 +742,7 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
 
 // Entry from ufalcon_bin_shells: returns 1 if the partitioned path was taken.
 int try_partitioned(BinParams &p, int dtype, void *workspace, size_t bytes, hipStream_t s, int *rc,
-                    ufalcon_phase_timer *timer) {
+                    ufalcon_phase_timer *timer, const PartHooks *hooks) {
     const int64_t ncells = (int64_t)p.c.nb * p.npix;
     if ((uintptr_t)p.c.counts & 15u) return 0;  // the block update uses 16-byte accesses
     PartLayout L;
@@ -748,8 +750,8 @@ int try_partitioned(BinParams &p, int dtype, void *workspace, size_t bytes, hipS
     if (!plan_layout(L, p.c.n, ncells, img, bytes, 0)) return 0;
     if (L.total > bytes) return 0;
     char *ws = static_cast<char *>(workspace);
-    *rc = dtype == UFALCON_F32 ? launch_partitioned<float>(p, L, img, ws, s, timer)
-                               : launch_partitioned<double>(p, L, img, ws, s, timer);
+    *rc = dtype == UFALCON_F32 ? launch_partitioned<float>(p, L, img, ws, s, timer, hooks)
+                               : launch_partitioned<double>(p, L, img, ws, s, timer, hooks);
     return 1;
 }
 

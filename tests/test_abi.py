@@ -99,3 +99,15 @@ def test_phase_timer_validation():
     # a timed call without a timer is rejected before any validation or launch
     assert lib.ufalcon_bin_shells_timed(FAKE, FAKE, FAKE, 4, 0, D3(0.0, 0.0, 0.0), 1.0, 0, e, 1, 0, 1, 4, FAKE,
                                         None, ctypes.c_void_p(0x1000), 256, None, None) == -1
+
+
+def test_batch_autotune_validation():
+    lib = uf.load()
+    tun = uf.Tuning()
+    assert lib.ufalcon_batch_autotune(None, 1, 0, 16, 1, 0, 0, ctypes.byref(tun), None) == -1
+    items = (uf.BatchItem * 1)()
+    assert lib.ufalcon_batch_autotune(items, 0, 0, 16, 1, 0, 0, ctypes.byref(tun), None) == -1
+    assert lib.ufalcon_batch_autotune(items, 1, 0, 16, 1, 0, 0, None, None) == -1
+    # an unknown accumulation is rejected before anything is allocated
+    plan = ctypes.c_void_p()
+    assert lib.ufalcon_batch_plan_create(items, 1, 0, 16, 1, 0, 0, 0, 3, ctypes.byref(plan)) == -1

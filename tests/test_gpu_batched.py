@@ -83,3 +83,26 @@ def test_graph_replays_match_eager(ufalcon, method):
             assert torch.equal(it["counts"], eager_counts[k]), (rep, k)
             assert torch.equal(it["kappa"], eager_kappa[k]), (rep, k)
     plan.close()
+
+
+def test_autotuned_plan_matches_plain(ufalcon):
+    nside = 16
+    items = _realisations([60001, 20000, 90000], [4, 6, 3], nside=nside, seed0=20)
+    tun = uf.autotune_batch(items, nside, T=1, sample_items=2)
+    assert len(tun["candidates"]) == 10
+    times = [c["ms"] for c in tun["candidates"]]
+    assert all(t > 0.0 for t in times)
+    assert tun["best"] == int(np.argmin(times))
+    best = tun["candidates"][tun["best"]]
+    assert (tun["method"], tun["tile"], tun["persistent_wgs"]) == (best["method"], best["tile"],
+                                                                 best["persistent_wgs"])
+    plan = uf.BatchPlan(items, nside, T=1, method="auto")
+    plan.clear()
+    plan.bin()
+    plan.born()
+    torch.cuda.synchronize()
+    for it in items:
+        plain = uf.bin_shells(it["x"], it["y"], it["z"], it["chi_edges"], nside, box_L=it["box_L"], n_rep=it["n_rep"])
+        assert torch.equal(plain, it["counts"])
+        assert torch.equal(uf.born_kappa(it["counts"], it["W"], it["inv_nbar"]), it["kappa"])
+    plan.close()
