@@ -17,7 +17,8 @@ from dataclasses import dataclass
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libufalcon.so")
+# the in-tree build; UFALCON_LIB selects another build of the same library
+LIB_PATH = os.environ.get("UFALCON_LIB") or os.path.join(_HERE, "libufalcon.so")
 
 F32, F64 = 0, 1
 SOURCE_DELTA, SOURCE_SMAIL = 0, 1

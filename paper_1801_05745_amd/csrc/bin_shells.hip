@@ -41,23 +41,18 @@ namespace ufx {
 template <typename T, int kMode>
 __global__ __launch_bounds__(kBinBlock) void bin_shells_kernel(BinParams p) {
     if (kMode == kRescue && p.guard->overflow == 0u) return;  // uniform: nothing to rescue
-    __shared__ double e_s[UFALCON_MAX_SHELLS + 1];
-    __shared__ double e2_s[UFALCON_MAX_SHELLS + 1];
-    __shared__ double qx[kBinWaves][kQueue], qy[kBinWaves][kQueue], qz[kBinWaves][kQueue];
-    for (int j = threadIdx.x; j <= p.c.nb; j += kBinBlock) {
-        e_s[j] = p.e[j];
-        e2_s[j] = p.e[j] * p.e[j];
-    }
-    __syncthreads();
+    __shared__ EdgeLds E;
+    __shared__ double qbuf[kBinWaves][3 * kQueue];
+    load_edges(E, p.c, p.e);
     const int w = threadIdx.x >> 6;
     const Shared sh = shared_of(p);
     LaneStats st;
     Emitter em{};
-    int count = 0;
+    WaveQueue q{qbuf[w], 0, 0};
     const int64_t base = (int64_t)blockIdx.x * kBinBlock + w * 64;
     const int64_t stride = (int64_t)gridDim.x * kBinBlock;
-    bin_wave_range<T, kMode>(p.c, sh, e_s, e2_s, base, p.c.n, stride, qx[w], qy[w], qz[w], count, st, em);
-    drain_queue<kMode>(p.c, sh, e_s, e2_s, qx[w], qy[w], qz[w], count, st, em);
+    bin_wave_range<T, kMode>(p.c, sh, E, base, p.c.n, stride, q, st, em);
+    drain_queue<kMode>(p.c, sh, E, q, st, em);
     flush_stats(p.status, st);
 }
 
@@ -134,16 +129,15 @@ __device__ __forceinline__ int find_item(const BatchItemDev *items, int n_items,
 template <typename T, int kMode>
 __global__ __launch_bounds__(kBinBlock) void bin_batched_kernel(BatchParams p) {
     if (kMode == kRescue && p.sh.guard->overflow == 0u) return;
-    __shared__ double e_s[UFALCON_MAX_SHELLS + 1];
-    __shared__ double e2_s[UFALCON_MAX_SHELLS + 1];
-    __shared__ double qx[kBinWaves][kQueue], qy[kBinWaves][kQueue], qz[kBinWaves][kQueue];
+    __shared__ EdgeLds E;
+    __shared__ double qbuf[kBinWaves][3 * kQueue];
     __shared__ int64_t work;
     __shared__ int cur_item;
     const int w = threadIdx.x >> 6;
     if (threadIdx.x == 0) cur_item = -1;
     LaneStats st;
     Emitter em{};
-    int count = 0;
+    WaveQueue q{qbuf[w], 0, 0};
     unsigned int *ctr = kMode == kRescue ? &p.sh.guard->next_rescue : &p.sh.guard->next;
     for (;;) {
         __syncthreads();
@@ -153,21 +147,15 @@ __global__ __launch_bounds__(kBinBlock) void bin_batched_kernel(BatchParams p) {
         if (t >= p.total_tiles) break;  // uniform over the block: every wave exits here
         const int k = find_item(p.items, p.n_items, t);
         const BinCore c = p.items[k].c;
-        if (k != cur_item) {
+        if (k != cur_item) {  // uniform: `work` is shared
             __syncthreads();
-            const double *e = p.edges + p.items[k].edge_off;
-            for (int j = threadIdx.x; j <= c.nb; j += kBinBlock) {
-                e_s[j] = e[j];
-                e2_s[j] = e[j] * e[j];
-            }
-            __syncthreads();
+            load_edges(E, c, p.edges + p.items[k].edge_off);
             if (threadIdx.x == 0) cur_item = k;
         }
         const int64_t first = (t - p.items[k].tile_begin) * p.tile;
         const int64_t last = first + p.tile < c.n ? first + p.tile : c.n;
-        bin_wave_range<T, kMode>(c, p.sh, e_s, e2_s, first + w * 64, last, kBinBlock, qx[w], qy[w], qz[w], count, st,
-                                 em);
-        drain_queue<kMode>(c, p.sh, e_s, e2_s, qx[w], qy[w], qz[w], count, st, em);
+        bin_wave_range<T, kMode>(c, p.sh, E, first + w * 64, last, kBinBlock, q, st, em);
+        drain_queue<kMode>(c, p.sh, E, q, st, em);
     }
     flush_stats(p.status, st);
 }
@@ -251,6 +239,14 @@ int fill_core(BinCore &c, double *e_out, const void *x, const void *y, const voi
     const double elo = e_out[0], ehi = e_out[c.nb];
     c.lo2 = elo * elo * (1.0 - 0x1p-36);
     c.hi2 = ehi * ehi * (1.0 + 0x1p-36);
+    // shell lookup table over the prefilter range [lo2, hi2)
+    double e2[UFALCON_MAX_SHELLS + 1];
+    for (int j = 0; j <= c.nb; ++j) e2[j] = e_out[j] * e_out[j];
+    c.tab_n = shell_table_cells(e2, c.nb, c.lo2, c.hi2);
+    c.pad = 0;
+    c.tab_lo = c.lo2;
+    c.tab_h = c.tab_n ? (c.hi2 - c.lo2) / c.tab_n : 0.0;
+    c.tab_scale = c.tab_n ? c.tab_n / (c.hi2 - c.lo2) : 0.0;
     return UFALCON_OK;
 }
 
@@ -614,6 +610,7 @@ static BatchParams batch_params(ufalcon_batch_plan *plan, ufalcon_status *status
     bp.sh.nside = plan->nside;
     bp.sh.npix = plan->npix;
     bp.sh.eps = floor_margin((double)plan->nside);
+    bp.sh.status = status;
     bp.status = status;
     return bp;
 }

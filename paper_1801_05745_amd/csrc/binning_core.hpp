@@ -23,12 +23,18 @@ namespace ufx {
 
 constexpr int kBinBlock = 256;
 constexpr int kBinWaves = kBinBlock / 64;
-constexpr int kQueue = 128;  // < 64 pending + up to 64 new entries
+// Per-wave LDS queue of in-range images, two-ended: belt directions fill it from
+// the bottom, cap directions from the top, and each end is taken 64 at a time,
+// so that every lane of a batch runs the same pixel formula.  Before an image
+// step each end holds < 64 entries and the step adds at most 64: 63 + 63 + 64
+// entries fit in 192 slots without the ends meeting.
+constexpr int kQueue = 192;
+constexpr int kMaxRep = 64;  // largest n_rep the entry points accept
 
 enum BinMode { kAtomic = 0, kRescue = 1, kEmit = 2 };
 
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;   // sentinel in key buffers
-constexpr int kKeyChunk = 1024;            // key slots a wave reserves at a time
+constexpr int kKeyChunk = 4096;            // key slots a wave reserves at a time (larger: fewer contended reservations)
 
 // Workspace layout: this header, then guard_cap entries.
 struct GuardList {
@@ -57,7 +63,39 @@ struct BinCore {
     int32_t steps;        // binary-search steps over nb + 1 edges
     int32_t item;         // realisation index (batched) or 0
     uint32_t *counts;     // row of the first shell in range
+    int32_t tab_n;        // cells of the shell lookup table (0: binary search)
+    int32_t pad;
+    double tab_lo, tab_h, tab_scale;  // table over r^2 from tab_lo, cell width tab_h = 1 / tab_scale
 };
+
+// Edges of one shell range in LDS: the radii (exact path), the squared radii
+// with two sentinels on each side (e2() is indexable from -2 to nb + 2) and the
+// shell lookup table.
+struct EdgeLds {
+    double e[UFALCON_MAX_SHELLS + 1];
+    double e2p[UFALCON_MAX_SHELLS + 5];
+    double sL[2 * kMaxRep + 1];  // fl(s L) for s = -R .. R (index s + R)
+    int16_t tab[kShellTabMax];
+    __device__ const double *e2() const { return e2p + 2; }
+};
+
+// Fill `E` for the range of `c` with radii `e`.  Every thread of the block calls
+// it (it synchronises twice).
+__device__ inline void load_edges(EdgeLds &E, const BinCore &c, const double *e) {
+    for (int j = threadIdx.x; j <= c.nb; j += blockDim.x) {
+        E.e[j] = e[j];
+        E.e2p[j + 2] = e[j] * e[j];
+    }
+    if (threadIdx.x < 2) {
+        E.e2p[threadIdx.x] = -kEdgeSentinel;
+        E.e2p[c.nb + 3 + threadIdx.x] = kEdgeSentinel;
+    }
+    for (int k = threadIdx.x; k <= 2 * c.R; k += blockDim.x) E.sL[k] = (double)(k - c.R) * c.L;
+    __syncthreads();
+    for (int t = threadIdx.x; t < c.tab_n; t += blockDim.x)
+        E.tab[t] = (int16_t)shell_of_r2(E.e2(), c.nb, c.steps, c.tab_lo + (double)t * c.tab_h);
+    __syncthreads();
+}
 
 struct BinParams {
     BinCore c;
@@ -69,8 +107,10 @@ struct BinParams {
     double e[UFALCON_MAX_SHELLS + 1];  // edges of the range, e_b0 .. e_b1
 };
 
+// Per-lane event counts, flushed into the status by flush_stats (also whenever a
+// lane's instance count passes 2^30, see bin_wave_range).
 struct LaneStats {
-    unsigned long long inst = 0, guarded = 0, unresolved = 0, invalid = 0;
+    uint32_t inst = 0, guarded = 0, unresolved = 0, invalid = 0;
 };
 
 struct Shared {
@@ -78,6 +118,7 @@ struct Shared {
     int64_t guard_cap;
     int64_t nside, npix;
     double eps;
+    ufalcon_status *status;  // event counts (may be null)
 };
 
 // Key emission state of one wave (kEmit).  All lanes hold the same values.
@@ -91,6 +132,31 @@ struct Emitter {
     int fill;                          // slots used in the current chunk
     bool full;                         // the key buffer is exhausted: fall back to atomics
 };
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Add the wave's counts to the status and reset them.  Reached by all 64 lanes.
+__device__ __forceinline__ void flush_stats(ufalcon_status *status, LaneStats &st) {
+    const unsigned long long a = wave_sum(st.inst), b = wave_sum(st.guarded), c = wave_sum(st.unresolved),
+                             d = wave_sum(st.invalid);
+    if (status && (threadIdx.x & 63) == 0) {
+        if (a) atomicAdd(&status->n_instances, a);
+        if (b) atomicAdd(&status->n_guarded, b);
+        if (c) atomicAdd(&status->n_unresolved, c);
+        if (d) atomicAdd(&status->n_invalid, d);
+    }
+    st = LaneStats{};
+}
+
+// Ballot of a lane predicate (the compare's lane mask, without a round trip
+// through a VGPR) and the number of lanes below this one set in a mask.
+__device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
 
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -110,29 +176,29 @@ __device__ __noinline__ int bin_instance_exact(uint32_t *counts, int64_t npix, i
 }
 
 // Decide one queued instance.  Returns its key (kEmit) or kNoKey.
-template <int kMode>
-__device__ __forceinline__ uint32_t bin_instance(const BinCore &c, const Shared &sh, const double *e_s,
-                                                 const double *e2_s, double Nd, double dx, double dy, double dz,
-                                                 LaneStats &st) {
+template <int kMode, bool kBelt>
+__device__ __forceinline__ uint32_t bin_instance(const BinCore &c, const Shared &sh, const EdgeLds &E, double Nd,
+                                                 double dx, double dy, double dz, LaneStats &st) {
     const double r2 = dx * dx + dy * dy + dz * dz;
     bool clear;
-    const int j = fast_shell(e2_s, c.nb, c.steps, r2, clear);
+    const int j = fast_shell(E.e2(), c.nb, c.steps, E.tab, c.tab_n, c.tab_lo, c.tab_scale, r2, clear);
     if (clear) {
         if (j < 0 || j >= c.nb) return kNoKey;
         int32_t pix;
         // the range test costs two compares and keeps any logic slip from writing out of bounds
-        if (fast_ring_pixel((int32_t)sh.nside, Nd, sh.eps, dx, dy, dz, pix) && pix >= 0 && pix < sh.npix) {
+        if (fast_ring_pixel_region<kBelt>((int32_t)sh.nside, Nd, sh.eps, dx, dy, dz, pix) && pix >= 0 &&
+            pix < sh.npix) {
             if (kMode == kRescue) return kNoKey;
             ++st.inst;
             if (kMode == kAtomic) {
                 atomicAdd(c.counts + (int64_t)j * sh.npix + pix, 1u);
                 return kNoKey;
             }
-            return (uint32_t)((int64_t)j * sh.npix + pix);
+            return (uint32_t)j * (uint32_t)sh.npix + (uint32_t)pix;  // < 2^32: the host checks B * npix
         }
     }
     if (kMode == kRescue) {
-        const int r = bin_instance_exact(c.counts, sh.npix, sh.nside, e_s, c.nb, dx, dy, dz);
+        const int r = bin_instance_exact(c.counts, sh.npix, sh.nside, E.e, c.nb, dx, dy, dz);
         st.inst += r & 1;
         st.unresolved += (r >> 1) & 1;
     } else {
@@ -156,14 +222,14 @@ __device__ __forceinline__ uint32_t bin_instance(const BinCore &c, const Shared 
 __device__ __forceinline__ void emit_keys(Emitter &em, const BinCore &c, uint32_t key) {
     const int lane = threadIdx.x & 63;
     const bool has = key != kNoKey;
-    const unsigned long long m = __ballot(has);
+    const unsigned long long m = wave_ballot(has);
     if (m == 0ull) return;
     if (em.full) {  // buffer exhausted earlier: count directly
         if (has) atomicAdd(c.counts + key, 1u);
         return;
     }
     const int n = __popcll(m);
-    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    const int rank = lanes_below(m);
     const int room = kKeyChunk - em.fill;
     if (has && rank < room) {
         em.keys[em.base + em.fill + rank] = key;
@@ -199,26 +265,77 @@ __device__ __forceinline__ void close_emitter(Emitter &em) {
     for (int k = em.fill + lane; k < kKeyChunk; k += 64) em.keys[em.base + k] = kNoKey;
 }
 
-// Per-wave core: this wave handles particles base, base + stride, ... (64 at a
-// time) below `end`; queued images persist in (Qx, Qy, Qz, count) across calls
-// and are drained by drain_queue().
-template <typename T, int kMode>
-__device__ __forceinline__ void bin_wave_range(const BinCore &c, const Shared &sh, const double *e_s,
-                                               const double *e2_s, int64_t base, int64_t end, int64_t stride,
-                                               double *Qx, double *Qy, double *Qz, int &count, LaneStats &st,
-                                               Emitter &em) {
+// The wave's queue (LDS arrays of kQueue slots) and its fill at each end.
+struct WaveQueue {
+    double *q;  // x at q[s], y at q[kQueue + s], z at q[2 kQueue + s] for slot s
+    int nb;     // belt entries in slots [0, nb)
+    int nc;     // cap entries in slots [kQueue - nc, kQueue)
+};
+
+// Take the 64 entries at one end of the queue, shift the rest of that end into
+// place, and decide the taken images (one per lane).  All 64 lanes call it.
+template <int kMode, bool kBelt>
+__device__ __forceinline__ void take_batch(const BinCore &c, const Shared &sh, const EdgeLds &E, double Nd,
+                                           WaveQueue &q, LaneStats &st, Emitter &em) {
     const int lane = threadIdx.x & 63;
-    const unsigned long long below = (1ull << lane) - 1ull;
+    const int rest = (kBelt ? q.nb : q.nc) - 64;
+    const int take = kBelt ? lane : kQueue - 64 + lane;
+    const int from = kBelt ? 64 + lane : kQueue - 64 - rest + lane;
+    const int to = kBelt ? lane : kQueue - rest + lane;
+    wave_lds_sync();
+    const double ax = q.q[take], ay = q.q[kQueue + take], az = q.q[2 * kQueue + take];
+    double rx = 0.0, ry = 0.0, rz = 0.0;
+    if (lane < rest) {
+        rx = q.q[from];
+        ry = q.q[kQueue + from];
+        rz = q.q[2 * kQueue + from];
+    }
+    wave_lds_sync();
+    if (lane < rest) {
+        q.q[to] = rx;
+        q.q[kQueue + to] = ry;
+        q.q[2 * kQueue + to] = rz;
+    }
+    if (kBelt)
+        q.nb = rest;
+    else
+        q.nc = rest;
+    const uint32_t key = bin_instance<kMode, kBelt>(c, sh, E, Nd, ax, ay, az, st);
+    if (kMode == kEmit) emit_keys(em, c, key);
+}
+
+// Per-wave core: this wave handles particles base, base + stride, ... (64 at a
+// time) below `end`; queued images persist in `q` across calls and are drained
+// by drain_queue().
+template <typename T, int kMode>
+__device__ __forceinline__ void bin_wave_range(const BinCore &c, const Shared &sh, const EdgeLds &E,
+                                               int64_t base, int64_t end, int64_t stride, WaveQueue &q,
+                                               LaneStats &st, Emitter &em) {
+    const int lane = threadIdx.x & 63;
     const T *X = static_cast<const T *>(c.x);
     const T *Y = static_cast<const T *>(c.y);
     const T *Z = static_cast<const T *>(c.z);
     const double Nd = (double)sh.nside;
+    // positions are loaded one iteration ahead, so that their memory latency
+    // overlaps the images of the current 64 particles
+    T px = T(0), py = T(0), pz = T(0);
+    if (base + lane < end) {
+        px = X[base + lane];
+        py = Y[base + lane];
+        pz = Z[base + lane];
+    }
     for (; base < end; base += stride) {
         const int64_t i = base + lane;
+        const double x = (double)px, y = (double)py, z = (double)pz;
+        const int64_t inext = base + stride + lane;
+        if (base + stride < end && inext < end) {
+            px = X[inext];
+            py = Y[inext];
+            pz = Z[inext];
+        }
         bool valid = false;
         double bx = 0.0, by = 0.0, bz = 0.0;
         if (i < end) {
-            const double x = (double)X[i], y = (double)Y[i], z = (double)Z[i];
             if (isfinite(x) && isfinite(y) && isfinite(z)) {
                 valid = true;
                 bx = x - c.ox;
@@ -228,80 +345,63 @@ __device__ __forceinline__ void bin_wave_range(const BinCore &c, const Shared &s
                 ++st.invalid;
             }
         }
-        for (int sx = -c.R; sx <= c.R; ++sx) {
-            const double dx = bx + (double)sx * c.L;
-            for (int sy = -c.R; sy <= c.R; ++sy) {
-                const double dy = by + (double)sy * c.L;
-                for (int sz = -c.R; sz <= c.R; ++sz) {
-                    const double dz = bz + (double)sz * c.L;
-                    const double r2 = dx * dx + dy * dy + dz * dz;
+        const int side = 2 * c.R + 1;
+        for (int ix = 0; ix < side; ++ix) {
+            const double dx = bx + E.sL[ix];  // d = (x - o) + fl(s L), per axis
+            for (int iy = 0; iy < side; ++iy) {
+                const double dy = by + E.sL[iy];
+                const double rho2 = dx * dx + dy * dy;
+                const double a4 = 4.0 * rho2;
+                for (int iz = 0; iz < side; ++iz) {
+                    const double dz = bz + E.sL[iz];
+                    const double dz2 = dz * dz;
+                    const double r2 = rho2 + dz2;  // the same roundings as the decision code
                     const bool in = valid && r2 >= c.lo2 && r2 < c.hi2;
-                    const unsigned long long m = __ballot(in);
-                    if (m == 0ull) continue;
-                    const int pos = count + __popcll(m & below);
+                    const bool belt = 5.0 * dz2 < a4;
+                    const unsigned long long mi = wave_ballot(in), mbelt = wave_ballot(belt);
+                    if (mi == 0ull) continue;
+                    const unsigned long long mb = mi & mbelt, mc = mi & ~mbelt;
                     if (in) {
-                        Qx[pos] = dx;
-                        Qy[pos] = dy;
-                        Qz[pos] = dz;
+                        const int pos = belt ? q.nb + lanes_below(mb) : kQueue - 1 - q.nc - lanes_below(mc);
+                        q.q[pos] = dx;
+                        q.q[kQueue + pos] = dy;
+                        q.q[2 * kQueue + pos] = dz;
                     }
-                    count += __popcll(m);
-                    if (count >= 64) {
-                        wave_lds_sync();
-                        const double ax = Qx[lane], ay = Qy[lane], az = Qz[lane];
-                        const int rest = count - 64;
-                        double rx = 0.0, ry = 0.0, rz = 0.0;
-                        if (lane < rest) {
-                            rx = Qx[64 + lane];
-                            ry = Qy[64 + lane];
-                            rz = Qz[64 + lane];
-                        }
-                        wave_lds_sync();
-                        if (lane < rest) {
-                            Qx[lane] = rx;
-                            Qy[lane] = ry;
-                            Qz[lane] = rz;
-                        }
-                        count = rest;
-                        const uint32_t key = bin_instance<kMode>(c, sh, e_s, e2_s, Nd, ax, ay, az, st);
-                        if (kMode == kEmit) emit_keys(em, c, key);
-                    }
+                    q.nb += __popcll(mb);
+                    q.nc += __popcll(mc);
+                    if (q.nb >= 64) take_batch<kMode, true>(c, sh, E, Nd, q, st, em);
+                    if (q.nc >= 64) take_batch<kMode, false>(c, sh, E, Nd, q, st, em);
                 }
             }
         }
+        // one iteration adds at most (2R+1)^3 <= 129^3 instances per lane: flushing
+        // past 2^30 keeps the 32-bit counts exact
+        if (__ballot(st.inst >= (1u << 30)) != 0ull) flush_stats(sh.status, st);
     }
 }
 
+// Decide what is left in the queue (fewer than 64 at each end).
 template <int kMode>
-__device__ __forceinline__ void drain_queue(const BinCore &c, const Shared &sh, const double *e_s, const double *e2_s,
-                                            double *Qx, double *Qy, double *Qz, int &count, LaneStats &st,
-                                            Emitter &em) {
+__device__ __forceinline__ void drain_queue(const BinCore &c, const Shared &sh, const EdgeLds &E, WaveQueue &q,
+                                            LaneStats &st, Emitter &em) {
     const int lane = threadIdx.x & 63;
+    const double Nd = (double)sh.nside;
     wave_lds_sync();
     uint32_t key = kNoKey;
-    if (lane < count) key = bin_instance<kMode>(c, sh, e_s, e2_s, (double)sh.nside, Qx[lane], Qy[lane], Qz[lane], st);
+    if (lane < q.nb)
+        key = bin_instance<kMode, true>(c, sh, E, Nd, q.q[lane], q.q[kQueue + lane], q.q[2 * kQueue + lane], st);
+    if (kMode == kEmit) emit_keys(em, c, key);
+    key = kNoKey;
+    const int t = kQueue - 1 - lane;
+    if (lane < q.nc) key = bin_instance<kMode, false>(c, sh, E, Nd, q.q[t], q.q[kQueue + t], q.q[2 * kQueue + t], st);
     if (kMode == kEmit) emit_keys(em, c, key);
     wave_lds_sync();
-    count = 0;
-}
-
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__device__ __forceinline__ void flush_stats(ufalcon_status *status, LaneStats &st) {
-    const unsigned long long a = wave_sum(st.inst), b = wave_sum(st.guarded), c = wave_sum(st.unresolved),
-                             d = wave_sum(st.invalid);
-    if (status && (threadIdx.x & 63) == 0) {
-        if (a) atomicAdd(&status->n_instances, a);
-        if (b) atomicAdd(&status->n_guarded, b);
-        if (c) atomicAdd(&status->n_unresolved, c);
-        if (d) atomicAdd(&status->n_invalid, d);
-    }
+    q.nb = 0;
+    q.nc = 0;
 }
 
 __device__ __forceinline__ Shared shared_of(const BinParams &p) {
-    return Shared{p.guard, p.guard_cap, p.nside, p.npix, p.eps};
+    return Shared{p.guard, p.guard_cap, p.nside, p.npix, p.eps, p.status};
 }
 
 // Host helpers (bin_shells.hip)

@@ -14,6 +14,8 @@
 #include <cmath>
 using std::fabs;
 using std::floor;
+using std::fmax;
+using std::fmin;
 using std::fma;
 using std::sqrt;
 using std::atan2;

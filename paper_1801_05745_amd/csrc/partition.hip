@@ -4,23 +4,23 @@
 // Random 32-bit atomics into a GB-sized map run at a fixed ceiling on this GPU
 // (about 2e10 per second), far below what the FP64 pixelisation delivers, so
 // this path never updates the map once per instance.  Instead:
-//   0. count: per group of particles, an upper bound on its in-range images
-//      (squared radius only); plan: split the particles into chunks whose keys
-//      fit the workspace (on the device, no host synchronisation);
+//   0. plan: when every image of the set fits the key buffer, one chunk;
+//      otherwise count, per group of particles, an upper bound on its in-range
+//      images (squared radius only) and split the particles into chunks whose
+//      keys fit the workspace (on the device, no host synchronisation);
 //   per chunk:
 //   1. keys: the binning core emits key = b * npix + pix per instance into a
-//      buffer (waves reserve 1024-slot chunks; a per-workgroup LDS histogram
-//      counts keys per level-1 bucket, key >> s1);
-//   2. level-1 partition by key >> s1 (MSD radix step, <= 1024 buckets);
-//   3. histogram of cell blocks (key >> 14) inside each level-1 bucket;
-//   4. level-2 partition by cell block into a block-ordered buffer;
-//   5. accumulate: one workgroup per 16384-cell block counts its keys with LDS
+//      buffer (waves reserve 4096-slot chunks with one global atomic each);
+//   2. level-1 partition by key >> s1 (MSD radix step, <= 512 buckets);
+//   3. level-2 partition by cell block (key >> 14) inside each level-1 bucket;
+//   4. accumulate: one workgroup per 16384-cell block counts its keys with LDS
 //      atomics and adds the block into the map with coalesced 16-byte
 //      read-modify-writes (blocks without keys are skipped).
-// Each partition step works on super-tiles of 32768 keys: a histogram pass, one
-// global reservation per nonempty bucket, then 8192-key sub-tiles sorted in LDS
-// and written as contiguous runs.  Integer counts make the result independent
-// of every order involved.
+// Each partition level works on super-tiles of 32768 keys: per-tile bucket
+// counts, their exclusive scan per bucket (every tile's write offset), a scan
+// of the bucket totals, then 8192-key sub-tiles ranked, sorted in LDS and
+// written as contiguous runs, with no global atomics.  Integer counts make the
+// result independent of every order involved.
 #include "binning_core.hpp"
 
 #include <algorithm>
@@ -232,19 +232,14 @@ struct KeyParams {
 template <typename T>
 __global__ __launch_bounds__(kBinBlock, 5) void keys_kernel(KeyParams kp) {
     const BinParams &p = kp.p;
-    __shared__ double e_s[UFALCON_MAX_SHELLS + 1];
-    __shared__ double e2_s[UFALCON_MAX_SHELLS + 1];
-    __shared__ double qx[kBinWaves][kQueue], qy[kBinWaves][kQueue], qz[kBinWaves][kQueue];
+    __shared__ EdgeLds E;
+    __shared__ double qbuf[kBinWaves][3 * kQueue];
     if (kp.k >= (int)kp.hdr->n_chunks && kp.k != kp.kmax - 1) return;  // uniform: empty chunk
     const int64_t p0 = (int64_t)kp.chunk[kp.k] * kGroup;
     int64_t p1 = (int64_t)kp.chunk[kp.k + 1] * kGroup;
     if (p1 > p.c.n) p1 = p.c.n;
     if (p0 >= p1) return;
-    for (int j = threadIdx.x; j <= p.c.nb; j += kBinBlock) {
-        e_s[j] = p.e[j];
-        e2_s[j] = p.e[j] * p.e[j];
-    }
-    __syncthreads();
+    load_edges(E, p.c, p.e);
     const int w = threadIdx.x >> 6;
     const Shared sh = shared_of(p);
     LaneStats st;
@@ -257,11 +252,11 @@ __global__ __launch_bounds__(kBinBlock, 5) void keys_kernel(KeyParams kp) {
     em.base = 0;
     em.fill = kKeyChunk;
     em.full = false;
-    int count = 0;
+    WaveQueue q{qbuf[w], 0, 0};
     const int64_t base = p0 + (int64_t)blockIdx.x * kBinBlock + w * 64;
     const int64_t stride = (int64_t)gridDim.x * kBinBlock;
-    bin_wave_range<T, kEmit>(p.c, sh, e_s, e2_s, base, p1, stride, qx[w], qy[w], qz[w], count, st, em);
-    drain_queue<kEmit>(p.c, sh, e_s, e2_s, qx[w], qy[w], qz[w], count, st, em);
+    bin_wave_range<T, kEmit>(p.c, sh, E, base, p1, stride, q, st, em);
+    drain_queue<kEmit>(p.c, sh, E, q, st, em);
     close_emitter(em);
     flush_stats(p.status, st);
 }
@@ -598,22 +593,17 @@ __global__ __launch_bounds__(256) void part_guarded_kernel(BinParams p) {
 template <typename T>
 __global__ __launch_bounds__(kBinBlock) void part_rescue_kernel(BinParams p) {
     if (p.guard->overflow == 0u) return;
-    __shared__ double e_s[UFALCON_MAX_SHELLS + 1];
-    __shared__ double e2_s[UFALCON_MAX_SHELLS + 1];
-    __shared__ double qx[kBinWaves][kQueue], qy[kBinWaves][kQueue], qz[kBinWaves][kQueue];
-    for (int j = threadIdx.x; j <= p.c.nb; j += kBinBlock) {
-        e_s[j] = p.e[j];
-        e2_s[j] = p.e[j] * p.e[j];
-    }
-    __syncthreads();
+    __shared__ EdgeLds E;
+    __shared__ double qbuf[kBinWaves][3 * kQueue];
+    load_edges(E, p.c, p.e);
     const int w = threadIdx.x >> 6;
     const Shared sh = shared_of(p);
     LaneStats st;
     Emitter em{};
-    int count = 0;
-    bin_wave_range<T, kRescue>(p.c, sh, e_s, e2_s, (int64_t)blockIdx.x * kBinBlock + w * 64, p.c.n,
-                               (int64_t)gridDim.x * kBinBlock, qx[w], qy[w], qz[w], count, st, em);
-    drain_queue<kRescue>(p.c, sh, e_s, e2_s, qx[w], qy[w], qz[w], count, st, em);
+    WaveQueue q{qbuf[w], 0, 0};
+    bin_wave_range<T, kRescue>(p.c, sh, E, (int64_t)blockIdx.x * kBinBlock + w * 64, p.c.n,
+                               (int64_t)gridDim.x * kBinBlock, q, st, em);
+    drain_queue<kRescue>(p.c, sh, E, q, st, em);
     flush_stats(p.status, st);
 }
 

@@ -23,8 +23,38 @@ namespace ufx {
 constexpr double kRelGuard = 0x1p-38;
 
 // margin on floor arguments: N * 2^-38 (the FP64 error of the arguments is
-// below ~6 N ulp(1) ~ N * 2^-50 for tt < 4, |z| <= 1)
+// below ~16 N ulp(1) = N * 2^-48 for tt < 4, |z| <= 1: a few roundings, the
+// refined reciprocals below and the azimuth polynomial)
 UFX_HD double floor_margin(double Nd) { return Nd * 0x1p-38; }
+
+// 1/sqrt(x) and 1/x for positive normal x to a few ulp: the hardware estimate
+// (good to well over 14 bits) refined by two Newton steps, each of which at
+// least doubles the correct bits.  The host build uses IEEE operations.
+UFX_FN double rsqrt_nr(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rsq(x);
+    for (int i = 0; i < 2; ++i) {
+        const double e = fma(-(x * y), y, 1.0);  // 1 - x y^2
+        y = fma(0.5 * e, y, y);
+    }
+    return y;
+#else
+    return 1.0 / sqrt(x);
+#endif
+}
+
+UFX_FN double rcp_nr(double d) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(d);
+    for (int i = 0; i < 2; ++i) {
+        const double e = fma(-d, r, 1.0);  // 1 - d r
+        r = fma(r, e, r);
+    }
+    return r;
+#else
+    return 1.0 / d;
+#endif
+}
 
 UFX_FN bool clear_of_integer(double v, double eps, double &fl) {
     fl = floor(v);
@@ -32,7 +62,7 @@ UFX_FN bool clear_of_integer(double v, double eps, double &fl) {
 }
 
 // tt = 2 phi / pi in [0, 4] for phi = atan2(dy, dx) taken in [0, 2 pi).
-// One division reduces the azimuth to an octant: with mn = min(|dx|,|dy|),
+// One reciprocal reduces the azimuth to an octant: with mn = min(|dx|,|dy|),
 // mx = max(|dx|,|dy|), u = mn/mx, or u = (mn - mx)/(mn + mx) plus a quarter of a
 // quadrant when mn/mx > tan(pi/8), so |u| <= tan(pi/8); then
 // (2/pi) atan(u) = u P(u^2) with P of degree 9 (gen_tt_poly.py: relative error
@@ -46,7 +76,7 @@ UFX_FN double fast_tt(double dx, double dy) {
     const bool upper = mn > 0.4142 * mx;
     const double num = upper ? mn - mx : mn;
     const double den = upper ? mn + mx : mx;
-    const double u = den > 0.0 ? num / den : 0.0;
+    const double u = den > 0.0 ? num * rcp_nr(den) : 0.0;  // den is normal whenever the caller accepts
     const double s = u * u;
     double p = -0.016116971463406102;
     p = fma(p, s, 0.0319886291636091);
@@ -64,69 +94,123 @@ UFX_FN double fast_tt(double dx, double dy) {
     return dy >= 0.0 ? 2.0 - th : 2.0 + th;
 }
 
-// Returns true and the pixel when every decision is clear of its boundary.
-// Pixel arithmetic is 32-bit: 12 N^2 < 2^31 for N <= 8192.
+// Returns true and the pixel when every decision is clear of its boundary, for
+// a direction already known to lie in the belt (kBelt: 5 dz^2 < 4 rho^2, i.e.
+// |z| < 2/3) or in a cap; a direction of the other region, or near |z| = 2/3,
+// is deferred.  Pixel arithmetic is 32-bit: 12 N^2 < 2^31 for N <= 8192.
 //
-// Written without data-dependent branches: a wave holds belt and cap directions
-// together, so both formulas are evaluated and selected per lane.  Every lane
-// computes exactly the FP64 expressions of its own region (one division serves
-// both: z = dz / r in the belt, 1 - |z| = rho2 / (r (r + |dz|)) in the caps), so
-// the values are those of a branching evaluation.
-UFX_FN bool fast_ring_pixel(int32_t N, double Nd, double eps, double dx, double dy, double dz, int32_t &pix) {
+// With y = 1/|d| (refined reciprocal square root): z = dz y in the belt, and in
+// the caps 1 - |z| = rho^2 / (r (r + |dz|)) = rho^2 y^2 / (1 + |z|), which has no
+// cancellation near the poles.  Vectors so short that a reciprocal would leave
+// the normal range (|d|^2 <= 2^-600 or max(|dx|,|dy|) <= 2^-500) are deferred.
+// No data-dependent branches: rejected lanes carry harmless values.
+template <bool kBelt>
+UFX_FN bool fast_ring_pixel_region(int32_t N, double Nd, double eps, double dx, double dy, double dz,
+                                   int32_t &pix) {
     const double rho2 = dx * dx + dy * dy;
     const double dz2 = dz * dz;
+    const double r2 = rho2 + dz2;
     const double a5 = 5.0 * dz2, a4 = 4.0 * rho2;
-    bool ok = fabs(a5 - a4) > kRelGuard * (a5 + a4);  // false near |z| = 2/3 (or d = 0)
-    const bool belt = a5 < a4;
-    const double r = sqrt(rho2 + dz2);
+    const double mx = fmax(fabs(dx), fabs(dy));
+    const bool region = (a5 < a4) == kBelt;
+    const bool away = fabs(a5 - a4) > kRelGuard * (a5 + a4);  // not near |z| = 2/3 (nor d = 0)
+    bool ok = region && away && r2 > 0x1p-600 && mx > 0x1p-500;
+    const double y = rsqrt_nr(ok ? r2 : 1.0);                   // 1 / |d|
     const double tt = fast_tt(dx, dy);
-    const double num = belt ? dz : rho2;
-    const double den0 = belt ? r : r * (r + fabs(dz));
-    const double den = ok ? den0 : 1.0;              // keeps rejected lanes finite
-    const double qd = num / den;                     // z (belt) or 1 - |z| (caps)
-    // belt arguments
-    const double t1 = Nd * (0.5 + tt);
-    const double t2 = 0.75 * Nd * qd;
-    // cap arguments
-    const double ftt = floor(tt);
-    const double u = tt - ftt;
-    const double sig = Nd * sqrt(3.0 * (belt ? 0.0 : qd));
-    const double va = belt ? t1 - t2 : u * sig;
-    const double vb = belt ? t1 + t2 : (1.0 - u) * sig;
-    double fa, fb;
-    ok = ok & clear_of_integer(va, eps, fa);
-    ok = ok & clear_of_integer(vb, eps, fb);
-    ok = ok & (belt | ((tt - ftt) > eps && (ftt + 1.0 - tt) > eps));
-    const int32_t ia = (int32_t)(ok ? fa : 0.0), ib = (int32_t)(ok ? fb : 0.0);
-    // belt: jp = ia, jm = ib, ring k below z = 2/3 in 1 .. 2N+1
-    const int32_t kb = N + 1 + ia - ib;
-    int32_t qb = (ia + ib - N + ((kb & 1) ^ 1) + 1) >> 1;            // 0 .. 4N+1
-    qb = qb >= 4 * N ? qb - 4 * N : qb;
-    const int32_t pix_b = 2 * N * (N - 1) + 4 * N * (kb - 1) + qb;
-    // caps: ring k from the pole in 1 .. N, q = floor(tt k) mod 4k
-    const int32_t kc = belt ? 1 : ia + ib + 1;                       // (belt lanes: a harmless 1)
-    double fq;
-    ok = ok & (belt | clear_of_integer(tt * (double)kc, eps, fq));
-    int32_t qc = (int32_t)(ok && !belt ? fq : 0.0);                  // 0 .. 4k-1 when clear
-    qc = qc >= 4 * kc ? qc - 4 * kc : qc;
-    const int32_t pix_c = dz > 0.0 ? 2 * kc * (kc - 1) + qc : 12 * N * N - 2 * kc * (kc + 1) + qc;
-    pix = belt ? pix_b : pix_c;
+    const double z = dz * y;
+    if (kBelt) {
+        const double t1 = Nd * (0.5 + tt);
+        const double t2 = 0.75 * Nd * z;
+        double fa, fb;
+        ok = ok & clear_of_integer(t1 - t2, eps, fa);
+        ok = ok & clear_of_integer(t1 + t2, eps, fb);
+        const int32_t jp = (int32_t)(ok ? fa : 0.0), jm = (int32_t)(ok ? fb : 0.0);
+        const int32_t k = N + 1 + jp - jm;                              // ring below z = 2/3, 1 .. 2N+1
+        int32_t q = (jp + jm - N + ((k & 1) ^ 1) + 1) >> 1;             // 0 .. 4N+1
+        q = q >= 4 * N ? q - 4 * N : q;
+        pix = 2 * N * (N - 1) + 4 * N * (k - 1) + q;
+    } else {
+        const double om = rho2 * y * y * rcp_nr(1.0 + fabs(z));       // 1 - |z|
+        double ftt;
+        ok = ok & clear_of_integer(tt, eps, ftt);
+        const double u = tt - ftt;
+        const double sig = Nd * sqrt(3.0 * om);
+        double fa, fb;
+        ok = ok & clear_of_integer(u * sig, eps, fa);
+        ok = ok & clear_of_integer((1.0 - u) * sig, eps, fb);
+        const int32_t k = (int32_t)(ok ? fa : 0.0) + (int32_t)(ok ? fb : 0.0) + 1;  // ring from the pole, 1 .. N
+        double fq;
+        ok = ok & clear_of_integer(tt * (double)k, eps, fq);
+        int32_t q = (int32_t)(ok ? fq : 0.0);                          // 0 .. 4k-1 when clear
+        q = q >= 4 * k ? q - 4 * k : q;
+        pix = dz > 0.0 ? 2 * k * (k - 1) + q : 12 * N * N - 2 * k * (k + 1) + q;
+    }
     return ok;
 }
 
-// Largest j in [-1, nb] with e2[j] <= r2 (e2 ascending, j = -1 below e2[0]);
-// *clear is false when r2 is within the relative guard of e2[j] or e2[j+1].
-UFX_FN int fast_shell(const double *e2, int nb, int steps, double r2, bool &clear) {
-    // branch-free binary search for the count of edges <= r2 over nb + 1 edges
+// The same for any direction: the region is read off the vector.
+UFX_FN bool fast_ring_pixel(int32_t N, double Nd, double eps, double dx, double dy, double dz, int32_t &pix) {
+    const double rho2 = dx * dx + dy * dy;
+    const double dz2 = dz * dz;
+    return 5.0 * dz2 < 4.0 * rho2 ? fast_ring_pixel_region<true>(N, Nd, eps, dx, dy, dz, pix)
+                                  : fast_ring_pixel_region<false>(N, Nd, eps, dx, dy, dz, pix);
+}
+
+// Squared-edge sentinels: e2[-2], e2[-1] = -kEdgeSentinel and e2[nb+1], e2[nb+2] =
+// +kEdgeSentinel make the guard tests at the ends of the range vacuous.
+constexpr double kEdgeSentinel = 1e300;
+constexpr int kShellTabMax = 2048;  // cells of the shell lookup table, at most
+
+// The shell holding r^2 = x: (number of e2[0..nb] that are <= x) - 1, by binary search.
+UFX_HD int shell_of_r2(const double *e2, int nb, int steps, double x) {
     int lo = 0;
     for (int s = steps; s >= 0; --s) {
-        int probe = lo + (1 << s);
-        if (probe <= nb + 1 && e2[probe - 1] <= r2) lo = probe;
+        const int probe = lo + (1 << s);
+        if (probe <= nb + 1 && e2[probe - 1] <= x) lo = probe;
     }
-    const int j = lo - 1;
-    clear = true;
-    if (j >= 0) clear = fabs(r2 - e2[j]) > kRelGuard * e2[j];
-    if (j + 1 <= nb) clear = clear && fabs(r2 - e2[j + 1]) > kRelGuard * e2[j + 1];
+    return lo - 1;
+}
+
+// Cells of the lookup table over r^2 in [lo2, hi2): the fewest (a power of two
+// <= kShellTabMax) for which consecutive squared edges lie at least two cells
+// apart; 0 when there are none (then the binary search is used).
+UFX_HD int shell_table_cells(const double *e2, int nb, double lo2, double hi2) {
+    double gap = kEdgeSentinel;
+    for (int j = 0; j < nb; ++j) gap = e2[j + 1] - e2[j] < gap ? e2[j + 1] - e2[j] : gap;
+    const double span = hi2 - lo2;
+    if (!(span > 0.0)) return 0;
+    for (int g = 64; g <= kShellTabMax; g *= 2)
+        if (2.0 * span / g <= gap) return g;
+    return 0;
+}
+
+// Largest j in [-1, nb] with e2[j] <= r2 (e2 ascending, indexable from -2 to
+// nb + 2 with the sentinels above); *clear is false when r2 is within the
+// relative guard of e2[j] or e2[j+1].  With a table (tab_n > 0), tab[c] is the
+// shell at the start of cell c of tab_n equal cells of r^2 from tab_lo (cell
+// width 1/tab_scale); consecutive edges being two cells apart, the hint of the
+// computed cell is within one of the answer (also when rounding moves r^2 into a
+// neighbouring cell), and one step up or down corrects it.
+UFX_FN int fast_shell(const double *e2, int nb, int steps, const int16_t *tab, int tab_n, double tab_lo,
+                      double tab_scale, double r2, bool &clear) {
+    int j;
+    double elo, ehi;
+    if (tab_n > 0) {
+        const double cf = fmin(fmax((r2 - tab_lo) * tab_scale, 0.0), (double)(tab_n - 1));
+        const int h = tab[(int)cf];
+        const double em = e2[h - 1], e0 = e2[h], e1 = e2[h + 1], ep = e2[h + 2];
+        const bool up = e1 <= r2, down = e0 > r2;
+        j = up ? h + 1 : (down ? h - 1 : h);
+        elo = up ? e1 : (down ? em : e0);
+        ehi = up ? ep : (down ? e0 : e1);
+    } else {
+        j = shell_of_r2(e2, nb, steps, r2);
+        elo = e2[j];
+        ehi = e2[j + 1];
+    }
+    const bool clear_lo = fabs(r2 - elo) > kRelGuard * elo;
+    const bool clear_hi = fabs(r2 - ehi) > kRelGuard * ehi;
+    clear = clear_lo && clear_hi;
     return j;
 }
 

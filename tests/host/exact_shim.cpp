@@ -1,6 +1,8 @@
 // Host build of the library's device-side decision code (exact.hpp, ring.hpp)
 // so that its logic can be checked against the oracle on a machine without a GPU.
 #define UFX_HOST_BUILD 1
+#include <vector>
+
 #include "../../paper_1801_05745_amd/csrc/exact.hpp"
 #include "../../paper_1801_05745_amd/csrc/ring.hpp"
 
@@ -19,11 +21,30 @@ int shim_fast_ring_pixel(int64_t nside, double dx, double dy, double dz, int64_t
     return ok;
 }
 double shim_fast_tt(double dx, double dy) { return ufx::fast_tt(dx, dy); }
-int shim_fast_shell(const double *e2, int nb, double r2, int *clear) {
+// fast_shell on squared edges e2[0..nb]; use_table selects the lookup-table form
+// (cells over [lo2, hi2) as the library builds them), else the binary search.
+// Returns -100 when a table was asked for and the edges admit none.
+int shim_fast_shell(const double *e2, int nb, double r2, int *clear, int use_table, double lo2, double hi2) {
     int steps = 0;
     while ((2 << steps) <= nb + 1) ++steps;
+    std::vector<double> pad(nb + 5);
+    pad[0] = pad[1] = -ufx::kEdgeSentinel;
+    for (int j = 0; j <= nb; ++j) pad[j + 2] = e2[j];
+    pad[nb + 3] = pad[nb + 4] = ufx::kEdgeSentinel;
+    const double *E = pad.data() + 2;
+    int tab_n = 0;
+    double h = 0.0, scale = 0.0;
+    std::vector<int16_t> tab;
+    if (use_table) {
+        tab_n = ufx::shell_table_cells(e2, nb, lo2, hi2);
+        if (!tab_n) return -100;
+        h = (hi2 - lo2) / tab_n;
+        scale = tab_n / (hi2 - lo2);
+        tab.resize(tab_n);
+        for (int t = 0; t < tab_n; ++t) tab[t] = (int16_t)ufx::shell_of_r2(E, nb, steps, lo2 + (double)t * h);
+    }
     bool c = false;
-    int j = ufx::fast_shell(e2, nb, steps, r2, c);
+    int j = ufx::fast_shell(E, nb, steps, tab.data(), tab_n, lo2, scale, r2, c);
     *clear = c ? 1 : 0;
     return j;
 }

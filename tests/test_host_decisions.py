@@ -37,7 +37,8 @@ def lib():
         _lib.shim_fast_ring_pixel.argtypes = [ctypes.c_int64] + [ctypes.c_double] * 3 + [ctypes.POINTER(ctypes.c_int64)]
         _lib.shim_fast_shell.restype = ctypes.c_int
         _lib.shim_fast_shell.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_double,
-                                         ctypes.POINTER(ctypes.c_int)]
+                                         ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_double]
         _lib.shim_tt.restype = ctypes.c_double
         _lib.shim_tt.argtypes = [ctypes.c_double, ctypes.c_double]
         _lib.shim_fast_tt.restype = ctypes.c_double
@@ -161,7 +162,68 @@ def test_library_shells_exact_and_fast():
         want = obin.exact_shell(v, edges, 0, nb)
         got = lib().shim_exact_shell(v[0], v[1], v[2], e, nb)
         assert (got if got >= 0 else None) == want, v
-        clear = ctypes.c_int(0)
-        j = lib().shim_fast_shell(e2, nb, v[0] * v[0] + v[1] * v[1] + v[2] * v[2], ctypes.byref(clear))
-        if clear.value:
-            assert (j if 0 <= j < nb else None) == want, v
+        lo2, hi2 = _prefilter_range(edges)
+        for table in (0, 1):
+            clear = ctypes.c_int(0)
+            j = lib().shim_fast_shell(e2, nb, v[0] * v[0] + v[1] * v[1] + v[2] * v[2], ctypes.byref(clear), table,
+                                      lo2, hi2)
+            assert j != -100
+            if clear.value:
+                assert (j if 0 <= j < nb else None) == want, v
+
+
+def _prefilter_range(edges):
+    # the library's guard-widened range of squared radii
+    return edges[0] * edges[0] * (1.0 - 2.0 ** -36), edges[-1] * edges[-1] * (1.0 + 2.0 ** -36)
+
+
+def test_shell_table_lookup_equals_binary_search():
+    # the lookup-table form must give the binary search's index and guard flag for
+    # every r^2: random edge sets (some with thin shells), values on and next to the
+    # edges and the cell boundaries, and values outside the table's range
+    rng = random.Random(7)
+    tables = 0
+    for trial in range(60):
+        nb = rng.randint(1, 60)
+        start = rng.choice([0.0, rng.uniform(0.0, 300.0)])
+        widths = [rng.uniform(0.5, 80.0) for _ in range(nb)]
+        if trial % 3 == 0:
+            widths[rng.randrange(nb)] = rng.uniform(0.01, 0.5)  # a thin shell: maybe no table
+        edges = [start]
+        for w in widths:
+            edges.append(edges[-1] + w)
+        e2l = [v * v for v in edges]
+        e2 = (ctypes.c_double * len(edges))(*e2l)
+        lo2, hi2 = _prefilter_range(edges)
+        probe = ctypes.c_int(0)
+        if lib().shim_fast_shell(e2, nb, lo2, ctypes.byref(probe), 1, lo2, hi2) == -100:
+            continue
+        tables += 1
+        xs = [rng.uniform(lo2, hi2) for _ in range(400)]
+        xs += [rng.uniform(0.0, lo2) for _ in range(20)] + [rng.uniform(hi2, 2 * hi2 + 1.0) for _ in range(20)]
+        for v in e2l:
+            xs += [v, math.nextafter(v, -math.inf), math.nextafter(v, math.inf)]
+        for g in (64, 128, 256, 512, 1024, 2048):
+            h = (hi2 - lo2) / g
+            xs += [lo2 + t * h for t in range(0, g, max(1, g // 16))]
+        for x in xs:
+            ca, cb = ctypes.c_int(0), ctypes.c_int(0)
+            ja = lib().shim_fast_shell(e2, nb, x, ctypes.byref(ca), 0, lo2, hi2)
+            jb = lib().shim_fast_shell(e2, nb, x, ctypes.byref(cb), 1, lo2, hi2)
+            assert (ja, ca.value) == (jb, cb.value), (trial, x)
+    assert tables >= 20
+
+
+def test_workload_edges_use_the_shell_table():
+    # the shell sets of the benchmark workloads all admit a lookup table
+    from workloads import chi_edges_from_z
+
+    sets = [[25.0 * k for k in range(11)],             # 10 equal shells to 250 Mpc/h
+            chi_edges_from_z(0.1, 0.5, 30), chi_edges_from_z(0.1, 1.0, 20), chi_edges_from_z(0.1, 1.0, 60),
+            chi_edges_from_z(0.1, 1.5, 47), chi_edges_from_z(0.1, 1.5, 40)]
+    for edges in sets:
+        nb = len(edges) - 1
+        e2 = (ctypes.c_double * len(edges))(*[v * v for v in edges])
+        lo2, hi2 = _prefilter_range(edges)
+        c = ctypes.c_int(0)
+        assert lib().shim_fast_shell(e2, nb, 0.5 * (lo2 + hi2), ctypes.byref(c), 1, lo2, hi2) != -100, nb
