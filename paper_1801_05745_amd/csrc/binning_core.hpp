@@ -75,6 +75,7 @@ struct EdgeLds {
     double e[UFALCON_MAX_SHELLS + 1];
     double e2p[UFALCON_MAX_SHELLS + 5];
     double sL[2 * kMaxRep + 1];  // fl(s L) for s = -R .. R (index s + R)
+    double ttc[kTtTerms];         // azimuth polynomial
     int16_t tab[kShellTabMax];
     __device__ const double *e2() const { return e2p + 2; }
 };
@@ -91,6 +92,7 @@ __device__ inline void load_edges(EdgeLds &E, const BinCore &c, const double *e)
         E.e2p[c.nb + 3 + threadIdx.x] = kEdgeSentinel;
     }
     for (int k = threadIdx.x; k <= 2 * c.R; k += blockDim.x) E.sL[k] = (double)(k - c.R) * c.L;
+    if (threadIdx.x < kTtTerms) E.ttc[threadIdx.x] = kTtCoef[threadIdx.x];
     __syncthreads();
     for (int t = threadIdx.x; t < c.tab_n; t += blockDim.x)
         E.tab[t] = (int16_t)shell_of_r2(E.e2(), c.nb, c.steps, c.tab_lo + (double)t * c.tab_h);
@@ -151,6 +153,15 @@ __device__ __forceinline__ void flush_stats(ufalcon_status *status, LaneStats &s
     st = LaneStats{};
 }
 
+// 0, but opaque to the compiler: an LDS index offset by it is reloaded where it
+// is used instead of being hoisted out of loops into registers kept for the
+// whole kernel (the azimuth coefficients).  Emits no instruction.
+__device__ __forceinline__ int opaque_zero() {
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    return z;
+}
+
 // Ballot of a lane predicate (the compare's lane mask, without a round trip
 // through a VGPR) and the number of lanes below this one set in a mask.
 __device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
@@ -186,8 +197,8 @@ __device__ __forceinline__ uint32_t bin_instance(const BinCore &c, const Shared 
         if (j < 0 || j >= c.nb) return kNoKey;
         int32_t pix;
         // the range test costs two compares and keeps any logic slip from writing out of bounds
-        if (fast_ring_pixel_region<kBelt>((int32_t)sh.nside, Nd, sh.eps, dx, dy, dz, pix) && pix >= 0 &&
-            pix < sh.npix) {
+        if (fast_ring_pixel_region<kBelt>((int32_t)sh.nside, Nd, sh.eps, dx, dy, dz, pix, E.ttc + opaque_zero()) &&
+            pix >= 0 && pix < sh.npix) {
             if (kMode == kRescue) return kNoKey;
             ++st.inst;
             if (kMode == kAtomic) {

@@ -230,7 +230,7 @@ struct KeyParams {
 };
 
 template <typename T>
-__global__ __launch_bounds__(kBinBlock, 5) void keys_kernel(KeyParams kp) {
+__global__ __launch_bounds__(kBinBlock, 6) void keys_kernel(KeyParams kp) {
     const BinParams &p = kp.p;
     __shared__ EdgeLds E;
     __shared__ double qbuf[kBinWaves][3 * kQueue];

@@ -69,7 +69,17 @@ UFX_FN bool clear_of_integer(double v, double eps, double &fl) {
 // < 1e-15 before rounding).  The absolute error of tt stays below ~2e-15, far
 // inside the floor margin N 2^-38.  tt may round to 4.0 just below the +x axis;
 // the guard band catches it.
-UFX_FN double fast_tt(double dx, double dy) {
+// Coefficients of P, constant term first (gen_tt_poly.py).
+constexpr int kTtTerms = 10;
+constexpr double kTtCoef[kTtTerms] = {
+    0.6366197723675807,   -0.21220659078848142, 0.1273239543359597,   -0.09094567142790448, 0.07073513392040226,
+    -0.05786574491875008, 0.04885124377544614,  -0.041418373955876615, 0.0319886291636091,  -0.016116971463406102};
+
+// `c` holds kTtCoef (the device code passes a copy in LDS, read through a
+// volatile pointer: every use is a fresh load the FMA may overwrite, so no
+// registers stay pinned to constants).
+template <typename CoefPtr>
+UFX_FN double fast_tt_c(double dx, double dy, CoefPtr c) {
     const double ax = fabs(dx), ay = fabs(dy);
     const double mn = ax < ay ? ax : ay;
     const double mx = ax < ay ? ay : ax;
@@ -78,21 +88,15 @@ UFX_FN double fast_tt(double dx, double dy) {
     const double den = upper ? mn + mx : mx;
     const double u = den > 0.0 ? num * rcp_nr(den) : 0.0;  // den is normal whenever the caller accepts
     const double s = u * u;
-    double p = -0.016116971463406102;
-    p = fma(p, s, 0.0319886291636091);
-    p = fma(p, s, -0.041418373955876615);
-    p = fma(p, s, 0.04885124377544614);
-    p = fma(p, s, -0.05786574491875008);
-    p = fma(p, s, 0.07073513392040226);
-    p = fma(p, s, -0.09094567142790448);
-    p = fma(p, s, 0.1273239543359597);
-    p = fma(p, s, -0.21220659078848142);
-    p = fma(p, s, 0.6366197723675807);
+    double p = c[kTtTerms - 1];
+    for (int k = kTtTerms - 2; k >= 0; --k) p = fma(p, s, c[k]);
     double th = fma(u, p, upper ? 0.5 : 0.0);  // quarter turns of atan(mn/mx), in [0, 1/2]
     th = ay > ax ? 1.0 - th : th;              // quarter turns of the angle of (|dx|, |dy|)
     if (dx >= 0.0) return dy >= 0.0 ? th : 4.0 - th;
     return dy >= 0.0 ? 2.0 - th : 2.0 + th;
 }
+
+UFX_FN double fast_tt(double dx, double dy) { return fast_tt_c(dx, dy, kTtCoef); }
 
 // Returns true and the pixel when every decision is clear of its boundary, for
 // a direction already known to lie in the belt (kBelt: 5 dz^2 < 4 rho^2, i.e.
@@ -104,9 +108,9 @@ UFX_FN double fast_tt(double dx, double dy) {
 // cancellation near the poles.  Vectors so short that a reciprocal would leave
 // the normal range (|d|^2 <= 2^-600 or max(|dx|,|dy|) <= 2^-500) are deferred.
 // No data-dependent branches: rejected lanes carry harmless values.
-template <bool kBelt>
-UFX_FN bool fast_ring_pixel_region(int32_t N, double Nd, double eps, double dx, double dy, double dz,
-                                   int32_t &pix) {
+template <bool kBelt, typename CoefPtr>
+UFX_FN bool fast_ring_pixel_region(int32_t N, double Nd, double eps, double dx, double dy, double dz, int32_t &pix,
+                                   CoefPtr tt_coef) {
     const double rho2 = dx * dx + dy * dy;
     const double dz2 = dz * dz;
     const double r2 = rho2 + dz2;
@@ -116,7 +120,7 @@ UFX_FN bool fast_ring_pixel_region(int32_t N, double Nd, double eps, double dx, 
     const bool away = fabs(a5 - a4) > kRelGuard * (a5 + a4);  // not near |z| = 2/3 (nor d = 0)
     bool ok = region && away && r2 > 0x1p-600 && mx > 0x1p-500;
     const double y = rsqrt_nr(ok ? r2 : 1.0);                   // 1 / |d|
-    const double tt = fast_tt(dx, dy);
+    const double tt = fast_tt_c(dx, dy, tt_coef);
     const double z = dz * y;
     if (kBelt) {
         const double t1 = Nd * (0.5 + tt);
@@ -152,14 +156,14 @@ UFX_FN bool fast_ring_pixel_region(int32_t N, double Nd, double eps, double dx, 
 UFX_FN bool fast_ring_pixel(int32_t N, double Nd, double eps, double dx, double dy, double dz, int32_t &pix) {
     const double rho2 = dx * dx + dy * dy;
     const double dz2 = dz * dz;
-    return 5.0 * dz2 < 4.0 * rho2 ? fast_ring_pixel_region<true>(N, Nd, eps, dx, dy, dz, pix)
-                                  : fast_ring_pixel_region<false>(N, Nd, eps, dx, dy, dz, pix);
+    return 5.0 * dz2 < 4.0 * rho2 ? fast_ring_pixel_region<true>(N, Nd, eps, dx, dy, dz, pix, kTtCoef)
+                                  : fast_ring_pixel_region<false>(N, Nd, eps, dx, dy, dz, pix, kTtCoef);
 }
 
 // Squared-edge sentinels: e2[-2], e2[-1] = -kEdgeSentinel and e2[nb+1], e2[nb+2] =
 // +kEdgeSentinel make the guard tests at the ends of the range vacuous.
 constexpr double kEdgeSentinel = 1e300;
-constexpr int kShellTabMax = 2048;  // cells of the shell lookup table, at most
+constexpr int kShellTabMax = 1024;  // cells of the shell lookup table, at most
 
 // The shell holding r^2 = x: (number of e2[0..nb] that are <= x) - 1, by binary search.
 UFX_HD int shell_of_r2(const double *e2, int nb, int steps, double x) {
