@@ -269,9 +269,8 @@ __global__ __launch_bounds__(kBinBlock, 6) void keys_kernel(KeyParams kp) {
 // turns them into per-super-tile write offsets inside each bucket (and bucket
 // totals), bucket_base scans the totals, and scatter writes every key at
 // base[bucket] + offset[tile][bucket] + its rank inside the super-tile, sorting
-// 4096-key sub-tiles in LDS so that each bucket's keys leave as contiguous runs.
-// No global atomics; ranks come from a wave-level multi-split (one ballot per
-// bucket bit).
+// 8192-key sub-tiles in LDS so that each bucket's keys leave as contiguous runs.
+// No global atomics; ranks inside a sub-tile come from LDS atomics.
 struct PartStep {
     const uint32_t *in;
     uint32_t *out;
@@ -281,7 +280,7 @@ struct PartStep {
     const uint32_t *seg_tiles;  // level 2: [nseg + 1] first super-tile of each segment
     const PartHeader *hdr;      // level 1: reserved slots
     unsigned long long cap;
-    int shift, nbins, nbits;
+    int shift, nbins;
     uint32_t *tile_hist;        // [ntiles][nbins]: counts, then offsets inside the bucket
     uint32_t *bucket_tot;       // [nseg * nbins]
     uint32_t *bucket_base;      // [nseg * nbins + 1] exclusive scan of bucket_tot
@@ -314,17 +313,6 @@ __device__ __forceinline__ void seg_range(const PartStep &ps, int64_t t, int &se
     seg = a;
     lo = (int64_t)ps.seg_off[a] + (t - ps.seg_tiles[a]) * kSuper;
     hi = lo + kSuper < (int64_t)ps.seg_off[a + 1] ? lo + kSuper : (int64_t)ps.seg_off[a + 1];
-}
-
-// Lanes of the wave holding the same bucket as this lane (valid lanes only).
-__device__ __forceinline__ unsigned long long match_bucket(uint32_t b, int nbits, bool valid) {
-    unsigned long long m = __ballot(valid);
-    for (int i = 0; i < nbits; ++i) {
-        const bool bit = (b >> i) & 1u;
-        const unsigned long long v = __ballot(bit);
-        m &= bit ? v : ~v;
-    }
-    return m;
 }
 
 // per-super-tile bucket counts (wave-private LDS histograms, summed); 16 loads
@@ -447,11 +435,10 @@ __global__ __launch_bounds__(1024) void bucket_base_kernel(const uint32_t *tot, 
     }
 }
 
-// scatter: per 8192-key sub-tile, wave-level multi-split ranks plus one LDS
-// atomic per (wave, bucket) group, a bucket-order scan, an LDS sort, then
-// contiguous runs written at base + tile offset + running count.  Key order
-// inside a bucket is irrelevant to the counts, so the nondeterministic order of
-// the group atomics is harmless.
+// scatter: per 8192-key sub-tile, ranks from LDS atomics on the bucket counts,
+// a bucket-order scan, an LDS sort, then contiguous runs written at base + tile
+// offset + running count.  Key order inside a bucket is irrelevant to the
+// counts, so the nondeterministic order of the atomics is harmless.
 constexpr int kScatThreads = 512;
 constexpr int kSub = 8192;
 __global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, int chunk_k, int kmax) {
@@ -467,7 +454,6 @@ __global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, i
     __shared__ uint32_t wsum[kW];
     if (chunk_k >= (int)ps.hdr->n_chunks && chunk_k != kmax - 1) return;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const unsigned long long below = (1ull << lane) - 1ull;
     const int64_t ntiles = step_tiles(ps);
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         int seg;
@@ -495,14 +481,8 @@ __global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, i
 #pragma unroll
                 for (int u = 0; u < kPer; ++u) {
                     const bool valid = u * 64 + lane < rem && kv[u] != kNoKey;
-                    const uint32_t bkt = valid ? (kv[u] >> ps.shift) - bin0 : 0u;
-                    const unsigned long long m = match_bucket(bkt, ps.nbits, valid);
-                    const uint32_t before = (uint32_t)__popcll(m & below);
-                    const int leader = valid ? __ffsll((long long)m) - 1 : 0;
-                    uint32_t gb = 0u;
-                    if (valid && before == 0u) gb = atomicAdd(&cnt[bkt], (uint32_t)__popcll(m));
-                    gb = __shfl(gb, leader, 64);
-                    rk[u] = valid ? bkt << 16 | (gb + before) : ~0u;
+                    const uint32_t bkt = (kv[u] >> ps.shift) - bin0;
+                    rk[u] = valid ? bkt << 16 | atomicAdd(&cnt[bkt], 1u) : ~0u;
                 }
             }
             __syncthreads();                                                  // 2
@@ -665,11 +645,6 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
     // one resident round: the particle loop is grid-strided and evenly loaded
     const unsigned key_grid = blocks_for(p.c.n, kBinBlock, resident_grid(keys_kernel<T>, kBinBlock, cus));
 
-    auto bits_of = [](int nb) {
-        int b = 0;
-        while ((1 << b) < nb) ++b;
-        return b;
-    };
     PartStep l1{};
     l1.in = keysa;
     l1.out = keysb;
@@ -679,7 +654,6 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
     l1.cap = L.cap;
     l1.shift = L.s1;
     l1.nbins = L.nb1;
-    l1.nbits = bits_of(L.nb1);
     l1.tile_hist = thist;
     l1.bucket_tot = tot;
     l1.bucket_base = off1;
@@ -694,7 +668,6 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
     l2.seg_tiles = tiles1;
     l2.shift = kBlockShift;
     l2.nbins = L.nb2;
-    l2.nbits = bits_of(L.nb2);
     l2.bucket_base = offb;
 
     const unsigned hist_grid = resident_grid(tile_hist_kernel, kPartThreads, cus);
