@@ -35,6 +35,7 @@ constexpr int kPartThreads = 256;
 constexpr int kMaxBins = 512;                    // buckets per partition level
 constexpr int kGroup = 8192;                     // particles per counting group
 constexpr int kAccThreads = 512;
+constexpr int kAccUnroll = 16;
 
 struct PartHeader {
     unsigned long long reserved;  // key slots reserved by the key pass of the current chunk
@@ -535,18 +536,41 @@ __global__ __launch_bounds__(kAccThreads) void accumulate_kernel(const uint32_t 
         if (lo == hi) continue;  // uniform over the block
         for (int j = threadIdx.x; j < kBlockCells; j += kAccThreads) h[j] = 0u;
         __syncthreads();
-        for (uint32_t i = lo + threadIdx.x; i < hi; i += kAccThreads) atomicAdd(&h[keys[i] & (kBlockCells - 1)], 1u);
+        // 16 key loads in flight per thread
+        for (uint32_t base = lo; base < hi; base += kAccThreads * kAccUnroll) {
+            uint32_t kk[kAccUnroll];
+#pragma unroll
+            for (int u = 0; u < kAccUnroll; ++u) {
+                const uint32_t i = base + u * kAccThreads + threadIdx.x;
+                kk[u] = i < hi ? keys[i] : kNoKey;
+            }
+#pragma unroll
+            for (int u = 0; u < kAccUnroll; ++u)
+                if (kk[u] != kNoKey) atomicAdd(&h[kk[u] & (kBlockCells - 1)], 1u);
+        }
         __syncthreads();
         const int64_t c0 = blk * kBlockCells;
         const int64_t cn = c0 + kBlockCells < ncells ? kBlockCells : ncells - c0;  // multiple of 4
         uint4 *dst = reinterpret_cast<uint4 *>(counts + c0);
-        for (int64_t j = threadIdx.x; j < cn / 4; j += kAccThreads) {
-            uint4 v = dst[j];
-            v.x += h[4 * j];
-            v.y += h[4 * j + 1];
-            v.z += h[4 * j + 2];
-            v.w += h[4 * j + 3];
-            dst[j] = v;
+        const int nq = (int)(cn / 4);
+        // the block's 16-byte words, all read before any is written back
+        constexpr int kPerThread = kBlockCells / 4 / kAccThreads;
+        uint4 v[kPerThread];
+#pragma unroll
+        for (int u = 0; u < kPerThread; ++u) {
+            const int j = u * kAccThreads + threadIdx.x;
+            if (j < nq) v[u] = dst[j];
+        }
+#pragma unroll
+        for (int u = 0; u < kPerThread; ++u) {
+            const int j = u * kAccThreads + threadIdx.x;
+            if (j < nq) {
+                v[u].x += h[4 * j];
+                v[u].y += h[4 * j + 1];
+                v[u].z += h[4 * j + 2];
+                v[u].w += h[4 * j + 3];
+                dst[j] = v[u];
+            }
         }
         __syncthreads();
     }
@@ -672,6 +696,7 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
 
     const unsigned hist_grid = resident_grid(tile_hist_kernel, kPartThreads, cus);
     const unsigned scat_grid = resident_grid(scatter_kernel, kScatThreads, cus);
+    const unsigned acc_grid = resident_grid(accumulate_kernel, kAccThreads, cus);
     for (int k = 0; k < L.kmax; ++k) {
         hipLaunchKernelGGL(reset_chunk_kernel, dim3(1), dim3(64), 0, s, hdr);
         kp.k = k;
@@ -692,7 +717,7 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
                            k, L.kmax);
         hipLaunchKernelGGL(scatter_kernel, dim3(scat_grid), dim3(kScatThreads), 0, s, l2, k, L.kmax);
         timer_mark(timer, UFALCON_PHASE_PARTITION, s);
-        hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)std::min<int64_t>(L.nblk, cus * 8)), dim3(kAccThreads), 0,
+        hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)std::min<int64_t>(L.nblk, acc_grid)), dim3(kAccThreads), 0,
                            s, keysa, offb, L.nblk, ncells, p.c.counts, hdr, k, L.kmax);
         timer_mark(timer, UFALCON_PHASE_ACCUMULATE, s);
     }
