@@ -316,6 +316,16 @@ __device__ __forceinline__ void seg_range(const PartStep &ps, int64_t t, int &se
     hi = lo + kSuper < (int64_t)ps.seg_off[a + 1] ? lo + kSuper : (int64_t)ps.seg_off[a + 1];
 }
 
+// Workgroup barrier that orders LDS only.  __syncthreads() also makes every
+// thread wait for its own outstanding global stores, which the partition
+// kernels never need: no thread reads global memory that another thread of the
+// workgroup wrote during the launch.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // per-super-tile bucket counts (wave-private LDS histograms, summed); 16 loads
 // in flight per thread
 constexpr int kHistUnroll = 16;
@@ -332,7 +342,7 @@ __global__ __launch_bounds__(kPartThreads) void tile_hist_kernel(PartStep ps, in
         const uint32_t bin0 = (uint32_t)seg * (uint32_t)ps.nbins;
         for (int b = tid; b < ps.nbins; b += kPartThreads)
             for (int k = 0; k < kW; ++k) wh[k][b] = 0u;
-        __syncthreads();
+        lds_barrier();
         for (int64_t base = lo; base < hi; base += (int64_t)kPartThreads * kHistUnroll) {
             uint32_t kk[kHistUnroll];
 #pragma unroll
@@ -344,14 +354,14 @@ __global__ __launch_bounds__(kPartThreads) void tile_hist_kernel(PartStep ps, in
             for (int u = 0; u < kHistUnroll; ++u)
                 if (kk[u] != kNoKey) atomicAdd(&wh[w][(kk[u] >> ps.shift) - bin0], 1u);
         }
-        __syncthreads();
+        lds_barrier();
         uint32_t *row = ps.tile_hist + t * (int64_t)ps.nbins;
         for (int b = tid; b < ps.nbins; b += kPartThreads) {
             uint32_t c = 0;
             for (int k = 0; k < kW; ++k) c += wh[k][b];
             row[b] = c;
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -436,6 +446,7 @@ __global__ __launch_bounds__(1024) void bucket_base_kernel(const uint32_t *tot, 
     }
 }
 
+
 // scatter: per 8192-key sub-tile, ranks from LDS atomics on the bucket counts,
 // a bucket-order scan, an LDS sort, then contiguous runs written at base + tile
 // offset + running count.  Key order inside a bucket is irrelevant to the
@@ -451,6 +462,7 @@ __global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, i
     __shared__ uint32_t gbase[kMaxBins];     // global start of this super-tile's run per bucket
     __shared__ uint32_t run[kMaxBins];       // keys of the bucket written by earlier sub-tiles
     __shared__ uint32_t soff[kMaxBins + 1];  // bucket start inside the sorted sub-tile
+    __shared__ uint32_t dst[kMaxBins];       // global position of sorted slot 0 of the bucket (mod 2^32)
     __shared__ uint32_t skeys[kSub];
     __shared__ uint32_t wsum[kW];
     if (chunk_k >= (int)ps.hdr->n_chunks && chunk_k != kmax - 1) return;
@@ -468,7 +480,7 @@ __global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, i
         for (int64_t sub = lo; sub < hi; sub += kSub) {
             const int64_t shi = sub + kSub < hi ? sub + kSub : hi;
             if (tid < ps.nbins) cnt[tid] = 0u;
-            __syncthreads();                                                  // 1
+            lds_barrier();                                                  // 1
             // rank pass; rk = bucket << 16 | rank inside the bucket, ~0 for no key.
             // Loads are unconditional at clamped indices so that all of them are in
             // flight together; a wave with no keys in the sub-tile skips them.
@@ -486,7 +498,7 @@ __global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, i
                     rk[u] = valid ? bkt << 16 | atomicAdd(&cnt[bkt], 1u) : ~0u;
                 }
             }
-            __syncthreads();                                                  // 2
+            lds_barrier();                                                  // 2
             const uint32_t c = tid < ps.nbins ? cnt[tid] : 0u;
             uint32_t x = c;  // inclusive scan within the wave, bucket order = thread order
             for (int off = 1; off < 64; off <<= 1) {
@@ -494,19 +506,22 @@ __global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, i
                 if (lane >= off) x += y;
             }
             if (lane == 63) wsum[w] = x;
-            __syncthreads();                                                  // 3
+            lds_barrier();                                                  // 3
             uint32_t acc = x - c;
             for (int k = 0; k < w; ++k) acc += wsum[k];
-            if (tid < ps.nbins) soff[tid] = acc;
+            if (tid < ps.nbins) {
+                soff[tid] = acc;
+                dst[tid] = gbase[tid] + run[tid] - acc;
+            }
             if (tid == kScatThreads - 1) soff[ps.nbins] = acc + c;
-            __syncthreads();                                                  // 4
+            lds_barrier();                                                  // 4
             // the keys placed in bucket order
             if (rem > 0) {
 #pragma unroll
                 for (int u = 0; u < kPer; ++u)
                     if (rk[u] != ~0u) skeys[soff[rk[u] >> 16] + (rk[u] & 0xFFFFu)] = kv[u];
             }
-            __syncthreads();                                                  // 5
+            lds_barrier();                                                  // 5
             const uint32_t nv = soff[ps.nbins];
             if (nv > 0) {
                 // unrolled, reads at clamped indices, so that the LDS reads overlap
@@ -514,12 +529,11 @@ __global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, i
                 for (int j = 0; j < kPer; ++j) {
                     const uint32_t sidx = (uint32_t)(j * kScatThreads + tid);
                     const uint32_t key = skeys[min(sidx, nv - 1u)];
-                    const uint32_t b = (key >> ps.shift) - bin0;
-                    const uint32_t pos = gbase[b] + run[b] + (sidx - soff[b]);
+                    const uint32_t pos = dst[(key >> ps.shift) - bin0] + sidx;
                     if (sidx < nv) ps.out[pos] = key;
                 }
             }
-            __syncthreads();                                                  // 6
+            lds_barrier();                                                  // 6
             if (tid < ps.nbins) run[tid] += soff[tid + 1] - soff[tid];
         }
     }
@@ -535,7 +549,7 @@ __global__ __launch_bounds__(kAccThreads) void accumulate_kernel(const uint32_t 
         const uint32_t lo = offb[blk], hi = offb[blk + 1];
         if (lo == hi) continue;  // uniform over the block
         for (int j = threadIdx.x; j < kBlockCells; j += kAccThreads) h[j] = 0u;
-        __syncthreads();
+        lds_barrier();
         // 16 key loads in flight per thread
         for (uint32_t base = lo; base < hi; base += kAccThreads * kAccUnroll) {
             uint32_t kk[kAccUnroll];
@@ -548,7 +562,7 @@ __global__ __launch_bounds__(kAccThreads) void accumulate_kernel(const uint32_t 
             for (int u = 0; u < kAccUnroll; ++u)
                 if (kk[u] != kNoKey) atomicAdd(&h[kk[u] & (kBlockCells - 1)], 1u);
         }
-        __syncthreads();
+        lds_barrier();
         const int64_t c0 = blk * kBlockCells;
         const int64_t cn = c0 + kBlockCells < ncells ? kBlockCells : ncells - c0;  // multiple of 4
         uint4 *dst = reinterpret_cast<uint4 *>(counts + c0);
@@ -572,7 +586,7 @@ __global__ __launch_bounds__(kAccThreads) void accumulate_kernel(const uint32_t 
                 dst[j] = v[u];
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
