@@ -95,7 +95,8 @@ def parse():
     ap.add_argument("--particles", type=int, default=1 << 27)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 23)
-    ap.add_argument("--batched", action="store_true", help="also time the batched form against plain calls")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched form against plain calls (16 realisations, 2.6e9 particles)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of known size (for PMC byte-counter scaling)")
     return ap.parse_args()
@@ -154,6 +155,8 @@ def main():
     ev_bin1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ev_born0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ev_born1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev_adj0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev_adj1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     outs = {}
 
     def step(k=None):
@@ -172,7 +175,11 @@ def main():
         if k is not None:
             ev_born1[k].record(stream)
         g = kap * 2.0  # dL/dkappa of L = sum kappa^2
+        if k is not None:
+            ev_adj0[k].record(stream)
         gW = uf.born_kappa_adjoint(counts, inb, g)
+        if k is not None:
+            ev_adj1[k].record(stream)
         gth = uf.lensing_weights_vjp(dW, gW)
         outs.update(kappa=kap, W=W, gW=gW, gth=gth, inb=inb)
 
@@ -188,6 +195,7 @@ def main():
     ms_per_step = 1e3 * wall / args.steps
     bin_ms = sum(a.elapsed_time(b) for a, b in zip(ev_bin0, ev_bin1)) / args.steps
     born_ms = sum(a.elapsed_time(b) for a, b in zip(ev_born0, ev_born1)) / args.steps
+    adj_ms = sum(a.elapsed_time(b) for a, b in zip(ev_adj0, ev_adj1)) / args.steps
     st = uf.status_dict(status)
     inst_per_step = st["n_instances"] / args.steps
 
@@ -259,6 +267,11 @@ def main():
             "frac_hbm": born_bytes / (born_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
             "maps_per_s": 1e3 / born_ms,
         },
+        "adjoint": {
+            "launch_ms": adj_ms,
+            "achieved_GBs": born_bytes / (adj_ms / 1e3) / 1e9,  # counts + dL/dkappa (FP32) read once
+            "frac_hbm": born_bytes / (adj_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+        },
         "instances_per_s": inst_per_step / (ms_per_step / 1e3),
         "guarded_per_step": st["n_guarded"] / args.steps,
         "unresolved": st["n_unresolved"],
@@ -269,7 +282,11 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, y, z, edges, nside, L, R, args.cpu_sample, n)
 
-    if args.batched:
+    if not args.no_batched:
+        # release the step's buffers first: the batched workload holds ~100 GB
+        del x, y, z, counts, ws, outs, kap
+        uf.release_workspaces()
+        torch.cuda.empty_cache()
         line["batched"] = batched_vs_plain(dev)
 
     print(json.dumps(line), flush=True)

@@ -156,6 +156,11 @@ def npix(nside: int) -> int:
 _ws_cache = {}
 
 
+def release_workspaces():
+    """Drop the cached workspaces (their memory returns to torch's allocator)."""
+    _ws_cache.clear()
+
+
 def _workspace(nbytes: int, device, key: str):
     """A cached device byte buffer of at least nbytes (256-byte aligned by the caching allocator)."""
     k = (key, str(device))
