@@ -160,6 +160,9 @@ int64_t oracle_bin_fast(const void *xs, const void *ys, const void *zs, int is_f
                     double dy = by + (double)sy * L;
                     double dz = bz + (double)sz * L;
                     double r2 = dx * dx + dy * dy + dz * dz;
+                    /* outside the range by more than the guard: no shell, no flag */
+                    if (r2 < e2[0] * (1.0 - 2.0 * REL_GUARD) || r2 > e2[nb] * (1.0 + 2.0 * REL_GUARD))
+                        continue;
                     int flag = 0, b = -1;
                     /* plain linear scan over the edges of [b0, b1] */
                     for (int j = 0; j <= nb; ++j) {
@@ -198,5 +201,79 @@ int64_t oracle_bin_fast(const void *xs, const void *ys, const void *zs, int is_f
         stats[0] += ninst;
         stats[1] += ninvalid;
     }
+    return nflag;
+}
+
+/*
+ * Per-shell instance totals (section 2.4 eq. (8) alone, no pixelisation):
+ * totals[b - b0] += number of instances of particles [i0, i1) with
+ * e_b <= |d| < e_{b+1}.  Instances whose r^2 lies within the relative guard of
+ * an edge are not counted; they are returned in `flagged` (as in
+ * oracle_bin_fast) for an exact decision.  Returns the number flagged;
+ * stats[1] += particles with a non-finite coordinate.
+ */
+int64_t oracle_shell_totals(const void *xs, const void *ys, const void *zs, int is_f64,
+                            int64_t i0, int64_t i1,
+                            double ox, double oy, double oz, double L, int R,
+                            const double *edges, int b0, int b1,
+                            int64_t *totals, int64_t *flagged, int64_t flag_cap,
+                            int64_t *stats, int atomic)
+{
+    const int W = 2 * R + 1;
+    double e2[1025];
+    int64_t nflag = 0, ninvalid = 0;
+    for (int j = b0; j <= b1; ++j)
+        e2[j - b0] = edges[j] * edges[j];
+    const int nb = b1 - b0;
+    int64_t local[1024];
+    for (int j = 0; j < nb; ++j)
+        local[j] = 0;
+
+    for (int64_t i = i0; i < i1; ++i) {
+        double x = load(xs, is_f64, i), y = load(ys, is_f64, i), z = load(zs, is_f64, i);
+        if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
+            ++ninvalid;
+            continue;
+        }
+        double bx = x - ox, by = y - oy, bz = z - oz;
+        for (int sx = -R; sx <= R; ++sx)
+            for (int sy = -R; sy <= R; ++sy)
+                for (int sz = -R; sz <= R; ++sz) {
+                    double dx = bx + (double)sx * L;
+                    double dy = by + (double)sy * L;
+                    double dz = bz + (double)sz * L;
+                    double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 < e2[0] * (1.0 - 2.0 * REL_GUARD) || r2 > e2[nb] * (1.0 + 2.0 * REL_GUARD))
+                        continue;
+                    int flag = 0, b = -1;
+                    for (int j = 0; j <= nb; ++j) {
+                        if (fabs(r2 - e2[j]) <= REL_GUARD * e2[j]) {
+                            flag = 1;
+                            break;
+                        }
+                        if (e2[j] <= r2)
+                            b = j;
+                    }
+                    if (flag) {
+                        if (nflag < flag_cap) {
+                            flagged[2 * nflag] = i;
+                            flagged[2 * nflag + 1] = ((int64_t)(sx + R) * W + (sy + R)) * W + (sz + R);
+                        }
+                        ++nflag;
+                    } else if (b >= 0 && b < nb) {
+                        ++local[b];
+                    }
+                }
+    }
+    for (int j = 0; j < nb; ++j) {
+        if (atomic)
+            __atomic_fetch_add(&totals[j], local[j], __ATOMIC_RELAXED);
+        else
+            totals[j] += local[j];
+    }
+    if (atomic)
+        __atomic_fetch_add(&stats[1], ninvalid, __ATOMIC_RELAXED);
+    else
+        stats[1] += ninvalid;
     return nflag;
 }

@@ -48,6 +48,13 @@ def _load():
                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                 ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int]
+            lib.oracle_shell_totals.restype = ctypes.c_int64
+            lib.oracle_shell_totals.argtypes = [
+                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                ctypes.c_int64, ctypes.c_int64,
+                ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int]
             lib.oracle_fast_ring_pixel.restype = ctypes.c_int
             lib.oracle_fast_ring_pixel.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                                    ctypes.c_double, ctypes.POINTER(ctypes.c_int64)]
@@ -184,6 +191,71 @@ def bin_shells(x, y, z, observer, box_L: float, n_rep: int, edges, nside: int,
                 counts[res[0] - b0, res[1]] += 1
                 stats["instances"] += 1
     return counts, stats
+
+
+def shell_totals(x, y, z, observer, box_L: float, n_rep: int, edges, shell_begin: int = 0,
+                 shell_end: int | None = None, threads: int = 1, flag_cap: int = 1 << 20):
+    """Instances per shell, int64 [shell_end - shell_begin] (section 2.4 eq. (8) alone):
+    the row sums of bin_shells' count maps, without the pixelisation.  Guarded
+    radii are decided exactly.  Returns (totals, stats) like bin_shells."""
+    xs, ys, zs = _as_np(x), _as_np(y), _as_np(z)
+    e = check_edges(edges)
+    nshell = len(e) - 1
+    b0 = int(shell_begin)
+    b1 = nshell if shell_end is None else int(shell_end)
+    if not (0 <= b0 <= b1 <= nshell):
+        raise ValueError("bad shell range")
+    n = xs.shape[0]
+    totals = np.zeros(b1 - b0, dtype=np.int64)
+    stats = {"instances": 0, "invalid": 0, "flagged": 0}
+    if n == 0 or b0 == b1:
+        return totals, stats
+    lib = _load()
+    is_f64 = 1 if xs.dtype == np.float64 else 0
+    e_arr = np.asarray(e, dtype=np.float64)
+    ox, oy, oz = (float(v) for v in observer)
+    R = int(n_rep)
+    W = 2 * R + 1
+    threads = max(1, min(int(threads), n))
+    bounds = [n * k // threads for k in range(threads + 1)]
+    st = np.zeros(2, dtype=np.int64)
+    results = [None] * threads
+
+    def work(k, cap):
+        fl = np.zeros((cap, 2), dtype=np.int64)
+        nf = lib.oracle_shell_totals(xs.ctypes.data, ys.ctypes.data, zs.ctypes.data, is_f64,
+                                     bounds[k], bounds[k + 1], ox, oy, oz, float(box_L), R,
+                                     e_arr.ctypes.data, b0, b1, totals.ctypes.data,
+                                     fl.ctypes.data, cap, st.ctypes.data, 1 if threads > 1 else 0)
+        results[k] = (nf, fl)
+
+    def run_all(cap):
+        ts = [threading.Thread(target=work, args=(k, cap)) for k in range(threads)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+
+    run_all(flag_cap)
+    if any(r[0] > flag_cap for r in results):
+        need = max(r[0] for r in results)
+        totals[:] = 0
+        st[:] = 0
+        run_all(need)
+    stats["invalid"] = int(st[1])
+    for nf, fl in results:
+        for i, code in fl[:nf]:
+            sz = code % W - R
+            sy = (code // W) % W - R
+            sx = code // (W * W) - R
+            d = instance_vector(float(xs[i]), float(ys[i]), float(zs[i]), (ox, oy, oz), float(box_L),
+                                (sx, sy, sz))
+            b = exact_shell(d, e, b0, b1)
+            stats["flagged"] += 1
+            if b is not None:
+                totals[b - b0] += 1
+    stats["instances"] = int(totals.sum())
+    return totals, stats
 
 
 def bin_shells_bruteforce(x, y, z, observer, box_L, n_rep, edges, nside, shell_begin=0, shell_end=None):

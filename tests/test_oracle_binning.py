@@ -138,3 +138,34 @@ def test_empty_and_degenerate():
         bn.bin_shells(e, e, e, (0, 0, 0), 1.0, 0, [1.0, 1.0], 1)
     with pytest.raises(ValueError):
         bn.bin_shells(e, e, e, (0, 0, 0), 1.0, 0, [0.0, 1.0], 0)
+
+
+@pytest.mark.parametrize("R,threads", [(0, 1), (1, 3), (2, 4)])
+def test_shell_totals_against_radial_histogram_and_maps(R, threads):
+    # per-shell totals without the pixelisation: the independent numpy histogram
+    # and the row sums of the count maps
+    L = 100.0
+    x, y, z = synth.lognormal_box(30000, L, seed=11, ngrid=16)
+    edges = [0.0, 12.0, 31.0, 55.0, 90.0, 140.0, 190.0][: 4 + R]
+    obs = (50.0, 50.0, 50.0)
+    tot, st = bn.shell_totals(x, y, z, obs, L, R, edges, threads=threads)
+    ref = _radial_histogram(x.numpy(), y.numpy(), z.numpy(), obs, L, R, edges)
+    assert np.array_equal(tot, ref)
+    counts, _ = bn.bin_shells(x, y, z, obs, L, R, edges, 4, threads=threads)
+    assert np.array_equal(tot, counts.sum(axis=1))
+    assert st["instances"] == int(tot.sum())
+
+
+def test_shell_totals_edge_particles_and_range():
+    # radii exactly on edges go to the shell they open (half-open shells), and a
+    # shell sub-range counts only its own shells
+    edges = [0.0, 1.0, 2.0, 3.0]
+    obs = (10.0, 10.0, 10.0)
+    xs = np.array([11.0, 12.0, 13.0, 10.0, 10.0, 10.5], dtype=np.float64)
+    ys = np.array([10.0, 10.0, 10.0, 10.0, 7.0, 10.0], dtype=np.float64)
+    zs = np.array([10.0, 10.0, 10.0, 12.0, 10.0, 10.0], dtype=np.float64)
+    tot, st = bn.shell_totals(xs, ys, zs, obs, 100.0, 0, edges)
+    assert tot.tolist() == [1, 1, 2]
+    assert st["flagged"] == 5
+    tot12, _ = bn.shell_totals(xs, ys, zs, obs, 100.0, 0, edges, shell_begin=1, shell_end=3)
+    assert tot12.tolist() == [1, 2]
