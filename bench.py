@@ -52,11 +52,11 @@ FLOPS_PER_INSTANCE = 80
 # reports traffic null.
 PMC_TRAFFIC = {
     "kernel": "keys_kernel<float>",
-    "fetch_kib": 786897.8,
-    "write_kib": 5066878.8,
+    "fetch_kib": 786740.0,
+    "write_kib": 5073815.4,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
-    "sources_sha1": "6f86d456c53f1d11f88c156bf894df3198802b67",
+    "sources_sha1": "01233e9448f96658123b1aba5ee1d7ec36d10121",
     "profile": "profiles/keys_kernel_lognormal512_z05_nside1024_pmc.md",
 }
 
