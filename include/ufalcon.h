@@ -261,6 +261,12 @@ typedef enum ufalcon_accumulation {
 } ufalcon_accumulation;
 
 /*
+ * Realisations may share a count map: snapshots bound to disjoint shell ranges of
+ * one map (section 2.4's nested boxes), or subvolumes binned into the same shells
+ * (counts add).  Realisations whose written rows overlap are binned one after
+ * another; the Born launch of such a plan computes each realisation's kappa from
+ * its whole map (use T = 0 and one ufalcon_born_kappa call on the shared map).
+ *
  * tile: particles per work item of the persistent kernel (0 = default, or the
  * autotuner's choice under UFALCON_ACCUMULATE_AUTO); persistent_wgs: its
  * workgroups (0 likewise); accumulation: ufalcon_accumulation.

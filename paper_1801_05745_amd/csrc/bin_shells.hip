@@ -400,6 +400,7 @@ struct ufalcon_batch_plan {
     hipStream_t aux_stream = nullptr;
     hipEvent_t fork_event = nullptr, join_event = nullptr;
     std::vector<hipEvent_t> keys_done;
+    bool shared_rows = false;  // two realisations write overlapping count rows: one lane, in order
     std::vector<BinParams> item_params;  // per-item parameters for the partitioned path
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -551,11 +552,25 @@ extern "C" int ufalcon_batch_plan_create(const ufalcon_batch_item *items, int32_
         }
     }
     p->total_tiles = tiles;
+    // count rows written by each realisation (its shell range of its map); the
+    // partitioned block updates are not atomic, so realisations whose rows
+    // overlap (subvolumes of one map) must not run on different lanes
+    for (int32_t a = 0; a < n_items && !p->shared_rows; ++a)
+        for (int32_t b = a + 1; b < n_items; ++b) {
+            const uintptr_t a0 = (uintptr_t)(items[a].counts + (int64_t)items[a].shell_begin * p->npix);
+            const uintptr_t a1 = (uintptr_t)(items[a].counts + (int64_t)items[a].shell_end * p->npix);
+            const uintptr_t b0 = (uintptr_t)(items[b].counts + (int64_t)items[b].shell_begin * p->npix);
+            const uintptr_t b1 = (uintptr_t)(items[b].counts + (int64_t)items[b].shell_end * p->npix);
+            if (a0 < a1 && b0 < b1 && a0 < b1 && b0 < a1) {
+                p->shared_rows = true;
+                break;
+            }
+        }
     p->work_bytes = kGuardHeader + (size_t)65536 * sizeof(GuardEntry);
     if (part_need > 0) {
         p->part_bytes = part_need;
         bool ok = hipMalloc(&p->d_part, part_need) == hipSuccess;
-        if (ok && p->item_params.size() > 1) {
+        if (ok && p->item_params.size() > 1 && !p->shared_rows) {  // the second lane
             ok = hipMalloc(&p->d_part2, part_need) == hipSuccess &&
                  hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking) == hipSuccess &&
                  hipEventCreateWithFlags(&p->fork_event, hipEventDisableTiming) == hipSuccess &&
@@ -621,13 +636,15 @@ extern "C" int ufalcon_bin_shells_batched(ufalcon_batch_plan *plan, ufalcon_stat
     if (plan->accumulation == UFALCON_ACCUMULATE_PARTITIONED) {
         hipStream_t s0 = as_stream(stream);
         const size_t m = plan->item_params.size();
-        if (m == 1) {
-            BinParams bp = plan->item_params[0];
-            bp.status = status;
-            int rc = UFALCON_OK;
-            if (!try_partitioned(bp, plan->dtype, plan->d_part, plan->part_bytes, s0, &rc, nullptr))
-                return UFALCON_EWORKSPACE;
-            return rc;
+        if (m == 1 || plan->shared_rows) {  // one lane, realisations in order
+            for (BinParams bp : plan->item_params) {
+                bp.status = status;
+                int rc = UFALCON_OK;
+                if (!try_partitioned(bp, plan->dtype, plan->d_part, plan->part_bytes, s0, &rc, nullptr))
+                    return UFALCON_EWORKSPACE;
+                if (rc) return rc;
+            }
+            return UFALCON_OK;
         }
         // two lanes: fork the aux stream from the caller's, alternate realisations,
         // chain the key passes, join at the end (also valid under stream capture)

@@ -106,3 +106,44 @@ def test_autotuned_plan_matches_plain(ufalcon):
         assert torch.equal(plain, it["counts"])
         assert torch.equal(uf.born_kappa(it["counts"], it["W"], it["inv_nbar"]), it["kappa"])
     plan.close()
+
+
+@pytest.mark.parametrize("method", ["partition", "atomic"])
+def test_snapshots_and_subvolumes_share_one_map(ufalcon, method):
+    # snapshot mode: three particle sets, each bound to its own shell range of one
+    # shared 8-shell map (nested boxes); subvolume mode: two particle sets binned
+    # into the same shells of one map, whose counts add (section 2.4)
+    nside = 16
+    edges = chi_edges_from_z(0.02, 0.12, 8)
+    ranges = [(0, 3), (3, 5), (5, 8)]
+    boxes = [(60.0, 0), (120.0, 1), (240.0, 2)]
+    shared = uf.new_counts(8, nside, DEV)
+    items, ref = [], np.zeros((8, 12 * nside * nside), dtype=np.int64)
+    for (L, seed), (b0, b1) in zip(boxes, ranges):
+        x, y, z = synth.lognormal_box(50000 + 7 * seed, L, seed=30 + seed, ngrid=16, dtype=torch.float32)
+        R = obin.default_n_rep(edges[b0:b1 + 1], L)
+        items.append(dict(x=x.to(DEV), y=y.to(DEV), z=z.to(DEV), chi_edges=edges, box_L=L, n_rep=R,
+                          shell_begin=b0, shell_end=b1, counts=shared))
+        c, _ = obin.bin_shells(x, y, z, (L / 2,) * 3, L, R, edges, nside, shell_begin=b0, shell_end=b1, threads=8)
+        ref[b0:b1] += c
+    plan = uf.BatchPlan(items, nside, T=0, tile=8192, method=method)
+    plan.clear()
+    plan.bin()
+    torch.cuda.synchronize()
+    assert np.array_equal(shared.cpu().numpy().astype(np.int64), ref)
+    plan.close()
+
+    L = 100.0
+    x, y, z = synth.lognormal_box(90001, L, seed=40, ngrid=16, dtype=torch.float32)
+    sub = uf.new_counts(8, nside, DEV)
+    R = obin.default_n_rep(edges, L)
+    halves = [slice(0, 45000), slice(45000, 90001)]
+    items = [dict(x=x[h].contiguous().to(DEV), y=y[h].contiguous().to(DEV), z=z[h].contiguous().to(DEV),
+                  chi_edges=edges, box_L=L, n_rep=R, counts=sub) for h in halves]
+    plan = uf.BatchPlan(items, nside, T=0, tile=8192, method=method)
+    plan.clear()
+    plan.bin()
+    torch.cuda.synchronize()
+    ref2, _ = obin.bin_shells(x, y, z, (L / 2,) * 3, L, R, edges, nside, threads=8)
+    assert np.array_equal(sub.cpu().numpy().astype(np.int64), ref2)
+    plan.close()
