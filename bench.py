@@ -52,11 +52,11 @@ FLOPS_PER_INSTANCE = 80
 # reports traffic null.
 PMC_TRAFFIC = {
     "kernel": "keys_kernel<float>",
-    "fetch_kib": 786740.0,
-    "write_kib": 5073815.4,
+    "fetch_kib": 786742.4,
+    "write_kib": 5073814.8,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
-    "sources_sha1": "01233e9448f96658123b1aba5ee1d7ec36d10121",
+    "sources_sha1": "b1a106bfc479856d2203a4c37a9a02c96a428786",
     "profile": "profiles/keys_kernel_lognormal512_z05_nside1024_pmc.md",
 }
 
@@ -199,6 +199,18 @@ def main():
     st = uf.status_dict(status)
     inst_per_step = st["n_instances"] / args.steps
 
+    # projected overdensity (eq. (7)) on the last step's map: the same streaming
+    # pass with weights Delta chi_b / sum Delta chi_b, timed on its own
+    ev_od = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    uf.overdensity(counts, edges, outs["inb"])
+    ev_od[0].record(stream)
+    for _ in range(3):
+        delta = uf.overdensity(counts, edges, outs["inb"])
+    ev_od[1].record(stream)
+    torch.cuda.synchronize()
+    od_ms = ev_od[0].elapsed_time(ev_od[1]) / 3
+    del delta
+
     kap = outs["kappa"].double()
     rms = float(kap.pow(2).mean().sqrt())
     max_over_rms = float(kap.abs().max()) / rms
@@ -266,6 +278,11 @@ def main():
             "achieved_GBs": born_bytes / (born_ms / 1e3) / 1e9,
             "frac_hbm": born_bytes / (born_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
             "maps_per_s": 1e3 / born_ms,
+        },
+        "overdensity": {
+            "launch_ms": od_ms,
+            "achieved_GBs": born_bytes / (od_ms / 1e3) / 1e9,
+            "frac_hbm": born_bytes / (od_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         },
         "adjoint": {
             "launch_ms": adj_ms,

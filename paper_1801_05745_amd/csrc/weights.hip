@@ -15,6 +15,7 @@
 // so dW comes out exactly for the discretised integrals (forward mode).
 #include "../../include/ufalcon.h"
 #include "internal.hpp"
+#include "gl_rules.hpp"
 
 namespace ufx {
 
@@ -100,57 +101,15 @@ __device__ __forceinline__ dual dlog(dual a) {
 }
 
 // ------------------------------------------------------------------ Gauss-Legendre
+// Nodes and weights on [-1, 1], tabulated once from 60-digit roots of P_n.
 constexpr int kGL_D = 32;   // D(z) on [0, z]
 constexpr int kGL_O = 16;   // outer integral over a shell
 constexpr int kGL_I = 48;   // inner n(z) integral over [z, z_max]
 constexpr int kGL_N = 16;   // per panel of the n(z) normalisation
 constexpr int kNormPanels = 14;
-
-struct GLRule {
-    double x[48], w[48];
-};
-
-// nodes/weights of the n-point rule on [-1, 1] (Newton on P_n from Chebyshev-like guesses)
-__device__ void gl_rule(int n, double *x, double *w, int i) {
-    double t = cos(M_PI * (i + 0.75) / (n + 0.5));
-    double dp = 1.0;
-    for (int it = 0; it < 100; ++it) {
-        double p0 = 1.0, p1 = t;
-        for (int k = 2; k <= n; ++k) {
-            const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
-            p0 = p1;
-            p1 = p2;
-        }
-        dp = n * (t * p1 - p0) / (t * t - 1.0);
-        const double dt = p1 / dp;
-        t -= dt;
-        if (fabs(dt) < 1e-17) break;
-    }
-    double p0 = 1.0, p1 = t;
-    for (int k = 2; k <= n; ++k) {
-        const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
-        p0 = p1;
-        p1 = p2;
-    }
-    dp = n * (t * p1 - p0) / (t * t - 1.0);
-    x[i] = t;
-    w[i] = 2.0 / ((1.0 - t * t) * dp * dp);
-}
-
-struct Rules {
-    double xD[kGL_D], wD[kGL_D];
-    double xO[kGL_O], wO[kGL_O];
-    double xI[kGL_I], wI[kGL_I];
-    double xN[kGL_N], wN[kGL_N];
-};
-
-__device__ void build_rules(Rules *r) {
-    const int i = threadIdx.x;
-    if (i < kGL_D) gl_rule(kGL_D, r->xD, r->wD, i);
-    else if (i < kGL_D + kGL_O) gl_rule(kGL_O, r->xO, r->wO, i - kGL_D);
-    else if (i < kGL_D + kGL_O + kGL_I) gl_rule(kGL_I, r->xI, r->wI, i - kGL_D - kGL_O);
-    else if (i < kGL_D + kGL_O + kGL_I + kGL_N) gl_rule(kGL_N, r->xN, r->wN, i - kGL_D - kGL_O - kGL_I);
-}
+static_assert(sizeof(kGLDx) == kGL_D * sizeof(double) && sizeof(kGLOx) == kGL_O * sizeof(double) &&
+                  sizeof(kGLIx) == kGL_I * sizeof(double) && sizeof(kGLNx) == kGL_N * sizeof(double),
+              "rule sizes");
 
 // ------------------------------------------------------------------ cosmology in duals
 __device__ __forceinline__ dual inv_E(dual z, dual om) {
@@ -158,41 +117,43 @@ __device__ __forceinline__ dual inv_E(dual z, dual om) {
     return dconst(1.0) / dsqrt(om * (a * a * a) + (1.0 + (-1.0) * om));
 }
 
-__device__ dual D_of_z(dual z, dual om, const Rules *r) {
+__device__ dual D_of_z(dual z, dual om) {
     dual s = dconst(0.0);
+#pragma unroll 4
     for (int i = 0; i < kGL_D; ++i) {
-        const dual zi = (0.5 * (1.0 + r->xD[i])) * z;
-        s = s + r->wD[i] * inv_E(zi, om);
+        const dual zi = (0.5 * (1.0 + kGLDx[i])) * z;
+        s = s + kGLDw[i] * inv_E(zi, om);
     }
     return 0.5 * (z * s);
 }
 
-__device__ double D_of_z_plain(double z, double om, const Rules *r) {
+__device__ double D_of_z_plain(double z, double om) {
     double s = 0.0;
+#pragma unroll 8
     for (int i = 0; i < kGL_D; ++i) {
-        const double zi = 0.5 * (1.0 + r->xD[i]) * z;
+        const double zi = 0.5 * (1.0 + kGLDx[i]) * z;
         const double a = 1.0 + zi;
-        s += r->wD[i] / sqrt(om * a * a * a + 1.0 - om);
+        s += kGLDw[i] / sqrt(om * a * a * a + 1.0 - om);
     }
     return 0.5 * z * s;
 }
 
 // z with D(z) = Dt: Newton in plain FP64, then two dual Newton steps that carry
 // the tangents (dz = -(dD/dtheta - dDt) E at the root).
-__device__ dual z_of_D(dual Dt, dual om, const Rules *r) {
+__device__ dual z_of_D(dual Dt, dual om) {
     // start from the second-order expansion D = z - (3/4) Om z^2 inverted, then Newton;
     // stop once the step is at the rounding level (quadratic convergence takes ~4 steps)
     double z = Dt.v * (1.0 + 0.75 * om.v * Dt.v);
     for (int it = 0; it < 40; ++it) {
         const double a = 1.0 + z;
         const double E = sqrt(om.v * a * a * a + 1.0 - om.v);
-        const double dz = (D_of_z_plain(z, om.v, r) - Dt.v) * E;
+        const double dz = (D_of_z_plain(z, om.v) - Dt.v) * E;
         z -= dz;
         if (fabs(dz) <= 1e-15 * (1.0 + z)) break;
     }
     dual zd = dconst(z);
     for (int it = 0; it < 2; ++it) {
-        const dual f = D_of_z(zd, om, r) - Dt;
+        const dual f = D_of_z(zd, om) - Dt;
         const dual invE = inv_E(zd, om);
         zd = zd - f / invE;
     }
@@ -222,15 +183,32 @@ struct WeightParams {
     double D[UFALCON_MAX_SHELLS + 1];  // edges in units of c/H0
 };
 
-// One block per (t, b).  Threads: outer node o = tid / 16, inner lane l = tid % 16.
-__global__ __launch_bounds__(256) void lensing_weights_kernel(WeightParams p) {
-    __shared__ Rules rules;
-    __shared__ dual red[256];
-    __shared__ dual norm_s;
+// Sum of one dual per thread over a kWThreads block, in a fixed tree order (the
+// result does not depend on scheduling).  `red` holds kWThreads duals.
+constexpr int kWThreads = kGL_O * kGL_I;  // one thread per (outer, inner) node pair
+static_assert(kWThreads == 768 && kNormPanels * kGL_N <= kWThreads, "block shape");
+
+__device__ dual block_sum(dual v, dual *red) {
+    const int tid = threadIdx.x;
+    red[tid] = v;
+    __syncthreads();
+    if (tid < 256) red[tid] = red[tid] + red[tid + 256] + red[tid + 512];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = red[tid] + red[tid + s];
+        __syncthreads();
+    }
+    const dual r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// One block per (t, b).  Thread (o, i) = (tid / kGL_I, tid % kGL_I) evaluates
+// outer node o of the shell and inner node i of the n(z) integral at z(D_o).
+__global__ __launch_bounds__(kWThreads) void lensing_weights_kernel(WeightParams p) {
+    __shared__ dual red[kWThreads];
     __shared__ dual zmax_D_s;
     const int t = blockIdx.x / p.B, b = blockIdx.x % p.B;
-    build_rules(&rules);
-    __syncthreads();
 
     const SrcParams sp = p.src[t];
     const dual om = dvar(p.om, 0);
@@ -239,27 +217,20 @@ __global__ __launch_bounds__(256) void lensing_weights_kernel(WeightParams p) {
     dual alpha = dvar(sp.alpha, 1), beta = dvar(sp.beta, 2), z0 = dvar(sp.z0, 3);
 
     // normalisation of n(z) on graded panels [0, zmax 2^-13], ..., [zmax/2, zmax]
+    dual norm = dconst(1.0);
     if (!delta) {
         dual s = dconst(0.0);
-        const int nodes = kNormPanels * kGL_N;
-        if (tid < nodes) {
+        if (tid < kNormPanels * kGL_N) {
             const int pnl = tid / kGL_N, i = tid % kGL_N;
             const double hi = sp.zmax * ldexp(1.0, -(kNormPanels - 1 - pnl));
             const double lo = pnl == 0 ? 0.0 : 0.5 * hi;
-            const double zi = lo + 0.5 * (hi - lo) * (1.0 + rules.xN[i]);
-            s = (0.5 * (hi - lo) * rules.wN[i]) * smail_n(dconst(zi), alpha, beta, z0);
+            const double zi = lo + 0.5 * (hi - lo) * (1.0 + kGLNx[i]);
+            s = (0.5 * (hi - lo) * kGLNw[i]) * smail_n(dconst(zi), alpha, beta, z0);
         }
-        red[tid] = s;
-        __syncthreads();
-        if (tid == 0) {
-            dual acc = dconst(0.0);
-            for (int k = 0; k < 256; ++k) acc = acc + red[k];  // fixed order
-            norm_s = acc;
-            zmax_D_s = D_of_z(dconst(sp.zmax), om, &rules);
-        }
-        __syncthreads();
+        norm = block_sum(s, red);
+        if (tid == 0) zmax_D_s = D_of_z(dconst(sp.zmax), om);
     } else if (tid == 0) {
-        zmax_D_s = D_of_z(dvar(sp.zs, 1), om, &rules);  // D_s, depends on Om and z_s
+        zmax_D_s = D_of_z(dvar(sp.zs, 1), om);  // D_s, depends on Om and z_s
     }
     __syncthreads();
 
@@ -272,36 +243,30 @@ __global__ __launch_bounds__(256) void lensing_weights_kernel(WeightParams p) {
     else if (Dcut.v < Dhi.v) Dhi = Dcut;
 
     dual contrib = dconst(0.0);
-    const int o = tid / 16, l = tid % 16;
+    const int o = tid / kGL_I, i = tid % kGL_I;
     if (!empty) {
         const dual half = 0.5 * (Dhi + (-1.0) * dconst(Dlo));
-        const dual Dk = dconst(Dlo) + (1.0 + rules.xO[o]) * half;
-        const dual zk = z_of_D(Dk, om, &rules);
+        const dual Dk = dconst(Dlo) + (1.0 + kGLOx[o]) * half;
         if (delta) {
-            if (l == 0) {
+            if (i == 0) {
+                const dual zk = z_of_D(Dk, om);
                 const dual q = 1.0 + (-1.0) * (Dk / Dcut);
-                contrib = (rules.wO[o] * half) * ((1.0 + zk) * (Dk * q));
+                contrib = (kGLOw[o] * half) * ((1.0 + zk) * (Dk * q));
             }
         } else {
-            // inner integral over [zk, zmax], nodes l, l+16, l+32
+            // inner node i of the integral over [zk, zmax]
+            const dual zk = z_of_D(Dk, om);
             const dual span = 0.5 * (dconst(sp.zmax) - zk);
-            dual inner = dconst(0.0);
-            for (int i = l; i < kGL_I; i += 16) {
-                const dual zi = zk + (1.0 + rules.xI[i]) * span;
-                const dual Di = D_of_z(zi, om, &rules);
-                const dual nz = smail_n(zi, alpha, beta, z0);
-                inner = inner + rules.wI[i] * (nz * (1.0 + (-1.0) * (Dk / Di)));
-            }
-            inner = span * inner;
-            contrib = (rules.wO[o] * half) * ((1.0 + zk) * (Dk * inner));
+            const dual zi = zk + (1.0 + kGLIx[i]) * span;
+            const dual Di = D_of_z(zi, om);
+            const dual nz = smail_n(zi, alpha, beta, z0);
+            const dual inner = (kGLIw[i] * span) * (nz * (1.0 + (-1.0) * (Dk / Di)));
+            contrib = (kGLOw[o] * half) * ((1.0 + zk) * (Dk * inner));
         }
     }
-    red[tid] = contrib;
-    __syncthreads();
+    dual acc = block_sum(contrib, red);
     if (tid == 0) {
-        dual acc = dconst(0.0);
-        for (int k = 0; k < 256; ++k) acc = acc + red[k];
-        if (!delta) acc = acc / norm_s;
+        if (!delta) acc = acc / norm;
         const dual Wd = (1.5 * om) * acc;
         p.W[t * p.B + b] = empty ? 0.0 : Wd.v;
         if (p.dW)
@@ -310,11 +275,8 @@ __global__ __launch_bounds__(256) void lensing_weights_kernel(WeightParams p) {
 }
 
 __global__ void comoving_distance_kernel(const double *z, int64_t n, double om, double *chi) {
-    __shared__ Rules rules;
-    build_rules(&rules);
-    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) chi[i] = kCoverH0 * D_of_z_plain(z[i], om, &rules);
+    if (i < n) chi[i] = kCoverH0 * D_of_z_plain(z[i], om);
 }
 
 __global__ void weights_vjp_kernel(const double *dW, const double *gW, int32_t T, int32_t B, double *out) {
@@ -396,7 +358,7 @@ extern "C" int ufalcon_lensing_weights(double omega_m, const ufalcon_source *sou
         }
     }
     for (int j = 0; j <= n_shells; ++j) p.D[j] = chi_edges[j] / kCoverH0;
-    hipLaunchKernelGGL(lensing_weights_kernel, dim3(T * n_shells), dim3(256), 0, as_stream(stream), p);
+    hipLaunchKernelGGL(lensing_weights_kernel, dim3(T * n_shells), dim3(kWThreads), 0, as_stream(stream), p);
     UFX_HIP_CHECK(hipGetLastError());
     return UFALCON_OK;
 }
