@@ -8,6 +8,7 @@ never imports it.
   healpix    exact RING ang2pix / pix2ang and an independent projection brute force
   binning    FP64 C particle loop with guard bands + exact resolution of flagged instances
   cosmology  D(z), lensing weights (delta and Smail n(z) sources), nbar, kappa, adjoint
+  spectra    spherical-harmonic coefficients, C_l and their covariance over realisations
 """
 
-from . import binning, cosmology, healpix  # noqa: F401
+from . import binning, cosmology, healpix, spectra  # noqa: F401
