@@ -316,6 +316,54 @@ int ufalcon_batch_autotune(const ufalcon_batch_item *items, int32_t n_items, int
                            int out_dtype, int32_t sample_items, ufalcon_batch_tuning *tuning,
                            ufalcon_stream_t stream);
 
+/*
+ * Spherical-harmonic coefficients of HEALPix RING maps (section 3.1: the
+ * harmonic analysis behind the power spectrum of eq. (9), done there with
+ * ANAFAST up to lmax = 3 Nside - 1).  The pixel quadrature
+ *   a_lm = (4 pi / N_pix) sum_p map_p conj(Y_lm(theta_p, phi_p)),  0 <= m <= l <= lmax,
+ * at the pixel centres, Y_lm with the Condon-Shortley phase, evaluated in
+ * FP64 with a fixed reduction order (bitwise reproducible).
+ * maps device [n_maps][12 Nside^2] of dtype (UFALCON_F32 | UFALCON_F64);
+ * alm device double [n_maps][n_alm][2] (re, im), n_alm = (lmax+1)(lmax+2)/2,
+ * m-major: index m (2 lmax + 1 - m) / 2 + l.  Any lmax in [0, 4 * 8192] is
+ * accepted (beyond 3 Nside - 1 the quadrature aliases, as ANAFAST's does).
+ * workspace device, at least ufalcon_map2alm_workspace_size(nside, lmax)
+ * bytes (0 for invalid arguments): ring sums, lambda_mm seeds and recurrence
+ * coefficients, about 16 (lmax+1)(4 Nside) + 12 (lmax+1)(2 Nside) + 16 n_alm
+ * bytes (~350 MB at Nside 1024, lmax 3071).  Returns UFALCON_EINVAL for bad
+ * arguments, UFALCON_ENSIDE, UFALCON_EWORKSPACE if the workspace is short.
+ */
+size_t ufalcon_map2alm_workspace_size(int64_t nside, int32_t lmax);
+int ufalcon_map2alm(const void *maps, int dtype, int32_t n_maps, int64_t nside, int32_t lmax, double *alm,
+                    void *workspace, size_t workspace_bytes, ufalcon_stream_t stream);
+
+/*
+ * Angular power spectrum from the coefficients of a real map (section 3.1
+ * eq. (9), the average over m standing for the ensemble average):
+ *   C_l = (|a_l0|^2 + 2 sum_{m=1}^{l} |a_lm|^2) / (2l + 1).
+ * alm device as written by ufalcon_map2alm; cl device double [n_maps][lmax+1].
+ */
+int ufalcon_alm2cl(const double *alm, int32_t n_maps, int32_t lmax, double *cl, ufalcon_stream_t stream);
+
+/*
+ * Covariance and correlation of power spectra over realisations (section 3.2
+ * eqs. (10) and (11)).  Band b averages C_l over l in
+ * [ell_min + b delta_ell, ell_min + (b+1) delta_ell) (the paper bins by
+ * delta_ell = 4, 10, 24); then
+ *   band_mean[b] = (1/R) sum_r X[r][b]
+ *   cov[b][c]    = sum_r (X[r][b] - band_mean[b]) (X[r][c] - band_mean[c]) / (R - ddof)
+ *   corr[b][c]   = cov[b][c] / (sqrt(cov[b][b]) sqrt(cov[c][c]))   (NaN where a variance is 0)
+ * (eq. (10) as printed multiplies two averages; the product is averaged here).
+ * cl device double [n_real][n_ell]; band_mean device [n_bands]; cov, corr
+ * device [n_bands][n_bands] (corr may be NULL); ddof 0 or 1, n_real > ddof;
+ * ell_min + n_bands * delta_ell <= n_ell; n_bands <= 65535.  workspace device,
+ * at least ufalcon_cl_covariance_workspace_size() bytes (the band powers).
+ */
+size_t ufalcon_cl_covariance_workspace_size(int32_t n_real, int32_t n_bands);
+int ufalcon_cl_covariance(const double *cl, int32_t n_real, int32_t n_ell, int32_t ell_min, int32_t delta_ell,
+                          int32_t n_bands, int32_t ddof, double *band_mean, double *cov, double *corr,
+                          void *workspace, size_t workspace_bytes, ufalcon_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

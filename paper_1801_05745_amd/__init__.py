@@ -97,6 +97,11 @@ _SIGS = {
     "ufalcon_batch_run_graph": (ctypes.c_int, [_P, _P, _P]),
     "ufalcon_batch_autotune": (ctypes.c_int, [ctypes.POINTER(BatchItem), _I32, ctypes.c_int, _I64, _I32, ctypes.c_int,
                                               _I32, _P, _P]),
+    "ufalcon_map2alm_workspace_size": (_SZ, [_I64, _I32]),
+    "ufalcon_map2alm": (ctypes.c_int, [_P, ctypes.c_int, _I32, _I64, _I32, _P, _P, _SZ, _P]),
+    "ufalcon_alm2cl": (ctypes.c_int, [_P, _I32, _I32, _P, _P]),
+    "ufalcon_cl_covariance_workspace_size": (_SZ, [_I32, _I32]),
+    "ufalcon_cl_covariance": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _SZ, _P]),
 }
 
 
@@ -419,6 +424,81 @@ def born_kappa_adjoint(counts, inv_nbar_, grad_kappa):
                                           _ptr(out), _ptr(ws), ws.numel(), _stream(counts.device)),
            "ufalcon_born_kappa_adjoint")
     return out
+
+
+# ---------------------------------------------------------------- power spectra
+
+def n_alm(lmax: int) -> int:
+    return (int(lmax) + 1) * (int(lmax) + 2) // 2
+
+
+def map2alm(maps, lmax=None):
+    """a_lm of HEALPix RING maps [n_maps][npix] (or one map [npix]), complex128
+    [n_maps][n_alm] in m-major order (index m (2 lmax + 1 - m)/2 + l);
+    lmax defaults to 3 Nside - 1."""
+    lib = load()
+    m = maps.contiguous()
+    single = m.dim() == 1
+    if single:
+        m = m[None, :]
+    nmaps, npx = m.shape
+    nside = int(round((npx / 12) ** 0.5))
+    if npix(nside) != npx:
+        raise ValueError(f"{npx} is not a HEALPix pixel count")
+    if lmax is None:
+        lmax = 3 * nside - 1
+    nbytes = int(lib.ufalcon_map2alm_workspace_size(nside, int(lmax)))
+    if nbytes == 0:
+        raise ValueError("invalid nside or lmax")
+    ws = _workspace(nbytes, m.device, "map2alm")
+    out = torch.empty((nmaps, n_alm(lmax), 2), dtype=torch.float64, device=m.device)
+    _check(lib.ufalcon_map2alm(_ptr(m), _dtype_code(m.dtype), nmaps, nside, int(lmax), _ptr(out), _ptr(ws),
+                               ws.numel(), _stream(m.device)), "ufalcon_map2alm")
+    out = torch.view_as_complex(out)
+    return out[0] if single else out
+
+
+def alm2cl(alm, lmax):
+    """C_l [n_maps][lmax+1] from complex128 coefficients [n_maps][n_alm] (or [n_alm])."""
+    lib = load()
+    a = alm.contiguous()
+    single = a.dim() == 1
+    if single:
+        a = a[None, :]
+    if a.shape[1] != n_alm(lmax) or a.dtype != torch.complex128:
+        raise ValueError("alm must be complex128 [n_maps][(lmax+1)(lmax+2)/2]")
+    out = torch.empty((a.shape[0], int(lmax) + 1), dtype=torch.float64, device=a.device)
+    _check(lib.ufalcon_alm2cl(_ptr(torch.view_as_real(a)), a.shape[0], int(lmax), _ptr(out), _stream(a.device)),
+           "ufalcon_alm2cl")
+    return out[0] if single else out
+
+
+def anafast(maps, lmax=None):
+    """Power spectra C_l of maps [n_maps][npix] (or [npix]); lmax defaults to 3 Nside - 1."""
+    npx = maps.shape[-1]
+    nside = int(round((npx / 12) ** 0.5))
+    if lmax is None:
+        lmax = 3 * nside - 1
+    return alm2cl(map2alm(maps, lmax), lmax)
+
+
+def cl_covariance(cl, ell_min=0, delta_ell=1, n_bands=None, ddof=1, with_corr=True):
+    """(band means [n_bands], covariance [n_bands][n_bands], correlation or None) of
+    power spectra cl [n_real][n_ell] over the realisations."""
+    lib = load()
+    c = cl.to(torch.float64).contiguous()
+    R, n_ell = c.shape
+    if n_bands is None:
+        n_bands = (n_ell - ell_min) // delta_ell
+    nbytes = int(lib.ufalcon_cl_covariance_workspace_size(R, int(n_bands)))
+    ws = _workspace(max(nbytes, 1), c.device, "cl_covariance")
+    mean = torch.empty(n_bands, dtype=torch.float64, device=c.device)
+    cov = torch.empty((n_bands, n_bands), dtype=torch.float64, device=c.device)
+    corr = torch.empty_like(cov) if with_corr else None
+    _check(lib.ufalcon_cl_covariance(_ptr(c), R, n_ell, int(ell_min), int(delta_ell), int(n_bands), int(ddof),
+                                     _ptr(mean), _ptr(cov), _ptr(corr), _ptr(ws), ws.numel(), _stream(c.device)),
+           "ufalcon_cl_covariance")
+    return mean, cov, corr
 
 
 # ---------------------------------------------------------------- autograd

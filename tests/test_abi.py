@@ -111,3 +111,31 @@ def test_batch_autotune_validation():
     # an unknown accumulation is rejected before anything is allocated
     plan = ctypes.c_void_p()
     assert lib.ufalcon_batch_plan_create(items, 1, 0, 16, 1, 0, 0, 0, 3, ctypes.byref(plan)) == -1
+
+
+def test_spectra_validation():
+    lib = uf.load()
+    EINVAL, ENSIDE, EWORKSPACE = -1, -3, -5
+    assert lib.ufalcon_map2alm_workspace_size(0, 10) == 0
+    assert lib.ufalcon_map2alm_workspace_size(4, -1) == 0
+    small = lib.ufalcon_map2alm_workspace_size(4, 11)
+    assert small > 0 and lib.ufalcon_map2alm_workspace_size(4, 40) > small
+    assert lib.ufalcon_map2alm(FAKE, 0, 1, 0, 11, FAKE, FAKE, small, None) == ENSIDE
+    assert lib.ufalcon_map2alm(FAKE, 2, 1, 4, 11, FAKE, FAKE, small, None) == EINVAL
+    assert lib.ufalcon_map2alm(FAKE, 0, 1, 4, -2, FAKE, FAKE, small, None) == EINVAL
+    assert lib.ufalcon_map2alm(FAKE, 0, 0, 4, 11, None, None, 0, None) == 0       # nothing to do
+    assert lib.ufalcon_map2alm(FAKE, 0, 1, 4, 11, FAKE, FAKE, small - 1, None) == EWORKSPACE
+    assert lib.ufalcon_alm2cl(FAKE, 1, -1, FAKE, None) == EINVAL
+    assert lib.ufalcon_alm2cl(None, 1, 5, FAKE, None) == EINVAL
+    assert lib.ufalcon_cl_covariance_workspace_size(0, 4) == 0
+    ws = lib.ufalcon_cl_covariance_workspace_size(10, 4)
+    assert ws == 10 * 4 * 8
+
+    def cov(R=10, n_ell=20, l0=0, dl=5, nb=4, ddof=1, ws_bytes=ws):
+        return lib.ufalcon_cl_covariance(FAKE, R, n_ell, l0, dl, nb, ddof, FAKE, FAKE, None, FAKE, ws_bytes, None)
+
+    assert cov(ddof=2) == EINVAL
+    assert cov(R=1, ddof=1) == EINVAL
+    assert cov(l0=1) == EINVAL          # bands run past n_ell
+    assert cov(dl=0) == EINVAL
+    assert cov(ws_bytes=ws - 8) == EWORKSPACE
