@@ -52,11 +52,11 @@ FLOPS_PER_INSTANCE = 80
 # reports traffic null.
 PMC_TRAFFIC = {
     "kernel": "keys_kernel<float>",
-    "fetch_kib": 786742.4,
-    "write_kib": 5073814.8,
+    "fetch_kib": 786743.9,
+    "write_kib": 5073815.0,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
-    "sources_sha1": "b1a106bfc479856d2203a4c37a9a02c96a428786",
+    "sources_sha1": "dc30a2a736041df1730ea7a2bcfe447bb4bc6555",
     "profile": "profiles/keys_kernel_lognormal512_z05_nside1024_pmc.md",
 }
 
@@ -100,6 +100,19 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of known size (for PMC byte-counter scaling)")
     return ap.parse_args()
+
+
+def sht_flops(nside, lmax):
+    """Algorithmic FP64 flops of one map2alm: the ring DFTs as four direct
+    length-n/4 DFTs per ring (4 flops per real-by-complex multiply-add) and
+    the Legendre step, 7 flops per (l, m, ring pair): the three-term
+    recurrence (3) and the complex multiply-add with the folded ring sum (4)."""
+    N = nside
+    n_alm = (lmax + 1) * (lmax + 2) // 2
+    legendre = 7 * n_alm * 2 * N
+    dft_eq = (2 * N + 1) * 4 * N * N * 4
+    dft_polar = sum(2 * 4 * i * i * 4 for i in range(1, N))
+    return float(legendre + dft_eq + dft_polar)
 
 
 def main():
@@ -211,6 +224,39 @@ def main():
     od_ms = ev_od[0].elapsed_time(ev_od[1]) / 3
     del delta
 
+    # angular power spectrum of the last step's kappa map (section 3.1: ANAFAST
+    # to lmax = 3 Nside - 1) and the covariance of 150 spectra (section 3.2),
+    # each timed on its own
+    lmax = 3 * nside - 1
+    kmap = outs["kappa"][0]
+    ev_sh = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    alm = uf.map2alm(kmap, lmax)
+    cl = uf.alm2cl(alm, lmax)
+    ev_sh[0].record(stream)
+    for _ in range(3):
+        alm = uf.map2alm(kmap, lmax)
+    ev_sh[1].record(stream)
+    for _ in range(3):
+        cl = uf.alm2cl(alm, lmax)
+    ev_sh[2].record(stream)
+    torch.cuda.synchronize()
+    sht_ms = ev_sh[0].elapsed_time(ev_sh[1]) / 3
+    cl_ms = ev_sh[1].elapsed_time(ev_sh[2]) / 3
+    sht_fl = sht_flops(nside, lmax)
+    n_real = 150
+    jitter = synth.uniform64(n_real * (lmax + 1), seed=5, stream=7, device=dev).reshape(n_real, lmax + 1)
+    cls = cl[None, :] * (0.5 + jitter)
+    ev_cv = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    uf.cl_covariance(cls)
+    ev_cv[0].record(stream)
+    for _ in range(3):
+        _, cov, corr = uf.cl_covariance(cls)
+    ev_cv[1].record(stream)
+    torch.cuda.synchronize()
+    cov_ms = ev_cv[0].elapsed_time(ev_cv[1]) / 3
+    del alm, cls, cov, corr
+    uf.release_workspaces()
+
     kap = outs["kappa"].double()
     rms = float(kap.pow(2).mean().sqrt())
     max_over_rms = float(kap.abs().max()) / rms
@@ -289,6 +335,18 @@ def main():
             "achieved_GBs": born_bytes / (adj_ms / 1e3) / 1e9,  # counts + dL/dkappa (FP32) read once
             "frac_hbm": born_bytes / (adj_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         },
+        "power_spectrum": {
+            "kernel": "ufalcon_map2alm (ring DFTs + Legendre contraction, FP64) + ufalcon_alm2cl",
+            "nside": nside, "lmax": lmax,
+            "map2alm_ms": sht_ms, "alm2cl_ms": cl_ms,
+            "maps_per_s": 1e3 / (sht_ms + cl_ms),
+            "algorithmic_flops": sht_fl,
+            "achieved": sht_fl / (sht_ms / 1e3) / 1e12,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": sht_fl / (sht_ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+        },
+        "cl_covariance": {"realisations": n_real, "bands": lmax + 1, "launch_ms": cov_ms},
         "instances_per_s": inst_per_step / (ms_per_step / 1e3),
         "guarded_per_step": st["n_guarded"] / args.steps,
         "unresolved": st["n_unresolved"],

@@ -13,11 +13,10 @@
 // bitwise reproducible.
 //
 // Kernels:
-//   ring_dft_kernel     one lane per m, RG rings of equal length per workgroup:
-//                       the map chunk is staged in LDS (FP32 or FP64 in, FP64
-//                       out) and read as broadcasts; the twiddle e^{-2 pi i m j/n}
-//                       advances by one complex multiply per pixel and is
-//                       re-seeded exactly from (m j mod n) every kDftJ pixels;
+//   ring_dft_kernel     ring DFTs by one radix-4 decimation (every ring holds
+//                       4 n4 pixels): one lane per k' < n4, RG rings of equal
+//                       length per workgroup, the map chunk staged in LDS (FP32
+//                       or FP64 in, FP64 out) and read as broadcasts;
 //   lambda_seed_kernel  lambda_mm(z) of every ring pair for m = 0..lmax, carried
 //                       as value * 2^{-600 k} so sin^m(theta) cannot underflow;
 //   legendre_kernel     one workgroup per (m, block of 256 R ring pairs): the
@@ -32,11 +31,14 @@ namespace {
 
 constexpr int kDftThreads = 256;
 constexpr int kDftJ = 64;      // pixels per staged chunk (and twiddle re-seed period)
-constexpr int kEqRings = 16;   // equatorial rings (all 4N long) per workgroup
+constexpr int kEqRings = 4;    // equatorial rings (all 4N long) per workgroup
 constexpr int kLegThreads = 256;
-constexpr int kLegR = 8;       // ring pairs per lane
+constexpr int kLegR = 4;       // ring pairs per lane
 constexpr int kLegC = 8;       // l values per reduction chunk
-static_assert(2 * kLegC * 16 == kLegThreads, "reduction layout: 16 lanes per output");
+constexpr int kLegStage = 128; // l values per coefficient stage in LDS
+constexpr int kLegBufs = 2;    // reduction buffers (1: two barriers per chunk)
+constexpr int kLegLanes = kLegThreads / (2 * kLegC);  // lanes summing one output
+static_assert(kLegLanes * 2 * kLegC == kLegThreads && (kLegLanes & (kLegLanes - 1)) == 0, "reduction layout");
 constexpr double kScaleUp = 0x1p600;
 constexpr double kScaleDown = 0x1p-600;
 constexpr double kTiny = 0x1p-300;
@@ -69,22 +71,29 @@ __device__ __forceinline__ void ring_z_sin(int64_t N, int64_t i, double &z, doub
 }
 
 // ------------------------------------------------------------------ ring sums
+// Every ring has n = 4 n4 pixels, so its DFT splits by decimation into four
+// DFTs of length n4 over the pixels j = 4j' + q:
+//   D_q[k'] = sum_{j'} x[4j' + q] e^{-2 pi i k' j' / n4},          k' < n4
+//   DFT[k' + t n4] = sum_q (-i)^{t q} e^{-2 pi i k' q / n} D_q[k'],   t = 0..3
+// and F(m) = e^{-i pi m s / n} DFT[m mod n] (aliasing for m >= n).  Lane k'
+// accumulates D_0..D_3 of RG rings of equal length (the twiddle advancing by
+// one complex multiply per j', re-seeded exactly every kDftJ steps), then
+// writes F(m) for every m = k' + t n4 + u n <= lmax.
 template <typename T, bool kPolar>
 __global__ __launch_bounds__(kDftThreads) void ring_dft_kernel(const T *__restrict__ map, int64_t N, int32_t lmax,
                                                                double2 *__restrict__ F) {
     constexpr int RG = kPolar ? 2 : kEqRings;
-    __shared__ double xs[RG][kDftJ];
-    const int m = blockIdx.x * kDftThreads + threadIdx.x;
+    __shared__ double xs[RG][4][kDftJ];
     const int64_t nring = 4 * N - 1;
     int64_t ring[RG];
     bool valid[RG];
-    int64_t n;
+    int64_t n4;
     if (kPolar) {
         const int64_t i = (int64_t)blockIdx.y + 1;
         ring[0] = i;
         ring[RG - 1] = 4 * N - i;
         valid[0] = valid[RG - 1] = true;
-        n = 4 * i;
+        n4 = i;
     } else {
         const int64_t i0 = N + (int64_t)blockIdx.y * RG;
 #pragma unroll
@@ -92,35 +101,42 @@ __global__ __launch_bounds__(kDftThreads) void ring_dft_kernel(const T *__restri
             valid[g] = i0 + g <= 3 * N;
             ring[g] = valid[g] ? i0 + g : 3 * N;
         }
-        n = 4 * N;
+        n4 = N;
     }
+    if ((int64_t)blockIdx.x * kDftThreads >= n4) return;  // whole workgroup past this ring length
+    const int64_t kp = (int64_t)blockIdx.x * kDftThreads + threadIdx.x;  // k'
+    const int64_t n = 4 * n4;
     int64_t first[RG];
 #pragma unroll
     for (int g = 0; g < RG; ++g) first[g] = ring_first(N, ring[g]);
 
-    double ar[RG], ai[RG];
+    double ar[RG][4], ai[RG][4];
 #pragma unroll
-    for (int g = 0; g < RG; ++g) ar[g] = ai[g] = 0.0;
-    // step e^{-2 pi i m / n}
-    double ws, wc;
-    sincospi(-2.0 * (double)((int64_t)m % n) / (double)n, &ws, &wc);
+    for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ar[g][q] = ai[g][q] = 0.0;
+    double ws, wc;  // step e^{-2 pi i k' / n4}
+    sincospi(-2.0 * (double)(kp % n4) / (double)n4, &ws, &wc);
 
-    for (int64_t jb = 0; jb < n; jb += kDftJ) {
-        const int cnt = (int)(n - jb < kDftJ ? n - jb : kDftJ);
-        for (int e = threadIdx.x; e < RG * kDftJ; e += kDftThreads) {
-            const int g = e / kDftJ, jj = e % kDftJ;
-            xs[g][jj] = jj < cnt ? (double)map[first[g] + jb + jj] : 0.0;
+    for (int64_t jb = 0; jb < n4; jb += kDftJ) {
+        const int cnt = (int)(n4 - jb < kDftJ ? n4 - jb : kDftJ);
+        for (int e = threadIdx.x; e < RG * 4 * kDftJ; e += kDftThreads) {
+            const int g = e / (4 * kDftJ), r = e % (4 * kDftJ);  // r = 4 jj + q: pixels in order
+            const int jj = r / 4, q = r % 4;
+            xs[g][q][jj] = jj < cnt ? (double)map[first[g] + 4 * jb + r] : 0.0;
         }
         __syncthreads();
         double wr, wi;
-        sincospi(-2.0 * (double)(((int64_t)m * jb) % n) / (double)n, &wi, &wr);
+        sincospi(-2.0 * (double)((kp * jb) % n4) / (double)n4, &wi, &wr);
         for (int jj = 0; jj < cnt; ++jj) {
 #pragma unroll
-            for (int g = 0; g < RG; ++g) {
-                const double x = xs[g][jj];
-                ar[g] = fma(x, wr, ar[g]);
-                ai[g] = fma(x, wi, ai[g]);
-            }
+            for (int g = 0; g < RG; ++g)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double x = xs[g][q][jj];
+                    ar[g][q] = fma(x, wr, ar[g][q]);
+                    ai[g][q] = fma(x, wi, ai[g][q]);
+                }
             const double nr = fma(wr, wc, -(wi * ws));
             const double ni = fma(wr, ws, wi * wc);
             wr = nr;
@@ -128,174 +144,266 @@ __global__ __launch_bounds__(kDftThreads) void ring_dft_kernel(const T *__restri
         }
         __syncthreads();
     }
-    if (m > lmax) return;
+    if (kp >= n4) return;
+    // e^{-2 pi i k' q / n}, q = 1, 2, 3
+    double s1, c1;
+    sincospi(-2.0 * (double)kp / (double)n, &s1, &c1);
+    const double c2 = c1 * c1 - s1 * s1, s2 = 2.0 * c1 * s1;
+    const double c3 = c2 * c1 - s2 * s1, s3 = c2 * s1 + s2 * c1;
 #pragma unroll
     for (int g = 0; g < RG; ++g) {
         if (!valid[g]) continue;
-        double re = ar[g], im = ai[g];
-        if (ring_shift(N, ring[g])) {  // e^{-i m pi / n}
-            double s, c;
-            sincospi(-(double)((int64_t)m % (2 * n)) / (double)n, &s, &c);
-            re = ar[g] * c - ai[g] * s;
-            im = ar[g] * s + ai[g] * c;
+        const double a0r = ar[g][0], a0i = ai[g][0];
+        const double a1r = ar[g][1] * c1 - ai[g][1] * s1, a1i = ar[g][1] * s1 + ai[g][1] * c1;
+        const double a2r = ar[g][2] * c2 - ai[g][2] * s2, a2i = ar[g][2] * s2 + ai[g][2] * c2;
+        const double a3r = ar[g][3] * c3 - ai[g][3] * s3, a3i = ar[g][3] * s3 + ai[g][3] * c3;
+        // radix-4 butterfly, (-i)(x + iy) = y - ix
+        double dr[4], di[4];
+        dr[0] = (a0r + a2r) + (a1r + a3r);
+        di[0] = (a0i + a2i) + (a1i + a3i);
+        dr[2] = (a0r + a2r) - (a1r + a3r);
+        di[2] = (a0i + a2i) - (a1i + a3i);
+        dr[1] = (a0r - a2r) + (a1i - a3i);
+        di[1] = (a0i - a2i) - (a1r - a3r);
+        dr[3] = (a0r - a2r) - (a1i - a3i);
+        di[3] = (a0i - a2i) + (a1r - a3r);
+        const bool shift = ring_shift(N, ring[g]) != 0;
+        const int64_t col = ring[g] - 1;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t k = kp + t * n4;  // k < n
+            if (k > lmax) break;
+            double gr = dr[t], gi = di[t];
+            if (shift) {  // e^{-i pi k / n}
+                double s, c;
+                sincospi(-(double)k / (double)n, &s, &c);
+                gr = dr[t] * c - di[t] * s;
+                gi = dr[t] * s + di[t] * c;
+            }
+            // F(k + u n) = (-1)^{u s} G(k)
+            for (int64_t m = k, u = 0; m <= lmax; m += n, ++u) {
+                const double sg = (shift && (u & 1)) ? -1.0 : 1.0;
+                F[m * nring + col] = make_double2(sg * gr, sg * gi);
+            }
         }
-        F[(int64_t)m * nring + (ring[g] - 1)] = make_double2(re, im);
     }
 }
 
 // ------------------------------------------------------------------ lambda_mm seeds
-__global__ void lambda_seed_kernel(int64_t N, int32_t lmax, double *__restrict__ seed, int32_t *__restrict__ seed_k) {
+// lambda_mm = -sqrt((2m+1)/(2m)) sin(theta) lambda_{m-1,m-1}; the factors are
+// shared by all rings and staged in LDS per chunk of kSeedThreads values of m.
+constexpr int kSeedThreads = 256;
+__global__ __launch_bounds__(kSeedThreads) void lambda_seed_kernel(int64_t N, int32_t lmax, double *__restrict__ seed,
+                                                                   int32_t *__restrict__ seed_k) {
+    __shared__ double fac[kSeedThreads];
     const int64_t npair = 2 * N;
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npair) return;
-    double z, st;
-    ring_z_sin(N, p + 1, z, st);
+    const int64_t p = (int64_t)blockIdx.x * kSeedThreads + threadIdx.x;
+    double z = 0.0, st = 0.0;
+    if (p < npair) ring_z_sin(N, p + 1, z, st);
     double v = 0.28209479177387814;  // 1/sqrt(4 pi)
     int32_t k = 0;
-    for (int m = 0; m <= lmax; ++m) {
-        seed[(int64_t)m * npair + p] = v;
-        seed_k[(int64_t)m * npair + p] = k;
-        v = v * (-sqrt((double)(2 * m + 3) / (double)(2 * m + 2))) * st;
-        if (v != 0.0 && fabs(v) < kTiny) {
-            v *= kScaleUp;
-            ++k;
+    for (int m0 = 0; m0 <= lmax; m0 += kSeedThreads) {
+        __syncthreads();
+        {
+            const int m = m0 + threadIdx.x;  // factor taking lambda_mm to lambda_{m+1,m+1}
+            fac[threadIdx.x] = -sqrt((double)(2 * m + 3) / (double)(2 * m + 2));
+        }
+        __syncthreads();
+        if (p >= npair) continue;
+        const int cnt = lmax - m0 + 1 < kSeedThreads ? lmax - m0 + 1 : kSeedThreads;
+        for (int c = 0; c < cnt; ++c) {
+            const int64_t idx = (int64_t)(m0 + c) * npair + p;
+            seed[idx] = v;
+            seed_k[idx] = k;
+            v = v * fac[c] * st;
+            if (v != 0.0 && fabs(v) < kTiny) {
+                v *= kScaleUp;
+                ++k;
+            }
         }
     }
 }
 
-// Recurrence coefficients per (m, l), packed like the coefficients:
-//   lambda_l = a_l z lambda_{l-1} - b_l lambda_{l-2}
-// l = m:   (0, -1)  with the state primed as (lambda_{l-2}, lambda_{l-1}) = (seed, 0)
-// l = m+1: (sqrt(2m+3), 0)
-// l > m+1: (c_l, c_l / c_{l-1}),  c_l = sqrt((4l^2-1)/(l^2-m^2)).
+// Recurrence coefficients per (m, l), packed like a_lm.  With
+// c_l = sqrt((4l^2 - 1)/(l^2 - m^2)) (c_{m+1} = sqrt(2m+3)), the recurrence
+// lambda_l = c_l z lambda_{l-1} - (c_l / c_{l-1}) lambda_{l-2} is run on
+// mu_l = lambda_l / sigma_l, sigma_l = prod of c_j from the start l0 of the
+// l-chunk (chunks of kLegC from m) to l:
+//   mu_l = z mu_{l-1} - g_l mu_{l-2},   g_l = 1 / c_{l-1}^2,
+// and the state (mu_{l-2}, mu_{l-1}) passes to the next chunk multiplied by
+// sigma at the chunk's last l.  Entry (g_l, sigma_l); at l = m the entry is
+// (-1, 1) with the state primed as (lambda_mm, 0), at l = m+1 it is (0, c_{m+1}).
 __global__ void legendre_coef_kernel(int32_t lmax, double2 *__restrict__ coef) {
     const int m = blockIdx.y;
-    const int l = m + blockIdx.x * blockDim.x + threadIdx.x;
-    if (l > lmax) return;
-    const int64_t idx = (int64_t)m * (2 * lmax + 1 - m) / 2 + l;
-    double a, b;
-    if (l == m) {
-        a = 0.0;
-        b = -1.0;
-    } else if (l == m + 1) {
-        a = sqrt((double)(2 * m + 3));
-        b = 0.0;
-    } else {
-        const double ll = l, mm = m, l1 = l - 1;
-        a = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mm * mm));
-        const double c1 = sqrt((4.0 * l1 * l1 - 1.0) / (l1 * l1 - mm * mm));
-        b = a / c1;
+    const int l0 = m + (blockIdx.x * blockDim.x + threadIdx.x) * kLegC;
+    if (l0 > lmax) return;
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const double mm = m;
+    double sig = 1.0;
+    for (int l = l0; l < l0 + kLegC && l <= lmax; ++l) {
+        double g, c;
+        if (l == m) {
+            g = -1.0;
+            c = 1.0;
+        } else {
+            const double ll = l;
+            c = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mm * mm));
+            if (l == m + 1) {
+                g = 0.0;
+            } else {
+                const double l1 = l - 1;
+                g = (l1 * l1 - mm * mm) / (4.0 * l1 * l1 - 1.0);  // 1 / c_{l-1}^2
+            }
+        }
+        sig *= c;
+        coef[base + l] = make_double2(g, sig);
     }
-    coef[idx] = make_double2(a, b);
 }
 
 // ------------------------------------------------------------------ Legendre contraction
+// State of the ring pairs one lane owns: z, the scaled recurrence pair
+// (mu_{l-2}, mu_{l-1}) times 2^{600 k}, and the folded ring sums E, O (zero
+// while k > 0, i.e. while the pair's lambda is below 2^-300).
+template <int R>
+struct PairState {
+    double z[R], prev[R], cur[R], er[R], ei[R], orr[R], oi[R];
+    int32_t k[R];
+};
+
+struct Folded {
+    double er, ei, orr, oi;
+};
+
+__device__ __forceinline__ Folded load_folded(const double2 *__restrict__ F, int64_t N, int64_t nring, int m,
+                                              int64_t p) {
+    const double2 fn = F[(int64_t)m * nring + p];
+    if (p + 1 == 2 * N) return {fn.x, fn.y, 0.0, 0.0};  // the equator is its own mirror
+    const double2 fs = F[(int64_t)m * nring + (nring - 1 - p)];
+    return {fn.x + fs.x, fn.y + fs.y, fn.x - fs.x, fn.y - fs.y};
+}
+
+template <int R>
 __global__ __launch_bounds__(kLegThreads) void legendre_kernel(const double2 *__restrict__ F,
                                                                const double *__restrict__ seed,
                                                                const int32_t *__restrict__ seed_k,
                                                                const double2 *__restrict__ coef, int64_t N,
                                                                int32_t lmax, double w, double2 *__restrict__ out,
                                                                int64_t out_stride) {
-    __shared__ double red[2 * kLegC][kLegThreads];
+    __shared__ double red[kLegBufs][2 * kLegC][kLegThreads];
     out += (int64_t)blockIdx.y * out_stride;
     const int m = blockIdx.x;
     const int tid = threadIdx.x;
     const int64_t npair = 2 * N, nring = 4 * N - 1;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
 
-    double z[kLegR], prev[kLegR], cur[kLegR], er[kLegR], ei[kLegR], orr[kLegR], oi[kLegR];
-    int32_t k[kLegR];
+    PairState<R> S;
+    bool dead = false;
 #pragma unroll
-    for (int r = 0; r < kLegR; ++r) {
-        const int64_t p = ((int64_t)blockIdx.y * kLegR + r) * kLegThreads + tid;
-        er[r] = ei[r] = orr[r] = oi[r] = 0.0;
-        z[r] = 0.0;
-        prev[r] = cur[r] = 0.0;
-        k[r] = 0;
+    for (int r = 0; r < R; ++r) {
+        const int64_t p = ((int64_t)blockIdx.y * R + r) * kLegThreads + tid;
+        S.er[r] = S.ei[r] = S.orr[r] = S.oi[r] = 0.0;
+        S.z[r] = S.prev[r] = S.cur[r] = 0.0;
+        S.k[r] = 0;
         if (p < npair) {
             double st;
-            ring_z_sin(N, p + 1, z[r], st);
-            prev[r] = seed[(int64_t)m * npair + p];
-            k[r] = seed_k[(int64_t)m * npair + p];
-            if (k[r] == 0) {
-                const double2 fn = F[(int64_t)m * nring + p];
-                const double2 fs = p + 1 == 2 * N ? make_double2(0.0, 0.0) : F[(int64_t)m * nring + (nring - 1 - p)];
-                if (p + 1 == 2 * N) {  // the equator is its own mirror
-                    er[r] = fn.x;
-                    ei[r] = fn.y;
-                } else {
-                    er[r] = fn.x + fs.x;
-                    ei[r] = fn.y + fs.y;
-                    orr[r] = fn.x - fs.x;
-                    oi[r] = fn.y - fs.y;
-                }
+            ring_z_sin(N, p + 1, S.z[r], st);
+            S.prev[r] = seed[(int64_t)m * npair + p];
+            S.k[r] = seed_k[(int64_t)m * npair + p];
+            if (S.k[r] == 0) {
+                const Folded f = load_folded(F, N, nring, m, p);
+                S.er[r] = f.er;
+                S.ei[r] = f.ei;
+                S.orr[r] = f.orr;
+                S.oi[r] = f.oi;
             }
         }
+        dead |= S.k[r] > 0;
     }
 
-    const int o = tid / 16, part = tid % 16;
-    for (int l0 = m; l0 <= lmax; l0 += kLegC) {
+    const int o = tid / kLegLanes, part = tid % kLegLanes;
+    // Coefficients pass through LDS in stages of kLegStage values of l (double
+    // buffered): the global load for the next stage is issued at the start of
+    // a stage and written to LDS half a stage later, hiding its latency.
+    __shared__ double2 cst[2][kLegStage];
+    if (tid < kLegStage) cst[0][tid] = coef[base + min(m + tid, lmax)];
+    __syncthreads();
+    double2 pre = make_double2(0.0, 0.0);
+    int buf = 0;
+    for (int l0 = m; l0 <= lmax; l0 += kLegC, buf ^= 1) {
+        const int ci = (l0 - m) / kLegC;
+        const int stage = ci / (kLegStage / kLegC), within = ci % (kLegStage / kLegC);
+        const double2 *cs = cst[stage & 1] + within * kLegC;
+        if (within == 0 && tid < kLegStage) pre = coef[base + min(l0 + kLegStage + tid, lmax)];
+        if (within == kLegStage / kLegC / 2 && tid < kLegStage) cst[(stage + 1) & 1][tid] = pre;
+        double2 cf[kLegC];
+#pragma unroll
+        for (int c = 0; c < kLegC; ++c) cf[c] = cs[c];
         double acc[2 * kLegC];
 #pragma unroll
         for (int c = 0; c < kLegC; ++c) {
             acc[2 * c] = acc[2 * c + 1] = 0.0;
-            const int l = l0 + c;
-            if (l <= lmax) {
-                const double2 ab = coef[base + l];
+            const double g = l0 + c <= lmax ? cf[c].x : 0.0;
 #pragma unroll
-                for (int r = 0; r < kLegR; ++r) {
-                    const double v = fma(-ab.y, prev[r], ab.x * (z[r] * cur[r]));
-                    prev[r] = cur[r];
-                    cur[r] = v;
-                    // (l - m) even <=> c even, since l0 - m is a multiple of kLegC
-                    if (c % 2 == 0) {
-                        acc[2 * c] = fma(v, er[r], acc[2 * c]);
-                        acc[2 * c + 1] = fma(v, ei[r], acc[2 * c + 1]);
-                    } else {
-                        acc[2 * c] = fma(v, orr[r], acc[2 * c]);
-                        acc[2 * c + 1] = fma(v, oi[r], acc[2 * c + 1]);
+            for (int r = 0; r < R; ++r) {
+                const double v = fma(-g, S.prev[r], S.z[r] * S.cur[r]);
+                S.prev[r] = S.cur[r];
+                S.cur[r] = v;
+                // (l - m) even <=> c even, since l0 - m is a multiple of kLegC
+                acc[2 * c] = fma(v, c % 2 == 0 ? S.er[r] : S.orr[r], acc[2 * c]);
+                acc[2 * c + 1] = fma(v, c % 2 == 0 ? S.ei[r] : S.oi[r], acc[2 * c + 1]);
+            }
+        }
+        // hand the state to the next chunk: multiply by sigma at its last l
+        const double sg = cf[kLegC - 1].y;
+        if (__builtin_amdgcn_ballot_w64(dead)) {
+            // pairs still below 2^-300 (times their scale) become live once they grow
+            uint32_t revive = 0;
+            dead = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double t = S.cur[r] * sg;
+                const bool grow = S.k[r] > 0 && fabs(t) > kBig;
+                const double f = grow ? kScaleDown : 1.0;
+                S.cur[r] = t * f;
+                S.prev[r] = S.prev[r] * sg * f;
+                S.k[r] -= grow ? 1 : 0;
+                revive |= (grow && S.k[r] == 0) ? 1u << r : 0u;
+                dead |= S.k[r] > 0;
+            }
+            if (revive) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (revive & (1u << r)) {
+                        const Folded f =
+                            load_folded(F, N, nring, m, ((int64_t)blockIdx.y * R + r) * kLegThreads + tid);
+                        S.er[r] = f.er;
+                        S.ei[r] = f.ei;
+                        S.orr[r] = f.orr;
+                        S.oi[r] = f.oi;
                     }
                 }
             }
-        }
-        // pairs still below 2^-300 (times their scale) become live once they grow
+        } else {
 #pragma unroll
-        for (int r = 0; r < kLegR; ++r) {
-            if (k[r] > 0 && fabs(cur[r]) > kBig) {
-                cur[r] *= kScaleDown;
-                prev[r] *= kScaleDown;
-                if (--k[r] == 0) {
-                    const int64_t p = ((int64_t)blockIdx.y * kLegR + r) * kLegThreads + tid;
-                    const double2 fn = F[(int64_t)m * nring + p];
-                    if (p + 1 == 2 * N) {
-                        er[r] = fn.x;
-                        ei[r] = fn.y;
-                    } else {
-                        const double2 fs = F[(int64_t)m * nring + (nring - 1 - p)];
-                        er[r] = fn.x + fs.x;
-                        ei[r] = fn.y + fs.y;
-                        orr[r] = fn.x - fs.x;
-                        oi[r] = fn.y - fs.y;
-                    }
-                }
+            for (int r = 0; r < R; ++r) {
+                S.cur[r] *= sg;
+                S.prev[r] *= sg;
             }
         }
 #pragma unroll
-        for (int q = 0; q < 2 * kLegC; ++q) red[q][tid] = acc[q];
+        for (int q = 0; q < 2 * kLegC; ++q) red[kLegBufs == 2 ? buf : 0][q][tid] = acc[q];
         __syncthreads();
         double s = 0.0;
 #pragma unroll
-        for (int t = 0; t < kLegThreads / 16; ++t) s += red[o][part + 16 * t];
-        s += __shfl_xor(s, 8, 16);
-        s += __shfl_xor(s, 4, 16);
-        s += __shfl_xor(s, 2, 16);
-        s += __shfl_xor(s, 1, 16);
+        for (int t = 0; t < kLegThreads / kLegLanes; ++t) s += red[kLegBufs == 2 ? buf : 0][o][part + kLegLanes * t];
+#pragma unroll
+        for (int d = kLegLanes / 2; d > 0; d /= 2) s += __shfl_xor(s, d, kLegLanes);
         const int l = l0 + o / 2;
         if (part == 0 && l <= lmax) {
             double *dst = reinterpret_cast<double *>(out + base + l);
-            dst[o & 1] = w * s;
+            dst[o & 1] = (w * cs[o / 2].y) * s;
         }
-        __syncthreads();
+        if (kLegBufs == 1) __syncthreads();
     }
 }
 
@@ -312,18 +420,35 @@ __global__ void sum_partials_kernel(const double2 *__restrict__ part, int32_t nb
     out[i] = s;
 }
 
-// C_l = (|a_l0|^2 + 2 sum_{m>=1} |a_lm|^2) / (2l+1); one lane per (map, l)
-__global__ void alm2cl_kernel(const double2 *__restrict__ alm, int32_t lmax, int64_t n_alm, double *__restrict__ cl) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l > lmax) return;
+// C_l = (|a_l0|^2 + 2 sum_{m>=1} |a_lm|^2) / (2l+1).  One workgroup per (64
+// consecutive l, map): lane = l (coalesced rows of the m-major layout), wave w
+// sums m = w, w + kClWaves, ...; the waves' partial sums are added in order.
+constexpr int kClWaves = 16;
+__global__ __launch_bounds__(64 * kClWaves) void alm2cl_kernel(const double2 *__restrict__ alm, int32_t lmax,
+                                                               int64_t n_alm, double *__restrict__ cl) {
+    __shared__ double part[kClWaves][64];
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+    const int l = blockIdx.x * 64 + lane;
     const double2 *a = alm + (int64_t)blockIdx.y * n_alm;
+    const int mtop = min(blockIdx.x * 64 + 63, lmax);
     double s = 0.0;
-    for (int m = 0; m <= l; ++m) {
-        const double2 v = a[(int64_t)m * (2 * lmax + 1 - m) / 2 + l];
-        const double p = v.x * v.x + v.y * v.y;
-        s += m == 0 ? p : 2.0 * p;
+    if (l <= lmax) {
+#pragma unroll 4
+        for (int m = wv; m <= mtop; m += kClWaves) {
+            if (m > l) break;
+            const double2 v = a[(int64_t)m * (2 * lmax + 1 - m) / 2 + l];
+            const double q = v.x * v.x + v.y * v.y;
+            s += m == 0 ? q : 2.0 * q;
+        }
     }
-    cl[(int64_t)blockIdx.y * (lmax + 1) + l] = s / (double)(2 * l + 1);
+    part[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0 && l <= lmax) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kClWaves; ++w) t += part[w][lane];
+        cl[(int64_t)blockIdx.y * (lmax + 1) + l] = t / (double)(2 * l + 1);
+    }
 }
 
 // ------------------------------------------------------------------ covariance over realisations
@@ -436,11 +561,13 @@ extern "C" int ufalcon_map2alm(const void *maps, int dtype, int32_t n_maps, int6
     const int64_t N = nside, npix = npix_of(nside);
     const int64_t M = (int64_t)lmax + 1;
 
-    hipLaunchKernelGGL(lambda_seed_kernel, dim3(blocks_for(L.npair, 256)), dim3(256), 0, s, N, lmax, seed, seed_k);
-    hipLaunchKernelGGL(legendre_coef_kernel, dim3(blocks_for(M, 256), (unsigned)M), dim3(256), 0, s, lmax, coef);
+    hipLaunchKernelGGL(lambda_seed_kernel, dim3(blocks_for(L.npair, kSeedThreads)), dim3(kSeedThreads), 0, s, N, lmax,
+                       seed, seed_k);
+    hipLaunchKernelGGL(legendre_coef_kernel, dim3(blocks_for((M + kLegC - 1) / kLegC, 256), (unsigned)M), dim3(256), 0, s,
+                       lmax, coef);
     UFX_HIP_CHECK(hipGetLastError());
     const double w = 4.0 * M_PI / (double)npix;
-    const dim3 dft_x((unsigned)((M + kDftThreads - 1) / kDftThreads));
+    const dim3 dft_x((unsigned)((N + kDftThreads - 1) / kDftThreads));
     for (int32_t t = 0; t < n_maps; ++t) {
         double2 *a = reinterpret_cast<double2 *>(alm) + (int64_t)t * L.nalm;
         if (dtype == UFALCON_F32) {
@@ -461,7 +588,7 @@ extern "C" int ufalcon_map2alm(const void *maps, int dtype, int32_t n_maps, int6
                                s, mp, N, lmax, F);
         }
         double2 *dst = L.n_rb > 1 ? part : a;
-        hipLaunchKernelGGL(legendre_kernel, dim3((unsigned)M, (unsigned)L.n_rb), dim3(kLegThreads), 0, s, F, seed,
+        hipLaunchKernelGGL(legendre_kernel<kLegR>, dim3((unsigned)M, (unsigned)L.n_rb), dim3(kLegThreads), 0, s, F, seed,
                            seed_k, coef, N, lmax, w, dst, L.n_rb > 1 ? L.nalm : (int64_t)0);
         if (L.n_rb > 1)
             hipLaunchKernelGGL(sum_partials_kernel, dim3(blocks_for(L.nalm, 256)), dim3(256), 0, s, part, L.n_rb,
@@ -476,7 +603,7 @@ extern "C" int ufalcon_alm2cl(const double *alm, int32_t n_maps, int32_t lmax, d
     if (n_maps == 0) return UFALCON_OK;
     if (!alm || !cl) return UFALCON_EINVAL;
     const int64_t nalm = (int64_t)(lmax + 1) * (lmax + 2) / 2;
-    hipLaunchKernelGGL(alm2cl_kernel, dim3(blocks_for((int64_t)lmax + 1, 256), (unsigned)n_maps), dim3(256), 0,
+    hipLaunchKernelGGL(alm2cl_kernel, dim3(blocks_for((int64_t)lmax + 1, 64), (unsigned)n_maps), dim3(64 * kClWaves), 0,
                        as_stream(stream), reinterpret_cast<const double2 *>(alm), lmax, nalm, cl);
     UFX_HIP_CHECK(hipGetLastError());
     return UFALCON_OK;
