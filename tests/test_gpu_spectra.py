@@ -75,6 +75,7 @@ def test_map2alm_batch_and_determinism(ufalcon):
     (1024, None, [0, 1, 2, 3, 4, 17, 100, 1024, 2047, 2048, 3000, 3071]),
     (513, None, [0, 1, 5, 512, 1000, 1538]),
     (1100, 100, [0, 1, 33, 99, 100]),        # more ring pairs than one workgroup covers
+    (2048, None, [0, 7, 3000, 6143]),        # four ring-pair blocks, lmax 6143
 ])
 def test_map2alm_sampled_large(ufalcon, nside, lmax, ms):
     mp = _map(nside, seed=nside, dtype=torch.float32)
@@ -91,6 +92,22 @@ def test_map2alm_sampled_large(ufalcon, nside, lmax, ms):
     print(f"nside {nside}: max |a_gpu - a_oracle| / max |a| = {worst:.2e}")
 
 
+def test_map2alm_edge_cases(ufalcon):
+    # lmax 0: a_00 only; no maps: nothing to do; lmax beyond 3 Nside - 1 (aliased, still the quadrature)
+    nside = 4
+    mp = _map(nside, seed=3)[0]
+    a0 = uf.map2alm(mp.to(DEV), 0).cpu().numpy()
+    assert a0.shape == (1,)
+    ref0 = S.map2alm(mp.numpy(), nside, 0)
+    assert abs(a0[0] - ref0[0, 0]) <= 1e-14 * abs(ref0[0, 0])
+    empty = uf.map2alm(torch.zeros((0, S.npix(nside)), dtype=torch.float64, device=DEV), 5)
+    assert empty.shape == (0, 21)
+    big = uf.map2alm(mp.to(DEV), 40).cpu().numpy()
+    _check_alm(_packed_to_full(big, 40), S.map2alm(mp.numpy(), nside, 40), "lmax 40 at Nside 4")
+    with pytest.raises(ValueError):
+        uf.map2alm(torch.zeros(100, dtype=torch.float64, device=DEV))
+
+
 def test_anafast_of_constant_map(ufalcon):
     # C_0 = 4 pi c^2 exactly; the pixel quadrature leaks ~1e-8 of it into higher l
     nside = 32
@@ -102,7 +119,8 @@ def test_anafast_of_constant_map(ufalcon):
     assert c[1:].max() <= 1e-7 * c[0]
 
 
-@pytest.mark.parametrize("ell_min,delta_ell,n_bands,ddof", [(0, 1, None, 1), (2, 10, 9, 1), (5, 4, 20, 0)])
+@pytest.mark.parametrize("ell_min,delta_ell,n_bands,ddof", [(0, 1, None, 1), (2, 10, 9, 1), (5, 4, 20, 0),
+                                                            (0, 96, 1, 0), (95, 1, 1, 1)])
 def test_cl_covariance_parity(ufalcon, ell_min, delta_ell, n_bands, ddof):
     R, n_ell = 150, 96
     u = synth.uniform64(R * n_ell, seed=9, stream=43).reshape(R, n_ell).numpy()
@@ -112,6 +130,16 @@ def test_cl_covariance_parity(ufalcon, ell_min, delta_ell, n_bands, ddof):
     np.testing.assert_allclose(mean.cpu().numpy(), m_ref, rtol=1e-13)
     np.testing.assert_allclose(cov.cpu().numpy(), c_ref, rtol=1e-11, atol=1e-14 * np.abs(c_ref).max())
     np.testing.assert_allclose(corr.cpu().numpy(), r_ref, rtol=1e-10, atol=1e-12)
+
+
+def test_cl_covariance_two_realisations(ufalcon):
+    cl = np.array([[1.0, 2.0, 4.0], [3.0, 2.0, 0.0]])
+    mean, cov, corr = uf.cl_covariance(torch.from_numpy(cl).to(DEV), ddof=1)
+    np.testing.assert_allclose(mean.cpu().numpy(), [2.0, 2.0, 2.0])
+    np.testing.assert_allclose(cov.cpu().numpy(), np.cov(cl, rowvar=False, ddof=1), rtol=1e-15, atol=1e-15)
+    c = corr.cpu().numpy()
+    assert c[0, 2] == pytest.approx(-1.0) and c[0, 0] == pytest.approx(1.0)
+    assert np.isnan(c[1]).all()   # zero variance at l = 1
 
 
 def test_power_spectrum_of_many_maps_then_covariance(ufalcon):
