@@ -33,6 +33,16 @@ the azimuthal factor is the plain sum sum_j map_j e^{-i m phi_j} with m phi_j
 reduced modulo 2 pi in integers: ring r has n_r pixels at
 phi_j = pi (2j + s_r) / n_r, so m phi_j = pi ((m (2j + s_r)) mod 2 n_r) / n_r.
 
+Synthesis and smoothing (section 3.3: maps smoothed with a Gaussian beam of
+r.m.s. radius sigma before their PDF and moments are taken):
+  * map_p = sum_l b_l [a_l0 lambda_l0(z_p) + 2 Re sum_{m>=1} a_lm lambda_lm(z_p) e^{i m phi_p}],
+    the real field whose coefficients are a_lm (a_{l,-m} = (-1)^m conj(a_lm)),
+    with the Gaussian beam b_l = exp(-l(l+1) sigma^2 / 2);
+  * moments of a map of N pixels (eqs. (12), (13)): mean qbar, the central
+    sample moments m_k = (1/N) sum (q - qbar)^k; s^2 = m_2 (eq. (12) as
+    printed lacks the square), and the variance of the variance estimator
+    sigma_{s^2}^2 = (N-1)^2/N^3 mu_4 - (N-1)(N-3)/N^3 mu_2^2 with mu_k -> m_k.
+
 Pins (tests/test_oracle_spectra.py): lambda against mpmath's spherical
 harmonics up to l = 3071, a pixel-by-pixel mpmath sum at Nside 1 and 2, the
 constant map, the exact rotation and mirror symmetries of the HEALPix grid,
@@ -209,3 +219,45 @@ def cl_covariance(cl: np.ndarray, ell_min: int = 0, delta_ell: int = 1, n_bands:
     with np.errstate(divide="ignore", invalid="ignore"):
         corr = cov / np.outer(sd, sd)
     return mean, cov, corr
+
+
+def gaussian_beam(sigma: float, lmax: int) -> np.ndarray:
+    """b_l = exp(-l (l+1) sigma^2 / 2), sigma the r.m.s. radius in radians."""
+    l = np.arange(lmax + 1, dtype=np.float64)
+    return np.exp(-0.5 * l * (l + 1.0) * sigma * sigma)
+
+
+def alm2map(a_full: np.ndarray, nside: int, beam=None) -> np.ndarray:
+    """Real map from the full [m, l] coefficients (m = 0..lmax), optionally
+    multiplied by a beam b_l; grouped by ring, azimuths reduced in integers."""
+    lmax = a_full.shape[1] - 1
+    start, count, shift, z, st = ring_table(nside)
+    b = np.ones(lmax + 1) if beam is None else np.asarray(beam, dtype=np.float64)
+    # per ring and m: F_r(m) = sum_l b_l a_lm lambda_lm(z_r)
+    Fr = np.zeros((len(start), lmax + 1), dtype=np.complex128)
+    for m in range(lmax + 1):
+        lam = legendre_lambda(lmax, m, z, st)                  # [l, ring]
+        Fr[:, m] = (b * a_full[m]) @ lam
+    out = np.zeros(npix(nside))
+    ms = np.arange(lmax + 1, dtype=np.int64)
+    for r in range(len(start)):
+        n = int(count[r])
+        j2s = 2 * np.arange(n, dtype=np.int64) + shift[r]      # phi_j = pi j2s / n
+        k = (ms[None, :] * j2s[:, None]) % (2 * n)
+        ang = np.pi * k.astype(np.float64) / n
+        terms = (Fr[r][None, :] * (np.cos(ang) + 1j * np.sin(ang))).real
+        out[start[r]:start[r] + n] = terms[:, 0] + 2.0 * terms[:, 1:].sum(axis=1)
+    return out
+
+
+def map_moments(q: np.ndarray):
+    """(mean, m2, m4, s2, var_s2) of one map: central sample moments with
+    exactly rounded sums (math.fsum), s2 = m2 and eq. (13) with mu_k = m_k."""
+    q = np.asarray(q, dtype=np.float64)
+    N = q.size
+    mean = math.fsum(q) / N
+    d = q - mean
+    m2 = math.fsum(d * d) / N
+    m4 = math.fsum((d * d) * (d * d)) / N
+    var_s2 = (N - 1) ** 2 / N ** 3 * m4 - (N - 1) * (N - 3) / N ** 3 * m2 * m2
+    return mean, m2, m4, m2, var_s2

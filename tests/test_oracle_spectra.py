@@ -1,5 +1,6 @@
 """Pins of the power-spectrum oracle (section 3.1 eq. (9); section 3.2
-eqs. (10), (11)) against mathematics and libraries that share nothing with it."""
+eqs. (10), (11); section 3.3: smoothing and eqs. (12), (13)) against
+mathematics and libraries that share nothing with it."""
 
 from fractions import Fraction as F
 import math
@@ -193,3 +194,68 @@ def test_covariance_against_numpy(ddof):
     np.testing.assert_allclose(cov, np.cov(X, rowvar=False, ddof=ddof), rtol=1e-12)
     np.testing.assert_allclose(corr, np.corrcoef(X, rowvar=False), rtol=1e-12, atol=1e-15)
     assert np.allclose(np.diag(corr), 1.0)
+
+
+@pytest.mark.parametrize("l,m,a", [(4, 2, 0.3 - 0.7j), (3, 0, 1.25), (5, 5, -0.2 + 0.1j)])
+def test_alm2map_single_mode_against_mpmath(l, m, a):
+    # a real field with one coefficient a_lm (and a_{l,-m} = (-1)^m conj(a_lm)):
+    # map = a Y_l0 for m = 0, else 2 Re(a_lm Y_lm), at every pixel centre of Nside 2
+    mpmath.mp.dps = 25
+    nside, lmax = 2, 6
+    full = np.zeros((lmax + 1, lmax + 1), dtype=complex)
+    full[m, l] = a
+    got = S.alm2map(full, nside)
+    for p in range(S.npix(nside)):
+        zq, phi = H.pix2ang_ring(nside, p)
+        y = mpmath.spherharm(l, m, _theta_mp(zq), phi)
+        ref = float((a * y).real) if m == 0 else float(2 * (mpmath.mpc(a.real, a.imag) * y).real)
+        assert abs(got[p] - ref) <= 1e-14, (p, got[p], ref)
+
+
+def test_alm2map_is_the_adjoint_of_map2alm():
+    # sum_p x_p alm2map(a)_p = (N_pix / 4 pi) Re sum_lm w_m a_lm conj(map2alm(x)_lm),
+    # w_0 = 1, w_m = 2: the quadrature of map2alm is the transpose of the synthesis
+    rng = np.random.default_rng(1)
+    nside = 4
+    lmax = 3 * nside - 1
+    x = rng.standard_normal(S.npix(nside))
+    a = np.zeros((lmax + 1, lmax + 1), dtype=complex)
+    for m in range(lmax + 1):
+        a[m, m:] = rng.standard_normal(lmax + 1 - m) + (1j * rng.standard_normal(lmax + 1 - m) if m else 0)
+    y = S.map2alm(x, nside)
+    lhs = float(np.dot(x, S.alm2map(a, nside)))
+    w = np.full((lmax + 1, 1), 2.0)
+    w[0] = 1.0
+    rhs = float((w * (a * np.conj(y))).real.sum()) * S.npix(nside) / (4 * np.pi)
+    assert lhs == pytest.approx(rhs, rel=1e-13)
+
+
+def test_gaussian_beam_is_the_transform_of_a_gaussian_profile():
+    # b_l = (int K P_l sin) / (int K sin) for K(theta) = exp(-theta^2 / (2 sigma^2)):
+    # equals exp(-l(l+1) sigma^2 / 2) up to O(sigma^2) on the sphere
+    from scipy.integrate import quad
+    from scipy.special import eval_legendre
+    sigma = np.radians(10.8 / 60.0)
+    b = S.gaussian_beam(sigma, 400)
+    norm = quad(lambda t: np.exp(-t * t / (2 * sigma ** 2)) * np.sin(t), 0, 12 * sigma)[0]
+    for l in (0, 1, 10, 100, 250, 400):
+        num = quad(lambda t: np.exp(-t * t / (2 * sigma ** 2)) * eval_legendre(l, np.cos(t)) * np.sin(t),
+                   0, 12 * sigma, limit=400)[0]
+        assert num / norm == pytest.approx(b[l], rel=2e-3, abs=1e-12), l
+
+
+def test_map_moments_against_scipy_and_closed_forms():
+    from scipy.stats import moment
+    rng = np.random.default_rng(4)
+    q = rng.gamma(2.0, 1.5, size=100_001)
+    mean, m2, m4, s2, var_s2 = S.map_moments(q)
+    assert mean == pytest.approx(q.mean(), rel=1e-14)
+    assert m2 == pytest.approx(moment(q, 2), rel=1e-12)
+    assert m4 == pytest.approx(moment(q, 4), rel=1e-12)
+    assert s2 == m2
+    # two-point values +-1: m2 = m4 = 1, var_s2 = ((N-1)^2 - (N-1)(N-3)) / N^3 = 2(N-1)/N^3
+    N = 1000
+    two = np.where(np.arange(N) % 2 == 0, 1.0, -1.0)
+    mean, m2, m4, s2, var_s2 = S.map_moments(two)
+    assert mean == 0.0 and m2 == 1.0 and m4 == 1.0
+    assert var_s2 == pytest.approx(2.0 * (N - 1) / N ** 3, rel=1e-14)
