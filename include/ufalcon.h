@@ -364,6 +364,44 @@ int ufalcon_cl_covariance(const double *cl, int32_t n_real, int32_t n_ell, int32
                           int32_t n_bands, int32_t ddof, double *band_mean, double *cov, double *corr,
                           void *workspace, size_t workspace_bytes, ufalcon_stream_t stream);
 
+/*
+ * Synthesis: the real maps whose coefficients are alm (section 3.3 smooths
+ * the kappa and delta maps with a Gaussian beam before taking their PDF and
+ * moments), optionally multiplied by a beam b_l:
+ *   map_p = sum_l b_l [a_l0 Y_l0(p) + 2 Re sum_{m>=1} a_lm Y_lm(p)]
+ * at the pixel centres (a_{l,-m} = (-1)^m conj(a_lm); Im a_l0 is ignored).
+ * alm device double [n_maps][n_alm][2] (the layout of ufalcon_map2alm);
+ * beam device double [lmax+1] or NULL (b_l = 1); maps device
+ * [n_maps][12 Nside^2] of dtype, overwritten.  workspace device, at least
+ * ufalcon_alm2map_workspace_size(nside, lmax) bytes (0 for invalid
+ * arguments).  FP64 throughout, bitwise reproducible.
+ */
+size_t ufalcon_alm2map_workspace_size(int64_t nside, int32_t lmax);
+int ufalcon_alm2map(const double *alm, int32_t n_maps, int64_t nside, int32_t lmax, const double *beam, void *maps,
+                    int dtype, void *workspace, size_t workspace_bytes, ufalcon_stream_t stream);
+
+/*
+ * Gaussian beam of r.m.s. radius sigma (radians; section 3.3 uses 10.8
+ * arcmin): beam[l] = exp(-l (l+1) sigma^2 / 2), l = 0..lmax, device double.
+ */
+int ufalcon_gaussian_beam(double sigma, int32_t lmax, double *beam, ufalcon_stream_t stream);
+
+/*
+ * One-point moments of maps of npix values (section 3.3 eqs. (12), (13)),
+ * per map, in FP64 with a fixed reduction order (two passes: the mean, then
+ * the central sums):
+ *   [0] mean qbar      [1] m2 = (1/N) sum (q - qbar)^2     [2] m4 = (1/N) sum (q - qbar)^4
+ *   [3] s^2 = m2 (eq. (12); the printed formula lacks the square)
+ *   [4] sigma_{s^2}^2 = (N-1)^2/N^3 m4 - (N-1)(N-3)/N^3 m2^2   (eq. (13), mu_k -> m_k)
+ * maps device [n_maps][npix] of dtype; moments device double
+ * [n_maps][UFALCON_NMOMENTS]; workspace device, at least
+ * ufalcon_map_moments_workspace_size(n_maps) bytes; n_maps <= 65535.
+ */
+#define UFALCON_NMOMENTS 5
+size_t ufalcon_map_moments_workspace_size(int32_t n_maps);
+int ufalcon_map_moments(const void *maps, int dtype, int32_t n_maps, int64_t npix, double *moments, void *workspace,
+                        size_t workspace_bytes, ufalcon_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

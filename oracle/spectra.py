@@ -227,20 +227,25 @@ def gaussian_beam(sigma: float, lmax: int) -> np.ndarray:
     return np.exp(-0.5 * l * (l + 1.0) * sigma * sigma)
 
 
-def alm2map(a_full: np.ndarray, nside: int, beam=None) -> np.ndarray:
+def alm2map(a_full: np.ndarray, nside: int, beam=None, rings=None) -> np.ndarray:
     """Real map from the full [m, l] coefficients (m = 0..lmax), optionally
-    multiplied by a beam b_l; grouped by ring, azimuths reduced in integers."""
+    multiplied by a beam b_l; grouped by ring, azimuths reduced in integers.
+    `rings` (indices i-1) restricts the work to those rings; the other pixels
+    are left at zero."""
     lmax = a_full.shape[1] - 1
     start, count, shift, z, st = ring_table(nside)
+    sel = np.arange(len(start)) if rings is None else np.asarray(rings, dtype=np.int64)
     b = np.ones(lmax + 1) if beam is None else np.asarray(beam, dtype=np.float64)
     # per ring and m: F_r(m) = sum_l b_l a_lm lambda_lm(z_r)
     Fr = np.zeros((len(start), lmax + 1), dtype=np.complex128)
     for m in range(lmax + 1):
-        lam = legendre_lambda(lmax, m, z, st)                  # [l, ring]
-        Fr[:, m] = (b * a_full[m]) @ lam
+        if not a_full[m].any():
+            continue                                            # F_r(m) = 0
+        lam = legendre_lambda(lmax, m, z[sel], st[sel])        # [l, ring]
+        Fr[sel, m] = (b * a_full[m]) @ lam
     out = np.zeros(npix(nside))
     ms = np.arange(lmax + 1, dtype=np.int64)
-    for r in range(len(start)):
+    for r in sel:
         n = int(count[r])
         j2s = 2 * np.arange(n, dtype=np.int64) + shift[r]      # phi_j = pi j2s / n
         k = (ms[None, :] * j2s[:, None]) % (2 * n)

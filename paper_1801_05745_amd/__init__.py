@@ -102,6 +102,11 @@ _SIGS = {
     "ufalcon_alm2cl": (ctypes.c_int, [_P, _I32, _I32, _P, _P]),
     "ufalcon_cl_covariance_workspace_size": (_SZ, [_I32, _I32]),
     "ufalcon_cl_covariance": (ctypes.c_int, [_P, _I32, _I32, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _SZ, _P]),
+    "ufalcon_alm2map_workspace_size": (_SZ, [_I64, _I32]),
+    "ufalcon_alm2map": (ctypes.c_int, [_P, _I32, _I64, _I32, _P, _P, ctypes.c_int, _P, _SZ, _P]),
+    "ufalcon_gaussian_beam": (ctypes.c_int, [_D, _I32, _P, _P]),
+    "ufalcon_map_moments_workspace_size": (_SZ, [_I32]),
+    "ufalcon_map_moments": (ctypes.c_int, [_P, ctypes.c_int, _I32, _I64, _P, _P, _SZ, _P]),
 }
 
 
@@ -499,6 +504,69 @@ def cl_covariance(cl, ell_min=0, delta_ell=1, n_bands=None, ddof=1, with_corr=Tr
                                      _ptr(mean), _ptr(cov), _ptr(corr), _ptr(ws), ws.numel(), _stream(c.device)),
            "ufalcon_cl_covariance")
     return mean, cov, corr
+
+
+def gaussian_beam(sigma, lmax, device="cuda"):
+    """b_l = exp(-l(l+1) sigma^2 / 2) for l = 0..lmax (sigma: r.m.s. radius in radians)."""
+    lib = load()
+    out = torch.empty(int(lmax) + 1, dtype=torch.float64, device=device)
+    _check(lib.ufalcon_gaussian_beam(float(sigma), int(lmax), _ptr(out), _stream(out.device)), "ufalcon_gaussian_beam")
+    return out
+
+
+def alm2map(alm, nside, lmax, beam=None, out_dtype=torch.float64):
+    """Real maps [n_maps][npix] (or [npix]) from complex128 coefficients
+    [n_maps][n_alm] (or [n_alm]), optionally multiplied by a beam b_l."""
+    lib = load()
+    a = alm.contiguous()
+    single = a.dim() == 1
+    if single:
+        a = a[None, :]
+    if a.shape[1] != n_alm(lmax) or a.dtype != torch.complex128:
+        raise ValueError("alm must be complex128 [n_maps][(lmax+1)(lmax+2)/2]")
+    b = None
+    if beam is not None:
+        b = beam.to(device=a.device, dtype=torch.float64).contiguous()
+        if b.numel() != int(lmax) + 1:
+            raise ValueError("beam must hold lmax + 1 values")
+    nbytes = int(lib.ufalcon_alm2map_workspace_size(int(nside), int(lmax)))
+    if nbytes == 0:
+        raise ValueError("invalid nside or lmax")
+    ws = _workspace(nbytes, a.device, "map2alm")
+    out = torch.empty((a.shape[0], npix(nside)), dtype=out_dtype, device=a.device)
+    _check(lib.ufalcon_alm2map(_ptr(torch.view_as_real(a)), a.shape[0], int(nside), int(lmax), _ptr(b), _ptr(out),
+                               _dtype_code(out_dtype), _ptr(ws), ws.numel(), _stream(a.device)), "ufalcon_alm2map")
+    return out[0] if single else out
+
+
+def smooth(maps, sigma, lmax=None, out_dtype=None):
+    """Maps smoothed with a Gaussian beam of r.m.s. radius sigma (radians):
+    analysis to lmax (default 3 Nside - 1), beam, synthesis."""
+    npx = maps.shape[-1]
+    nside = int(round((npx / 12) ** 0.5))
+    if lmax is None:
+        lmax = 3 * nside - 1
+    a = map2alm(maps, lmax)
+    return alm2map(a, nside, lmax, gaussian_beam(sigma, lmax, maps.device),
+                   out_dtype=maps.dtype if out_dtype is None else out_dtype)
+
+
+MOMENT_NAMES = ("mean", "m2", "m4", "s2", "var_s2")
+
+
+def map_moments(maps):
+    """[n_maps][5] (or [5]) FP64: mean, m2, m4, s^2 and sigma_{s^2}^2 of each map."""
+    lib = load()
+    m = maps.contiguous()
+    single = m.dim() == 1
+    if single:
+        m = m[None, :]
+    nbytes = int(lib.ufalcon_map_moments_workspace_size(m.shape[0]))
+    ws = _workspace(max(nbytes, 8), m.device, "moments")
+    out = torch.empty((m.shape[0], len(MOMENT_NAMES)), dtype=torch.float64, device=m.device)
+    _check(lib.ufalcon_map_moments(_ptr(m), _dtype_code(m.dtype), m.shape[0], m.shape[1], _ptr(out), _ptr(ws),
+                                   ws.numel(), _stream(m.device)), "ufalcon_map_moments")
+    return out[0] if single else out
 
 
 # ---------------------------------------------------------------- autograd

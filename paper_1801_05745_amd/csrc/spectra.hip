@@ -496,6 +496,325 @@ __global__ void corr_kernel(const double *__restrict__ cov, int32_t nb, double *
     corr[(int64_t)b * nb + c] = cov[(int64_t)b * nb + c] / (sb * sc);
 }
 
+// ------------------------------------------------------------------ synthesis (alm2map)
+// map_p = sum_l b_l [a_l0 lambda_l0 + 2 Re sum_{m>=1} a_lm lambda_lm e^{i m phi_p}]
+// (the real field with coefficients a_lm).  Per m, every ring pair gets
+//   E = sum_{l-m even} b_l a_lm lambda_lm(z),  O = sum_{l-m odd} ...,
+// F_north(m) = E + O and F_south(m) = E - O (lambda_lm(-z) = (-1)^{l+m}
+// lambda_lm(z)); no cross-lane reduction is needed.  Then each ring folds
+// F(m) over m mod n and runs the inverse of the radix-4 ring transform.
+
+__global__ void gaussian_beam_kernel(double sigma, int32_t lmax, double *__restrict__ beam) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > lmax) return;
+    beam[l] = exp(-0.5 * (double)l * (double)(l + 1) * sigma * sigma);
+}
+
+template <int R>
+__global__ __launch_bounds__(kLegThreads) void legendre_synth_kernel(const double2 *__restrict__ alm,
+                                                                     const double *__restrict__ beam,
+                                                                     const double *__restrict__ seed,
+                                                                     const int32_t *__restrict__ seed_k,
+                                                                     const double2 *__restrict__ coef, int64_t N,
+                                                                     int32_t lmax, double2 *__restrict__ F) {
+    // per l of the current stage: (g_l, sigma_l) and sigma_l b_l a_lm
+    __shared__ double2 cst[2][kLegStage];
+    __shared__ double2 ast[2][kLegStage];
+    const int m = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t npair = 2 * N, nring = 4 * N - 1;
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+
+    double z[R], prev[R], cur[R], er[R], ei[R], orr[R], oi[R];
+    int32_t k[R];
+    bool dead = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t p = ((int64_t)blockIdx.y * R + r) * kLegThreads + tid;
+        z[r] = prev[r] = cur[r] = 0.0;
+        er[r] = ei[r] = orr[r] = oi[r] = 0.0;
+        k[r] = 0;
+        if (p < npair) {
+            double st;
+            ring_z_sin(N, p + 1, z[r], st);
+            prev[r] = seed[(int64_t)m * npair + p];
+            k[r] = seed_k[(int64_t)m * npair + p];
+        }
+        dead |= k[r] > 0;
+    }
+    auto stage_entry = [&](int l, double2 &c, double2 &a) {
+        const int lc = min(l, lmax);
+        c = coef[base + lc];
+        const double2 v = alm[base + lc];
+        const double f = l <= lmax ? c.y * (beam ? beam[lc] : 1.0) : 0.0;
+        a = make_double2(f * v.x, m == 0 ? 0.0 : f * v.y);
+    };
+    if (tid < kLegStage) stage_entry(m + tid, cst[0][tid], ast[0][tid]);
+    __syncthreads();
+    double2 pc = make_double2(0.0, 0.0), pa = make_double2(0.0, 0.0);
+    for (int l0 = m; l0 <= lmax; l0 += kLegC) {
+        const int ci = (l0 - m) / kLegC;
+        const int stage = ci / (kLegStage / kLegC), within = ci % (kLegStage / kLegC);
+        const double2 *cs = cst[stage & 1] + within * kLegC;
+        const double2 *as = ast[stage & 1] + within * kLegC;
+        if (within == 0 && tid < kLegStage) stage_entry(l0 + kLegStage + tid, pc, pa);
+        if (within == kLegStage / kLegC / 2 && tid < kLegStage) {
+            cst[(stage + 1) & 1][tid] = pc;
+            ast[(stage + 1) & 1][tid] = pa;
+        }
+#pragma unroll
+        for (int c = 0; c < kLegC; ++c) {
+            const double g = l0 + c <= lmax ? cs[c].x : 0.0;
+            const double2 a = as[c];  // zero past lmax
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double v = fma(-g, prev[r], z[r] * cur[r]);
+                prev[r] = cur[r];
+                cur[r] = v;
+                if (c % 2 == 0) {
+                    er[r] = fma(v, a.x, er[r]);
+                    ei[r] = fma(v, a.y, ei[r]);
+                } else {
+                    orr[r] = fma(v, a.x, orr[r]);
+                    oi[r] = fma(v, a.y, oi[r]);
+                }
+            }
+        }
+        const double sg = cs[kLegC - 1].y;
+        if (__builtin_amdgcn_ballot_w64(dead)) {
+            // a pair below 2^-300 has accumulated scaled values only: they are
+            // dropped when it revives (their true size is below 2^-240 |a|)
+            dead = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double t = cur[r] * sg;
+                const bool grow = k[r] > 0 && fabs(t) > kBig;
+                const double f = grow ? kScaleDown : 1.0;
+                cur[r] = t * f;
+                prev[r] = prev[r] * sg * f;
+                k[r] -= grow ? 1 : 0;
+                const bool drop = grow && k[r] == 0;
+                er[r] = drop ? 0.0 : er[r];
+                ei[r] = drop ? 0.0 : ei[r];
+                orr[r] = drop ? 0.0 : orr[r];
+                oi[r] = drop ? 0.0 : oi[r];
+                dead |= k[r] > 0;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                cur[r] *= sg;
+                prev[r] *= sg;
+            }
+        }
+        __syncthreads();  // stage buffers: the next chunk may switch stages
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t p = ((int64_t)blockIdx.y * R + r) * kLegThreads + tid;
+        if (p >= npair) continue;
+        const bool live = k[r] == 0;
+        const double2 fn = live ? make_double2(er[r] + orr[r], ei[r] + oi[r]) : make_double2(0.0, 0.0);
+        F[(int64_t)m * nring + p] = fn;
+        if (p + 1 != 2 * N)
+            F[(int64_t)m * nring + (nring - 1 - p)] =
+                live ? make_double2(er[r] - orr[r], ei[r] - oi[r]) : make_double2(0.0, 0.0);
+    }
+}
+
+// Inverse ring transform.  With H[k] = sum_{m = k mod n, m <= lmax} c_m F(m) e^{i pi m s/n}
+// (c_0 = 1, c_m = 2), map_j = Re sum_{k<n} H[k] e^{2 pi i k j/n}; by decimation,
+//   map[4j' + q] = Re sum_{k'<n4} P_q[k'] e^{2 pi i k' j'/n4},
+//   P_q[k'] = e^{2 pi i k' q/n} sum_t i^{t q} H[k' + t n4].
+// Lane j' accumulates the four outputs of RG rings of equal length.
+template <typename T, bool kPolar>
+__global__ __launch_bounds__(kDftThreads) void ring_idft_kernel(const double2 *__restrict__ F, int64_t N,
+                                                                int32_t lmax, T *__restrict__ map) {
+    constexpr int RG = kPolar ? 2 : kEqRings;
+    __shared__ double2 ps[RG][4][kDftJ];
+    const int64_t nring = 4 * N - 1;
+    int64_t ring[RG];
+    bool valid[RG];
+    int64_t n4;
+    if (kPolar) {
+        const int64_t i = (int64_t)blockIdx.y + 1;
+        ring[0] = i;
+        ring[RG - 1] = 4 * N - i;
+        valid[0] = valid[RG - 1] = true;
+        n4 = i;
+    } else {
+        const int64_t i0 = N + (int64_t)blockIdx.y * RG;
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+            valid[g] = i0 + g <= 3 * N;
+            ring[g] = valid[g] ? i0 + g : 3 * N;
+        }
+        n4 = N;
+    }
+    if ((int64_t)blockIdx.x * kDftThreads >= n4) return;
+    const int64_t jp = (int64_t)blockIdx.x * kDftThreads + threadIdx.x;  // j'
+    const int64_t n = 4 * n4;
+
+    double acc[RG][4];
+#pragma unroll
+    for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[g][q] = 0.0;
+    double ws, wc;  // step e^{2 pi i j' / n4}
+    sincospi(2.0 * (double)(jp % n4) / (double)n4, &ws, &wc);
+
+    for (int64_t kb = 0; kb < n4; kb += kDftJ) {
+        const int cnt = (int)(n4 - kb < kDftJ ? n4 - kb : kDftJ);
+        for (int e = threadIdx.x; e < RG * kDftJ; e += kDftThreads) {
+            const int g = e / kDftJ, kk = e % kDftJ;
+            double2 P[4] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0),
+                            make_double2(0.0, 0.0)};
+            if (kk < cnt) {
+                const int64_t kp = kb + kk;
+                const bool shift = ring_shift(N, ring[g]) != 0;
+                double2 Hh[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int64_t kf = kp + t * n4;  // folded index, < n
+                    double hr = 0.0, hi = 0.0;
+                    for (int64_t mm = kf, u = 0; mm <= lmax; mm += n, ++u) {
+                        const double2 f = F[mm * nring + (ring[g] - 1)];
+                        const double cm = (mm == 0 ? 1.0 : 2.0) * ((shift && (u & 1)) ? -1.0 : 1.0);
+                        hr = fma(cm, f.x, hr);
+                        hi = fma(cm, f.y, hi);
+                    }
+                    if (shift) {  // e^{i pi kf / n}
+                        double s, c;
+                        sincospi((double)kf / (double)n, &s, &c);
+                        const double r0 = hr * c - hi * s;
+                        hi = hr * s + hi * c;
+                        hr = r0;
+                    }
+                    Hh[t] = make_double2(hr, hi);
+                }
+                // sum_t i^{tq} H_t, i (x + iy) = -y + ix
+                const double ar = Hh[0].x + Hh[2].x, ai = Hh[0].y + Hh[2].y;
+                const double br = Hh[0].x - Hh[2].x, bi = Hh[0].y - Hh[2].y;
+                const double cr = Hh[1].x + Hh[3].x, ci = Hh[1].y + Hh[3].y;
+                const double dr = Hh[1].x - Hh[3].x, di = Hh[1].y - Hh[3].y;
+                const double qr[4] = {ar + cr, br - di, ar - cr, br + di};
+                const double qi[4] = {ai + ci, bi + dr, ai - ci, bi - dr};
+                // e^{2 pi i k' q / n}
+                double s1, c1;
+                sincospi(2.0 * (double)kp / (double)n, &s1, &c1);
+                const double c2 = c1 * c1 - s1 * s1, s2 = 2.0 * c1 * s1;
+                const double c3 = c2 * c1 - s2 * s1, s3 = c2 * s1 + s2 * c1;
+                const double tc[4] = {1.0, c1, c2, c3}, ts[4] = {0.0, s1, s2, s3};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) P[q] = make_double2(qr[q] * tc[q] - qi[q] * ts[q], qr[q] * ts[q] + qi[q] * tc[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ps[g][q][kk] = P[q];
+        }
+        __syncthreads();
+        double wr, wi;
+        sincospi(2.0 * (double)((jp * kb) % n4) / (double)n4, &wi, &wr);
+        for (int kk = 0; kk < cnt; ++kk) {
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double2 P = ps[g][q][kk];
+                    acc[g][q] = fma(P.x, wr, acc[g][q]);
+                    acc[g][q] = fma(-P.y, wi, acc[g][q]);
+                }
+            const double nr = fma(wr, wc, -(wi * ws));
+            const double ni = fma(wr, ws, wi * wc);
+            wr = nr;
+            wi = ni;
+        }
+        __syncthreads();
+    }
+    if (jp >= n4) return;
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+        if (!valid[g]) continue;
+        T *dst = map + ring_first(N, ring[g]) + 4 * jp;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q] = (T)acc[g][q];
+    }
+}
+
+// ------------------------------------------------------------------ map moments (eqs. (12), (13))
+constexpr int kMomBlocks = 1024;  // fixed, so the reduction order does not depend on the device
+constexpr int kMomThreads = 256;
+
+__device__ __forceinline__ double block_sum_fixed(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kMomThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// pass 0: sum q; pass 1: sum (q - mean)^2 and sum (q - mean)^4 (mean from the
+// previous pass's total).  Block b covers a fixed contiguous range.
+template <typename T>
+__global__ __launch_bounds__(kMomThreads) void moments_partial_kernel(const T *__restrict__ q, int64_t npix, int pass,
+                                                                      const double *__restrict__ mean,
+                                                                      double *__restrict__ part) {
+    __shared__ double sh[kMomThreads];
+    const T *x = q + (int64_t)blockIdx.y * npix;
+    const int64_t per = (npix + kMomBlocks - 1) / kMomBlocks;
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = lo + per < npix ? lo + per : npix;
+    const double mu = pass ? mean[blockIdx.y] : 0.0;
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kMomThreads) {
+        const double d = (double)x[i] - mu;
+        if (pass) {
+            const double d2 = d * d;
+            s1 += d2;
+            s2 = fma(d2, d2, s2);
+        } else {
+            s1 += d;
+        }
+    }
+    s1 = block_sum_fixed(s1, sh);
+    s2 = block_sum_fixed(s2, sh);
+    if (threadIdx.x == 0) {
+        double *o = part + ((int64_t)blockIdx.y * kMomBlocks + blockIdx.x) * 2;
+        o[0] = s1;
+        o[1] = s2;
+    }
+}
+
+// one block per map: totals of the partials; pass 0 writes the mean, pass 1 the moments
+__global__ __launch_bounds__(kMomThreads) void moments_final_kernel(const double *__restrict__ part, int64_t npix,
+                                                                    int pass, double *__restrict__ mean,
+                                                                    double *__restrict__ out) {
+    __shared__ double sh[kMomThreads];
+    const double *p = part + (int64_t)blockIdx.x * kMomBlocks * 2;
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < kMomBlocks; i += kMomThreads) {
+        a += p[2 * i];
+        b += p[2 * i + 1];
+    }
+    a = block_sum_fixed(a, sh);
+    b = block_sum_fixed(b, sh);
+    if (threadIdx.x != 0) return;
+    const double Nn = (double)npix;
+    if (pass == 0) {
+        mean[blockIdx.x] = a / Nn;
+        return;
+    }
+    const double m2 = a / Nn, m4 = b / Nn;
+    double *o = out + (int64_t)blockIdx.x * UFALCON_NMOMENTS;
+    o[0] = mean[blockIdx.x];
+    o[1] = m2;
+    o[2] = m4;
+    o[3] = m2;  // s^2
+    o[4] = (Nn - 1.0) * (Nn - 1.0) / (Nn * Nn * Nn) * m4 - (Nn - 1.0) * (Nn - 3.0) / (Nn * Nn * Nn) * m2 * m2;
+}
+
 // ------------------------------------------------------------------ host side
 struct ShtLayout {
     int64_t N, nring, npair, nalm;
@@ -635,6 +954,100 @@ extern "C" int ufalcon_cl_covariance(const double *cl, int32_t n_real, int32_t n
     if (corr)
         hipLaunchKernelGGL(corr_kernel, dim3(blocks_for(n_bands, 256), (unsigned)n_bands), dim3(256), 0, s, cov,
                            n_bands, corr);
+    UFX_HIP_CHECK(hipGetLastError());
+    return UFALCON_OK;
+}
+
+extern "C" int ufalcon_gaussian_beam(double sigma, int32_t lmax, double *beam, ufalcon_stream_t stream) {
+    if (!beam || lmax < 0 || lmax > kMaxLmax || !std::isfinite(sigma) || sigma < 0.0) return UFALCON_EINVAL;
+    hipLaunchKernelGGL(gaussian_beam_kernel, dim3(blocks_for((int64_t)lmax + 1, 256)), dim3(256), 0,
+                       as_stream(stream), sigma, lmax, beam);
+    UFX_HIP_CHECK(hipGetLastError());
+    return UFALCON_OK;
+}
+
+extern "C" size_t ufalcon_alm2map_workspace_size(int64_t nside, int32_t lmax) {
+    if (check_nside(nside) || lmax < 0 || lmax > kMaxLmax) return 0;
+    return sht_layout(nside, lmax).off_part;  // ring sums, seeds and coefficients
+}
+
+extern "C" int ufalcon_alm2map(const double *alm, int32_t n_maps, int64_t nside, int32_t lmax, const double *beam,
+                               void *maps, int dtype, void *workspace, size_t workspace_bytes,
+                               ufalcon_stream_t stream) {
+    int rc = check_nside(nside);
+    if (rc) return rc;
+    if (n_maps < 0 || lmax < 0 || lmax > kMaxLmax) return UFALCON_EINVAL;
+    if (dtype != UFALCON_F32 && dtype != UFALCON_F64) return UFALCON_EINVAL;
+    if (n_maps == 0) return UFALCON_OK;
+    if (!alm || !maps || !workspace) return UFALCON_EINVAL;
+    const ShtLayout L = sht_layout(nside, lmax);
+    if (workspace_bytes < L.off_part) return UFALCON_EWORKSPACE;
+    hipStream_t s = as_stream(stream);
+    char *ws = static_cast<char *>(workspace);
+    double2 *F = reinterpret_cast<double2 *>(ws + L.off_F);
+    double *seed = reinterpret_cast<double *>(ws + L.off_seed);
+    int32_t *seed_k = reinterpret_cast<int32_t *>(ws + L.off_k);
+    double2 *coef = reinterpret_cast<double2 *>(ws + L.off_coef);
+    const int64_t N = nside, npix = npix_of(nside);
+    const int64_t M = (int64_t)lmax + 1;
+    hipLaunchKernelGGL(lambda_seed_kernel, dim3(blocks_for(L.npair, kSeedThreads)), dim3(kSeedThreads), 0, s, N, lmax,
+                       seed, seed_k);
+    hipLaunchKernelGGL(legendre_coef_kernel, dim3(blocks_for((M + kLegC - 1) / kLegC, 256), (unsigned)M), dim3(256), 0, s,
+                       lmax, coef);
+    UFX_HIP_CHECK(hipGetLastError());
+    const unsigned dx = (unsigned)((N + kDftThreads - 1) / kDftThreads);
+    for (int32_t t = 0; t < n_maps; ++t) {
+        const double2 *a = reinterpret_cast<const double2 *>(alm) + (int64_t)t * L.nalm;
+        hipLaunchKernelGGL(legendre_synth_kernel<kLegR>, dim3((unsigned)M, (unsigned)L.n_rb), dim3(kLegThreads), 0, s,
+                           a, beam, seed, seed_k, coef, N, lmax, F);
+        if (dtype == UFALCON_F32) {
+            float *mp = static_cast<float *>(maps) + t * npix;
+            if (N > 1)
+                hipLaunchKernelGGL((ring_idft_kernel<float, true>), dim3(dx, (unsigned)(N - 1)), dim3(kDftThreads), 0,
+                                   s, F, N, lmax, mp);
+            hipLaunchKernelGGL((ring_idft_kernel<float, false>),
+                               dim3(dx, (unsigned)((2 * N + 1 + kEqRings - 1) / kEqRings)), dim3(kDftThreads), 0, s, F,
+                               N, lmax, mp);
+        } else {
+            double *mp = static_cast<double *>(maps) + t * npix;
+            if (N > 1)
+                hipLaunchKernelGGL((ring_idft_kernel<double, true>), dim3(dx, (unsigned)(N - 1)), dim3(kDftThreads), 0,
+                                   s, F, N, lmax, mp);
+            hipLaunchKernelGGL((ring_idft_kernel<double, false>),
+                               dim3(dx, (unsigned)((2 * N + 1 + kEqRings - 1) / kEqRings)), dim3(kDftThreads), 0, s, F,
+                               N, lmax, mp);
+        }
+        UFX_HIP_CHECK(hipGetLastError());
+    }
+    return UFALCON_OK;
+}
+
+extern "C" size_t ufalcon_map_moments_workspace_size(int32_t n_maps) {
+    if (n_maps < 1) return 0;
+    return (size_t)n_maps * (2 * kMomBlocks + 1) * sizeof(double);
+}
+
+extern "C" int ufalcon_map_moments(const void *maps, int dtype, int32_t n_maps, int64_t npix, double *moments,
+                                   void *workspace, size_t workspace_bytes, ufalcon_stream_t stream) {
+    if (n_maps < 0 || npix < 1) return UFALCON_EINVAL;
+    if (dtype != UFALCON_F32 && dtype != UFALCON_F64) return UFALCON_EINVAL;
+    if (n_maps == 0) return UFALCON_OK;
+    if (!maps || !moments || !workspace) return UFALCON_EINVAL;
+    if (n_maps > 65535) return UFALCON_EINVAL;
+    if (workspace_bytes < ufalcon_map_moments_workspace_size(n_maps)) return UFALCON_EWORKSPACE;
+    hipStream_t s = as_stream(stream);
+    double *part = static_cast<double *>(workspace);
+    double *mean = part + (int64_t)n_maps * 2 * kMomBlocks;
+    for (int pass = 0; pass < 2; ++pass) {
+        if (dtype == UFALCON_F32)
+            hipLaunchKernelGGL(moments_partial_kernel<float>, dim3(kMomBlocks, (unsigned)n_maps), dim3(kMomThreads), 0,
+                               s, static_cast<const float *>(maps), npix, pass, mean, part);
+        else
+            hipLaunchKernelGGL(moments_partial_kernel<double>, dim3(kMomBlocks, (unsigned)n_maps), dim3(kMomThreads), 0,
+                               s, static_cast<const double *>(maps), npix, pass, mean, part);
+        hipLaunchKernelGGL(moments_final_kernel, dim3((unsigned)n_maps), dim3(kMomThreads), 0, s, part, npix, pass, mean,
+                           moments);
+    }
     UFX_HIP_CHECK(hipGetLastError());
     return UFALCON_OK;
 }

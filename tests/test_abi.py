@@ -139,3 +139,22 @@ def test_spectra_validation():
     assert cov(l0=1) == EINVAL          # bands run past n_ell
     assert cov(dl=0) == EINVAL
     assert cov(ws_bytes=ws - 8) == EWORKSPACE
+
+
+def test_synthesis_and_moments_validation():
+    lib = uf.load()
+    EINVAL, ENSIDE, EWORKSPACE = -1, -3, -5
+    assert lib.ufalcon_alm2map_workspace_size(0, 4) == 0
+    ws = lib.ufalcon_alm2map_workspace_size(4, 11)
+    assert 0 < ws < lib.ufalcon_map2alm_workspace_size(4, 11) + 1
+    assert lib.ufalcon_alm2map(FAKE, 1, 9000, 11, None, FAKE, 1, FAKE, ws, None) == ENSIDE
+    assert lib.ufalcon_alm2map(FAKE, 1, 4, 11, None, FAKE, 3, FAKE, ws, None) == EINVAL
+    assert lib.ufalcon_alm2map(FAKE, 1, 4, 11, None, FAKE, 1, FAKE, ws - 1, None) == EWORKSPACE
+    assert lib.ufalcon_alm2map(None, 0, 4, 11, None, None, 1, None, 0, None) == 0
+    assert lib.ufalcon_gaussian_beam(-1.0, 10, FAKE, None) == EINVAL
+    assert lib.ufalcon_gaussian_beam(float("nan"), 10, FAKE, None) == EINVAL
+    assert lib.ufalcon_map_moments_workspace_size(0) == 0
+    mw = lib.ufalcon_map_moments_workspace_size(2)
+    assert lib.ufalcon_map_moments(FAKE, 0, 2, 0, FAKE, FAKE, mw, None) == EINVAL
+    assert lib.ufalcon_map_moments(FAKE, 5, 2, 10, FAKE, FAKE, mw, None) == EINVAL
+    assert lib.ufalcon_map_moments(FAKE, 0, 2, 10, FAKE, FAKE, mw - 8, None) == EWORKSPACE

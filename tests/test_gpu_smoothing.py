@@ -1,0 +1,126 @@
+"""GPU parity: spherical-harmonic synthesis, Gaussian smoothing and the map
+moments of section 3.3 (eqs. (12), (13)) against the oracle.
+
+Tolerances: synthesis is FP64 on both sides (recurrence and twiddle rounding
+as for the analysis), bounded by 1e-10 of the largest |map| value; moments are
+compared with the oracle's exactly rounded sums to 1e-12 (relative, and
+relative to the standard deviation for the mean).
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1801_05745_amd as uf
+import synth
+from oracle import spectra as S
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+MAP_TOL = 1e-10
+
+
+def _alm(lmax, seed):
+    """Seeded coefficients as the full [m, l] array (a_l0 real)."""
+    n = (lmax + 1) * (lmax + 1)
+    v = synth.normal64(2 * n, seed=seed, stream=51).numpy()
+    full = (v[:n] + 1j * v[n:]).reshape(lmax + 1, lmax + 1)
+    full[0] = full[0].real
+    for m in range(lmax + 1):
+        full[m, :m] = 0
+    return full
+
+
+def _packed(full):
+    return torch.from_numpy(S.pack_alm(full, full.shape[1] - 1)).to(DEV)
+
+
+@pytest.mark.parametrize("nside,lmax,beam_sigma,out_dtype", [
+    (1, 2, None, torch.float64), (2, 5, None, torch.float64), (4, 11, 0.2, torch.float64),
+    (4, 20, None, torch.float32), (16, 47, None, torch.float64), (32, 95, math.radians(2.0), torch.float64),
+])
+def test_alm2map_full_parity(ufalcon, nside, lmax, beam_sigma, out_dtype):
+    full = _alm(lmax, seed=nside)
+    beam = None if beam_sigma is None else uf.gaussian_beam(beam_sigma, lmax)
+    got = uf.alm2map(_packed(full), nside, lmax, beam, out_dtype=out_dtype).cpu().double().numpy()
+    want = S.alm2map(full, nside, None if beam_sigma is None else S.gaussian_beam(beam_sigma, lmax))
+    tol = MAP_TOL if out_dtype == torch.float64 else 2.0 ** -23
+    assert np.abs(got - want).max() <= tol * np.abs(want).max()
+
+
+def test_gaussian_beam(ufalcon):
+    sigma = math.radians(10.8 / 60.0)
+    b = uf.gaussian_beam(sigma, 3071).cpu().numpy()
+    np.testing.assert_allclose(b, S.gaussian_beam(sigma, 3071), rtol=1e-14, atol=1e-300)
+
+
+@pytest.mark.parametrize("nside,lmax,rings", [
+    (1024, 1023, [0, 1, 500, 1023, 1024, 2047, 2048, 3000, 4094]),
+    (2048, 300, [0, 7, 2047, 4095, 8190]),        # several ring-pair blocks
+])
+def test_alm2map_sampled_rings(ufalcon, nside, lmax, rings):
+    full = _alm(lmax, seed=nside + lmax)
+    got = uf.alm2map(_packed(full), nside, lmax).cpu().numpy()
+    want = S.alm2map(full, nside, rings=rings)
+    start, count, _, _, _ = S.ring_table(nside)
+    idx = np.concatenate([np.arange(start[r], start[r] + count[r]) for r in rings])
+    assert np.abs(got[idx] - want[idx]).max() <= MAP_TOL * np.abs(want[idx]).max()
+
+
+@pytest.mark.parametrize("l,m", [(3071, 1500), (3071, 3071), (3000, 5), (2047, 0)])
+def test_alm2map_single_high_modes(ufalcon, l, m):
+    # one coefficient at high l, Nside 1024, lmax 3071: exercises the 2^600 scaling of lambda_mm
+    nside, lmax = 1024, 3071
+    full = np.zeros((lmax + 1, lmax + 1), dtype=complex)
+    full[m, l] = 1.0 - 0.5j if m else 1.0
+    got = uf.alm2map(_packed(full), nside, lmax).cpu().numpy()
+    rings = [0, 3, 100, 1023, 1500, 2047, 3500, 4094]
+    want = S.alm2map(full, nside, rings=rings)
+    start, count, _, _, _ = S.ring_table(nside)
+    idx = np.concatenate([np.arange(start[r], start[r] + count[r]) for r in rings])
+    scale = max(np.abs(want[idx]).max(), 1e-3)
+    assert np.abs(got[idx] - want[idx]).max() <= MAP_TOL * scale
+
+
+def test_synthesis_is_the_adjoint_of_analysis_at_full_size(ufalcon):
+    # <x, alm2map(a)> = (N_pix / 4 pi) Re sum w_m a_lm conj(map2alm(x)_lm), at Nside 1024, lmax 3071
+    nside, lmax = 1024, 3071
+    npx = S.npix(nside)
+    x = synth.normal64(npx, seed=3, stream=52).to(DEV)
+    nal = (lmax + 1) * (lmax + 2) // 2
+    v = synth.normal64(2 * nal, seed=4, stream=53).to(DEV)
+    a = torch.complex(v[:nal], v[nal:])
+    a[: lmax + 1] = a[: lmax + 1].real.to(torch.complex128)   # m = 0 entries real
+    lhs = float(torch.dot(x, uf.alm2map(a, nside, lmax)))
+    y = uf.map2alm(x, lmax)
+    w = torch.full((nal,), 2.0, dtype=torch.float64, device=DEV)
+    w[: lmax + 1] = 1.0
+    rhs = float((w * (a * y.conj()).real).sum()) * npx / (4 * math.pi)
+    assert lhs == pytest.approx(rhs, rel=1e-10)
+
+
+def test_smooth_parity(ufalcon):
+    nside = 32
+    x = synth.normal64(S.npix(nside), seed=8, stream=54)
+    sigma = math.radians(3.0)
+    got = uf.smooth(x.to(DEV), sigma).cpu().numpy()
+    lmax = 3 * nside - 1
+    want = S.alm2map(S.map2alm(x.numpy(), nside), nside, S.gaussian_beam(sigma, lmax))
+    assert np.abs(got - want).max() <= MAP_TOL * np.abs(want).max()
+    # smoothing lowers the variance of white noise
+    assert got.var() < 0.1 * x.numpy().var()
+
+
+@pytest.mark.parametrize("nside,dtype,n_maps", [(1, torch.float64, 1), (16, torch.float64, 3), (1024, torch.float32, 1)])
+def test_map_moments_parity(ufalcon, nside, dtype, n_maps):
+    npx = S.npix(nside)
+    u = synth.uniform64(n_maps * npx, seed=nside, stream=55).reshape(n_maps, npx)
+    q = (torch.exp(3.0 * u) - 2.0).to(dtype)           # skewed, non-Gaussian values
+    got = uf.map_moments(q.to(DEV)).cpu().numpy()
+    for t in range(n_maps):
+        want = np.array(S.map_moments(q[t].double().numpy()))
+        sd = math.sqrt(want[1])
+        assert abs(got[t, 0] - want[0]) <= 1e-12 * sd
+        np.testing.assert_allclose(got[t, 1:], want[1:], rtol=1e-12)
