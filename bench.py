@@ -52,11 +52,11 @@ FLOPS_PER_INSTANCE = 80
 # reports traffic null.
 PMC_TRAFFIC = {
     "kernel": "keys_kernel<float>",
-    "fetch_kib": 786743.9,
-    "write_kib": 5073815.0,
+    "fetch_kib": 786744.1,
+    "write_kib": 5073815.9,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
-    "sources_sha1": "dc30a2a736041df1730ea7a2bcfe447bb4bc6555",
+    "sources_sha1": "fd29f9c515f52c29cba0ec8f2ac9730417600724",
     "profile": "profiles/keys_kernel_lognormal512_z05_nside1024_pmc.md",
 }
 
@@ -254,7 +254,25 @@ def main():
     ev_cv[1].record(stream)
     torch.cuda.synchronize()
     cov_ms = ev_cv[0].elapsed_time(ev_cv[1]) / 3
-    del alm, cls, cov, corr
+    # smoothing with a Gaussian beam of r.m.s. 10.8 arcmin and the one-point
+    # moments of the smoothed map (section 3.3, eqs. (12), (13))
+    sigma = math.radians(10.8 / 60.0)
+    beam = uf.gaussian_beam(sigma, lmax, device=dev)
+    sm = uf.alm2map(alm, nside, lmax, beam, out_dtype=torch.float32)
+    mom = uf.map_moments(sm)
+    ev_sm = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev_sm[0].record(stream)
+    for _ in range(3):
+        sm = uf.alm2map(alm, nside, lmax, beam, out_dtype=torch.float32)
+    ev_sm[1].record(stream)
+    for _ in range(3):
+        mom = uf.map_moments(sm)
+    ev_sm[2].record(stream)
+    torch.cuda.synchronize()
+    a2m_ms = ev_sm[0].elapsed_time(ev_sm[1]) / 3
+    mom_ms = ev_sm[1].elapsed_time(ev_sm[2]) / 3
+    mom = mom.cpu().tolist()
+    del alm, cls, cov, corr, sm, beam
     uf.release_workspaces()
 
     kap = outs["kappa"].double()
@@ -347,6 +365,16 @@ def main():
             "frac": sht_fl / (sht_ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
         },
         "cl_covariance": {"realisations": n_real, "bands": lmax + 1, "launch_ms": cov_ms},
+        "smoothing": {
+            "kernel": "ufalcon_alm2map (Legendre synthesis + inverse ring DFTs, FP64), Gaussian beam",
+            "sigma_arcmin": 10.8, "lmax": lmax,
+            "alm2map_ms": a2m_ms,
+            "achieved": sht_fl / (a2m_ms / 1e3) / 1e12,
+            "frac": sht_fl / (a2m_ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+            "moments_ms": mom_ms,
+            "moments_GBs": 2 * 4 * uf.npix(nside) / (mom_ms / 1e3) / 1e9,
+            "s2_over_var_s2": mom[3] / mom[4],
+        },
         "instances_per_s": inst_per_step / (ms_per_step / 1e3),
         "guarded_per_step": st["n_guarded"] / args.steps,
         "unresolved": st["n_unresolved"],
