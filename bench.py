@@ -60,6 +60,17 @@ PMC_TRAFFIC = {
     "profile": "profiles/keys_kernel_lognormal512_z05_nside1024_pmc.md",
 }
 
+# VALU wave instructions of one keys_kernel launch (PMC SQ_INSTS_VALU, same
+# workload), against the issue ceiling: one 64-lane VALU instruction occupies a
+# SIMD for 4 cycles, so 256 CUs x 4 SIMDs x 2.4 GHz / 4 = 6.14e11 per second.
+PMC_VALU = {
+    "instructions": 5.065e+09,
+    "fp64_instructions": 1.638e+09,
+    "sources_sha1": "fd29f9c515f52c29cba0ec8f2ac9730417600724",
+    "profile": "profiles/keys_kernel_lognormal512_z05_nside1024_instmix.md",
+}
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+
 
 def sources_sha1():
     """sha1 over the library sources (csrc/*.hip, csrc/*.hpp, include/ufalcon.h)."""
@@ -82,6 +93,17 @@ def measured_traffic():
     if t["fetch_kib"] is None or t["sources_sha1"] != sources_sha1():
         return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
+def valu_issue(launch_ms):
+    """Measured VALU instruction issue rate of the decision pass against its ceiling
+    (null once the library sources differ from those the counters were taken on)."""
+    v = PMC_VALU
+    if v["sources_sha1"] != sources_sha1():
+        return None
+    rate = v["instructions"] / (launch_ms / 1e3)
+    return {"instructions": v["instructions"], "fp64_share": v["fp64_instructions"] / v["instructions"],
+            "achieved_per_s": rate, "peak_per_s": VALU_ISSUE_PEAK, "frac": rate / VALU_ISSUE_PEAK}
 
 
 def parse():
@@ -325,6 +347,7 @@ def main():
             "flops_per_image": FLOPS_PER_IMAGE,
             "flops_per_instance": FLOPS_PER_INSTANCE,
             "images": images,
+            "valu_issue": valu_issue(decide_ms),
         },
         "roofline_hbm": {
             "bound": "hbm",
