@@ -655,11 +655,11 @@ __global__ __launch_bounds__(kDftThreads) void ring_idft_kernel(const double2 *_
     const int64_t jp = (int64_t)blockIdx.x * kDftThreads + threadIdx.x;  // j'
     const int64_t n = 4 * n4;
 
-    double acc[RG][4];
+    double acc[RG][4], acn[RG][4];  // sums of Re P cos and Im P sin; the output is their difference
 #pragma unroll
     for (int g = 0; g < RG; ++g)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[g][q] = 0.0;
+        for (int q = 0; q < 4; ++q) acc[g][q] = acn[g][q] = 0.0;
     double ws, wc;  // step e^{2 pi i j' / n4}
     sincospi(2.0 * (double)(jp % n4) / (double)n4, &ws, &wc);
 
@@ -672,6 +672,12 @@ __global__ __launch_bounds__(kDftThreads) void ring_idft_kernel(const double2 *_
             if (kk < cnt) {
                 const int64_t kp = kb + kk;
                 const bool shift = ring_shift(N, ring[g]) != 0;
+                // h0 = e^{i pi k'/n}: the shift phase of index k' + t n4 is h0 e^{i pi t/4},
+                // and h0^2 = e^{2 pi i k'/n} is the twiddle of q = 1
+                double s0, c0;
+                sincospi((double)kp / (double)n, &s0, &c0);
+                constexpr double kR = 0.70710678118654752440;  // cos(pi/4)
+                const double er[4] = {1.0, kR, 0.0, -kR}, ei[4] = {0.0, kR, 1.0, kR};
                 double2 Hh[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
@@ -684,8 +690,7 @@ __global__ __launch_bounds__(kDftThreads) void ring_idft_kernel(const double2 *_
                         hi = fma(cm, f.y, hi);
                     }
                     if (shift) {  // e^{i pi kf / n}
-                        double s, c;
-                        sincospi((double)kf / (double)n, &s, &c);
+                        const double c = c0 * er[t] - s0 * ei[t], s = c0 * ei[t] + s0 * er[t];
                         const double r0 = hr * c - hi * s;
                         hi = hr * s + hi * c;
                         hr = r0;
@@ -700,8 +705,7 @@ __global__ __launch_bounds__(kDftThreads) void ring_idft_kernel(const double2 *_
                 const double qr[4] = {ar + cr, br - di, ar - cr, br + di};
                 const double qi[4] = {ai + ci, bi + dr, ai - ci, bi - dr};
                 // e^{2 pi i k' q / n}
-                double s1, c1;
-                sincospi(2.0 * (double)kp / (double)n, &s1, &c1);
+                const double c1 = c0 * c0 - s0 * s0, s1 = 2.0 * c0 * s0;
                 const double c2 = c1 * c1 - s1 * s1, s2 = 2.0 * c1 * s1;
                 const double c3 = c2 * c1 - s2 * s1, s3 = c2 * s1 + s2 * c1;
                 const double tc[4] = {1.0, c1, c2, c3}, ts[4] = {0.0, s1, s2, s3};
@@ -715,13 +719,18 @@ __global__ __launch_bounds__(kDftThreads) void ring_idft_kernel(const double2 *_
         double wr, wi;
         sincospi(2.0 * (double)((jp * kb) % n4) / (double)n4, &wi, &wr);
         for (int kk = 0; kk < cnt; ++kk) {
+            // all of this step's LDS reads first, so that they are in flight together
+            double2 P[RG][4];
+#pragma unroll
+            for (int g = 0; g < RG; ++g)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) P[g][q] = ps[g][q][kk];
 #pragma unroll
             for (int g = 0; g < RG; ++g)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const double2 P = ps[g][q][kk];
-                    acc[g][q] = fma(P.x, wr, acc[g][q]);
-                    acc[g][q] = fma(-P.y, wi, acc[g][q]);
+                    acc[g][q] = fma(P[g][q].x, wr, acc[g][q]);
+                    acn[g][q] = fma(P[g][q].y, wi, acn[g][q]);
                 }
             const double nr = fma(wr, wc, -(wi * ws));
             const double ni = fma(wr, ws, wi * wc);
@@ -736,7 +745,7 @@ __global__ __launch_bounds__(kDftThreads) void ring_idft_kernel(const double2 *_
         if (!valid[g]) continue;
         T *dst = map + ring_first(N, ring[g]) + 4 * jp;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dst[q] = (T)acc[g][q];
+        for (int q = 0; q < 4; ++q) dst[q] = (T)(acc[g][q] - acn[g][q]);
     }
 }
 
