@@ -261,6 +261,24 @@ __global__ void legendre_coef_kernel(int32_t lmax, double2 *__restrict__ coef) {
 }
 
 // ------------------------------------------------------------------ Legendre contraction
+// Sum over the 16 lanes of a DPP row: exchanges within quads (lane ^ 1, ^ 2),
+// then half-row and row mirrors.  Every lane of the row ends with the same
+// value, ((q0 + q1) + (q2 + q3)) of its quad sums, so the order is fixed.
+template <int kCtrl>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), kCtrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), kCtrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row_sum16(double v) {
+    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return v;
+}
+static_assert(kLegLanes == 16, "row_sum16 sums one DPP row");
+
 // State of the ring pairs one lane owns: z, the scaled recurrence pair
 // (mu_{l-2}, mu_{l-1}) times 2^{600 k}, and the folded ring sums E, O (zero
 // while k > 0, i.e. while the pair's lambda is below 2^-300).
@@ -393,11 +411,15 @@ __global__ __launch_bounds__(kLegThreads) void legendre_kernel(const double2 *__
 #pragma unroll
         for (int q = 0; q < 2 * kLegC; ++q) red[kLegBufs == 2 ? buf : 0][q][tid] = acc[q];
         __syncthreads();
-        double s = 0.0;
+        // this lane's 16 values summed as a tree, then the 16 lanes of the row
+        double v[kLegThreads / kLegLanes];
 #pragma unroll
-        for (int t = 0; t < kLegThreads / kLegLanes; ++t) s += red[kLegBufs == 2 ? buf : 0][o][part + kLegLanes * t];
+        for (int t = 0; t < kLegThreads / kLegLanes; ++t) v[t] = red[kLegBufs == 2 ? buf : 0][o][part + kLegLanes * t];
 #pragma unroll
-        for (int d = kLegLanes / 2; d > 0; d /= 2) s += __shfl_xor(s, d, kLegLanes);
+        for (int w2 = kLegThreads / kLegLanes / 2; w2 > 0; w2 /= 2)
+#pragma unroll
+            for (int t = 0; t < w2; ++t) v[t] += v[t + w2];
+        const double s = row_sum16(v[0]);
         const int l = l0 + o / 2;
         if (part == 0 && l <= lmax) {
             double *dst = reinterpret_cast<double *>(out + base + l);
