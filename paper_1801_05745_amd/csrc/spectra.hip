@@ -32,13 +32,14 @@ namespace {
 constexpr int kDftThreads = 256;
 constexpr int kDftJ = 64;      // pixels per staged chunk (and twiddle re-seed period)
 constexpr int kEqRings = 4;    // equatorial rings (all 4N long) per workgroup
-constexpr int kLegThreads = 256;
+constexpr int kLegThreads = 128;
 constexpr int kLegR = 4;       // ring pairs per lane
 constexpr int kLegC = 8;       // l values per reduction chunk
-constexpr int kLegStage = 128; // l values per coefficient stage in LDS
+constexpr int kLegStage = kLegThreads < 128 ? kLegThreads : 128;  // l values per coefficient stage in LDS
 constexpr int kLegBufs = 2;    // reduction buffers (1: two barriers per chunk)
 constexpr int kLegLanes = kLegThreads / (2 * kLegC);  // lanes summing one output
 static_assert(kLegLanes * 2 * kLegC == kLegThreads && (kLegLanes & (kLegLanes - 1)) == 0, "reduction layout");
+static_assert(kLegStage % kLegC == 0 && kLegStage / kLegC >= 2, "coefficient stages");
 constexpr double kScaleUp = 0x1p600;
 constexpr double kScaleDown = 0x1p-600;
 constexpr double kTiny = 0x1p-300;
@@ -261,23 +262,25 @@ __global__ void legendre_coef_kernel(int32_t lmax, double2 *__restrict__ coef) {
 }
 
 // ------------------------------------------------------------------ Legendre contraction
-// Sum over the 16 lanes of a DPP row: exchanges within quads (lane ^ 1, ^ 2),
-// then half-row and row mirrors.  Every lane of the row ends with the same
-// value, ((q0 + q1) + (q2 + q3)) of its quad sums, so the order is fixed.
+// DPP lane sums: exchanges within quads (lane ^ 1, ^ 2), then half-row and row
+// mirrors.  Every lane of a group ends with the same value (the additions are
+// pairwise and commutative), so the order is fixed.
 template <int kCtrl>
 __device__ __forceinline__ double dpp_f64(double v) {
     const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), kCtrl, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), kCtrl, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ double row_sum16(double v) {
-    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
-    v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
-    v += dpp_f64<0x141>(v);  // row_half_mirror
-    v += dpp_f64<0x140>(v);  // row_mirror
+// Sum over aligned groups of kL = 4, 8 or 16 lanes.
+template <int kL>
+__device__ __forceinline__ double lane_group_sum(double v) {
+    static_assert(kL == 4 || kL == 8 || kL == 16, "a quad, half-row or row");
+    v += dpp_f64<0xB1>(v);                    // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);                    // quad_perm [2, 3, 0, 1]
+    if (kL >= 8) v += dpp_f64<0x141>(v);      // row_half_mirror
+    if (kL >= 16) v += dpp_f64<0x140>(v);     // row_mirror
     return v;
 }
-static_assert(kLegLanes == 16, "row_sum16 sums one DPP row");
 
 // State of the ring pairs one lane owns: z, the scaled recurrence pair
 // (mu_{l-2}, mu_{l-1}) times 2^{600 k}, and the folded ring sums E, O (zero
@@ -419,7 +422,7 @@ __global__ __launch_bounds__(kLegThreads) void legendre_kernel(const double2 *__
         for (int w2 = kLegThreads / kLegLanes / 2; w2 > 0; w2 /= 2)
 #pragma unroll
             for (int t = 0; t < w2; ++t) v[t] += v[t + w2];
-        const double s = row_sum16(v[0]);
+        const double s = lane_group_sum<kLegLanes>(v[0]);
         const int l = l0 + o / 2;
         if (part == 0 && l <= lmax) {
             double *dst = reinterpret_cast<double *>(out + base + l);
