@@ -274,7 +274,8 @@ __global__ __launch_bounds__(kBinBlock, 6) void keys_kernel(KeyParams kp) {
 // No global atomics; ranks inside a sub-tile come from LDS atomics.
 struct PartStep {
     const uint32_t *in;
-    uint32_t *out;
+    uint32_t *out;              // level 1: full keys
+    uint16_t *out16;            // level 2: the key's cell inside its block (the block is the position)
     int level;
     int nseg;
     const uint32_t *seg_off;    // level 2: [nseg + 1] segment starts in `in`
@@ -453,7 +454,10 @@ __global__ __launch_bounds__(1024) void bucket_base_kernel(const uint32_t *tot, 
 // counts, so the nondeterministic order of the atomics is harmless.
 constexpr int kScatThreads = 512;
 constexpr int kSub = 8192;
+template <typename OutT>
 __global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, int chunk_k, int kmax) {
+    static_assert(sizeof(OutT) == 4 || sizeof(OutT) == 2, "full keys or 16-bit cell indices");
+    static_assert(kBlockShift <= 16, "a cell index inside a block fits 16 bits");
     constexpr int kW = kScatThreads / 64;
     constexpr int kPer = kSub / kScatThreads;  // keys per thread per sub-tile
     static_assert(kMaxBins <= kScatThreads, "one bucket per thread in the scan");
@@ -530,7 +534,12 @@ __global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, i
                     const uint32_t sidx = (uint32_t)(j * kScatThreads + tid);
                     const uint32_t key = skeys[min(sidx, nv - 1u)];
                     const uint32_t pos = dst[(key >> ps.shift) - bin0] + sidx;
-                    if (sidx < nv) ps.out[pos] = key;
+                    if (sidx < nv) {
+                        if constexpr (sizeof(OutT) == 4)
+                            ps.out[pos] = key;
+                        else
+                            ps.out16[pos] = (uint16_t)(key & (kBlockCells - 1));
+                    }
                 }
             }
             lds_barrier();                                                  // 6
@@ -540,7 +549,7 @@ __global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, i
 }
 
 // 5. one workgroup per cell block: LDS histogram, then counts += histogram
-__global__ __launch_bounds__(kAccThreads) void accumulate_kernel(const uint32_t *keys, const uint32_t *offb,
+__global__ __launch_bounds__(kAccThreads) void accumulate_kernel(const uint16_t *cells, const uint32_t *offb,
                                                                  int64_t nblk, int64_t ncells, uint32_t *counts,
                                                                  const PartHeader *hdr, int chunk_k, int kmax) {
     __shared__ uint32_t h[kBlockCells];
@@ -556,11 +565,11 @@ __global__ __launch_bounds__(kAccThreads) void accumulate_kernel(const uint32_t 
 #pragma unroll
             for (int u = 0; u < kAccUnroll; ++u) {
                 const uint32_t i = base + u * kAccThreads + threadIdx.x;
-                kk[u] = i < hi ? keys[i] : kNoKey;
+                kk[u] = i < hi ? (uint32_t)cells[i] : kNoKey;
             }
 #pragma unroll
             for (int u = 0; u < kAccUnroll; ++u)
-                if (kk[u] != kNoKey) atomicAdd(&h[kk[u] & (kBlockCells - 1)], 1u);
+                if (kk[u] != kNoKey) atomicAdd(&h[kk[u]], 1u);
         }
         lds_barrier();
         const int64_t c0 = blk * kBlockCells;
@@ -699,7 +708,8 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
 
     PartStep l2 = l1;
     l2.in = keysb;
-    l2.out = keysa;
+    l2.out = nullptr;
+    l2.out16 = reinterpret_cast<uint16_t *>(keysa);
     l2.level = 2;
     l2.nseg = L.nb1;
     l2.seg_off = off1;
@@ -709,7 +719,7 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
     l2.bucket_base = offb;
 
     const unsigned hist_grid = resident_grid(tile_hist_kernel, kPartThreads, cus);
-    const unsigned scat_grid = resident_grid(scatter_kernel, kScatThreads, cus);
+    const unsigned scat_grid = resident_grid(scatter_kernel<uint32_t>, kScatThreads, cus);
     const unsigned acc_grid = resident_grid(accumulate_kernel, kAccThreads, cus);
     for (int k = 0; k < L.kmax; ++k) {
         hipLaunchKernelGGL(reset_chunk_kernel, dim3(1), dim3(64), 0, s, hdr);
@@ -723,16 +733,17 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
         hipLaunchKernelGGL(bucket_scan_kernel, dim3((unsigned)L.nb1), dim3(256), 0, s, l1, k, L.kmax);
         hipLaunchKernelGGL(bucket_base_kernel, dim3(1), dim3(1024), 0, s, tot, (int64_t)L.nb1, off1, tiles1, hdr, k,
                            L.kmax);
-        hipLaunchKernelGGL(scatter_kernel, dim3(scat_grid), dim3(kScatThreads), 0, s, l1, k, L.kmax);
+        hipLaunchKernelGGL(scatter_kernel<uint32_t>, dim3(scat_grid), dim3(kScatThreads), 0, s, l1, k, L.kmax);
         // level 2: by cell block inside each level-1 bucket
         hipLaunchKernelGGL(tile_hist_kernel, dim3(hist_grid), dim3(kPartThreads), 0, s, l2, k, L.kmax);
         hipLaunchKernelGGL(bucket_scan_kernel, dim3((unsigned)L.nblk), dim3(256), 0, s, l2, k, L.kmax);
         hipLaunchKernelGGL(bucket_base_kernel, dim3(1), dim3(1024), 0, s, tot, L.nblk, offb, (uint32_t *)nullptr, hdr,
                            k, L.kmax);
-        hipLaunchKernelGGL(scatter_kernel, dim3(scat_grid), dim3(kScatThreads), 0, s, l2, k, L.kmax);
+        hipLaunchKernelGGL(scatter_kernel<uint16_t>, dim3(scat_grid), dim3(kScatThreads), 0, s, l2, k, L.kmax);
         timer_mark(timer, UFALCON_PHASE_PARTITION, s);
         hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)std::min<int64_t>(L.nblk, acc_grid)), dim3(kAccThreads), 0,
-                           s, keysa, offb, L.nblk, ncells, p.c.counts, hdr, k, L.kmax);
+                           s, reinterpret_cast<const uint16_t *>(keysa), offb, L.nblk, ncells, p.c.counts, hdr, k,
+                           L.kmax);
         timer_mark(timer, UFALCON_PHASE_ACCUMULATE, s);
     }
     hipLaunchKernelGGL(part_guarded_kernel, dim3(64), dim3(256), 0, s, p);
