@@ -52,11 +52,11 @@ FLOPS_PER_INSTANCE = 80
 # reports traffic null.
 PMC_TRAFFIC = {
     "kernel": "keys_kernel<float>",
-    "fetch_kib": 786744.1,
-    "write_kib": 5073815.9,
+    "fetch_kib": 786740.3,
+    "write_kib": 5073814.8,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
-    "sources_sha1": "fd29f9c515f52c29cba0ec8f2ac9730417600724",
+    "sources_sha1": "bd0737e0342d40a25d6ba525e3152cab255a8aa8",
     "profile": "profiles/keys_kernel_lognormal512_z05_nside1024_pmc.md",
 }
 
@@ -66,7 +66,7 @@ PMC_TRAFFIC = {
 PMC_VALU = {
     "instructions": 5.065e+09,
     "fp64_instructions": 1.638e+09,
-    "sources_sha1": "fd29f9c515f52c29cba0ec8f2ac9730417600724",
+    "sources_sha1": "bd0737e0342d40a25d6ba525e3152cab255a8aa8",
     "profile": "profiles/keys_kernel_lognormal512_z05_nside1024_instmix.md",
 }
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
