@@ -13,10 +13,14 @@ Prints one JSON line.  value = input particles binned per second (whole step).
 The roofline object describes the dominant kernel, the FP64 decision pass of
 the binning call (keys_kernel: shell and RING pixel of every image), timed with
 HIP events that the library records on the stream the kernel runs on; it is
-bound by FP64 vector arithmetic.  roofline_hbm gives the whole binning call
-against HBM bandwidth (the fraction of the HBM roofline the task asks for) and
-born the Born pass.  cpu_baseline times the oracle on one host core on a
-bounded sample of the same catalogue.
+bound by FP64 vector arithmetic (valu_issue: its measured VALU instruction rate
+against the issue ceiling).  roofline_hbm gives the whole binning call against
+HBM bandwidth, born / overdensity / adjoint the streaming passes.  After the
+timed steps the bench also times, each on its own, the power spectrum of the
+last kappa map, the covariance of 150 spectra, Gaussian smoothing and the
+moments of the smoothed map, and (unless --no-batched) the batched workload of
+16 realisations.  cpu_baseline times the oracle on one host core on a bounded
+sample of the same catalogue.
 """
 
 from __future__ import annotations
@@ -140,8 +144,8 @@ def sht_flops(nside, lmax):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
-              f"of this path is described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build runs the path on "
+              f"a single GPU and has no multi-GPU sharding.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
