@@ -130,13 +130,14 @@ def parse():
 
 def sht_flops(nside, lmax):
     """Algorithmic FP64 flops of one map2alm: the ring DFTs as four direct
-    length-n/4 DFTs per ring (4 flops per real-by-complex multiply-add) and
-    the Legendre step, 7 flops per (l, m, ring pair): the three-term
+    length-n/4 DFTs per ring (4 flops per real-by-complex multiply-add; on the
+    equatorial rings of an even Nside the even/odd split of the outputs halves
+    that) and the Legendre step, 7 flops per (l, m, ring pair): the three-term
     recurrence (3) and the complex multiply-add with the folded ring sum (4)."""
     N = nside
     n_alm = (lmax + 1) * (lmax + 2) // 2
     legendre = 7 * n_alm * 2 * N
-    dft_eq = (2 * N + 1) * 4 * N * N * 4
+    dft_eq = (2 * N + 1) * 4 * N * N * (2 if N % 2 == 0 else 4)
     dft_polar = sum(2 * 4 * i * i * 4 for i in range(1, N))
     return float(legendre + dft_eq + dft_polar)
 

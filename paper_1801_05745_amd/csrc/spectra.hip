@@ -32,6 +32,7 @@ namespace {
 constexpr int kDftThreads = 256;
 constexpr int kDftJ = 64;      // pixels per staged chunk (and twiddle re-seed period)
 constexpr int kEqRings = 4;    // equatorial rings (all 4N long) per workgroup
+constexpr int kEqRingsSplit = 2;  // the same with the even/odd split of the outputs
 constexpr int kLegThreads = 128;
 constexpr int kLegR = 4;       // ring pairs per lane
 constexpr int kLegC = 8;       // l values per reduction chunk
@@ -79,11 +80,59 @@ __device__ __forceinline__ void ring_z_sin(int64_t N, int64_t i, double &z, doub
 // and F(m) = e^{-i pi m s / n} DFT[m mod n] (aliasing for m >= n).  Lane k'
 // accumulates D_0..D_3 of RG rings of equal length (the twiddle advancing by
 // one complex multiply per j', re-seeded exactly every kDftJ steps), then
-// writes F(m) for every m = k' + t n4 + u n <= lmax.
-template <typename T, bool kPolar>
+// writes F(m) for every m = k' + t n4 + u n <= lmax.  With kSplit (n4 even),
+// lane k' < n4/2 also yields D_q[k' + n4/2]: the sums over even and odd j' are
+// kept apart, D_q[k'] = E + O and D_q[k' + n4/2] = E - O, so every product
+// x w serves two outputs.
+
+// F(m) of one ring from its four D_q[kp].
+__device__ __forceinline__ void ring_dft_outputs(const double (&ar)[4], const double (&ai)[4], int64_t kp, int64_t n4,
+                                                 bool shift, int64_t col, int64_t nring, int32_t lmax,
+                                                 double2 *__restrict__ F) {
+    const int64_t n = 4 * n4;
+    // e^{-2 pi i k' q / n}, q = 1, 2, 3
+    double s1, c1;
+    sincospi(-2.0 * (double)kp / (double)n, &s1, &c1);
+    const double c2 = c1 * c1 - s1 * s1, s2 = 2.0 * c1 * s1;
+    const double c3 = c2 * c1 - s2 * s1, s3 = c2 * s1 + s2 * c1;
+    const double a0r = ar[0], a0i = ai[0];
+    const double a1r = ar[1] * c1 - ai[1] * s1, a1i = ar[1] * s1 + ai[1] * c1;
+    const double a2r = ar[2] * c2 - ai[2] * s2, a2i = ar[2] * s2 + ai[2] * c2;
+    const double a3r = ar[3] * c3 - ai[3] * s3, a3i = ar[3] * s3 + ai[3] * c3;
+    // radix-4 butterfly, (-i)(x + iy) = y - ix
+    double dr[4], di[4];
+    dr[0] = (a0r + a2r) + (a1r + a3r);
+    di[0] = (a0i + a2i) + (a1i + a3i);
+    dr[2] = (a0r + a2r) - (a1r + a3r);
+    di[2] = (a0i + a2i) - (a1i + a3i);
+    dr[1] = (a0r - a2r) + (a1i - a3i);
+    di[1] = (a0i - a2i) - (a1r - a3r);
+    dr[3] = (a0r - a2r) - (a1i - a3i);
+    di[3] = (a0i - a2i) + (a1r - a3r);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int64_t k = kp + t * n4;  // k < n
+        if (k > lmax) break;
+        double gr = dr[t], gi = di[t];
+        if (shift) {  // e^{-i pi k / n}
+            double s, c;
+            sincospi(-(double)k / (double)n, &s, &c);
+            gr = dr[t] * c - di[t] * s;
+            gi = dr[t] * s + di[t] * c;
+        }
+        // F(k + u n) = (-1)^{u s} G(k)
+        for (int64_t m = k, u = 0; m <= lmax; m += n, ++u) {
+            const double sg = (shift && (u & 1)) ? -1.0 : 1.0;
+            F[m * nring + col] = make_double2(sg * gr, sg * gi);
+        }
+    }
+}
+
+template <typename T, bool kPolar, bool kSplit>
 __global__ __launch_bounds__(kDftThreads) void ring_dft_kernel(const T *__restrict__ map, int64_t N, int32_t lmax,
                                                                double2 *__restrict__ F) {
-    constexpr int RG = kPolar ? 2 : kEqRings;
+    constexpr int RG = kPolar ? 2 : (kSplit ? kEqRingsSplit : kEqRings);
+    constexpr int H = kSplit ? 2 : 1;  // accumulators per output pair: even and odd j'
     __shared__ double xs[RG][4][kDftJ];
     const int64_t nring = 4 * N - 1;
     int64_t ring[RG];
@@ -104,23 +153,25 @@ __global__ __launch_bounds__(kDftThreads) void ring_dft_kernel(const T *__restri
         }
         n4 = N;
     }
-    if ((int64_t)blockIdx.x * kDftThreads >= n4) return;  // whole workgroup past this ring length
+    const int64_t nk = kSplit ? n4 / 2 : n4;                  // lanes needed
+    if ((int64_t)blockIdx.x * kDftThreads >= nk) return;  // whole workgroup past this ring length
     const int64_t kp = (int64_t)blockIdx.x * kDftThreads + threadIdx.x;  // k'
-    const int64_t n = 4 * n4;
     int64_t first[RG];
 #pragma unroll
     for (int g = 0; g < RG; ++g) first[g] = ring_first(N, ring[g]);
 
-    double ar[RG][4], ai[RG][4];
+    double ar[H][RG][4], ai[H][RG][4];
 #pragma unroll
-    for (int g = 0; g < RG; ++g)
+    for (int h = 0; h < H; ++h)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) ar[g][q] = ai[g][q] = 0.0;
+        for (int g = 0; g < RG; ++g)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ar[h][g][q] = ai[h][g][q] = 0.0;
     double ws, wc;  // step e^{-2 pi i k' / n4}
     sincospi(-2.0 * (double)(kp % n4) / (double)n4, &ws, &wc);
 
     for (int64_t jb = 0; jb < n4; jb += kDftJ) {
-        const int cnt = (int)(n4 - jb < kDftJ ? n4 - jb : kDftJ);
+        const int cnt = (int)(n4 - jb < kDftJ ? n4 - jb : kDftJ);  // even with kSplit
         for (int e = threadIdx.x; e < RG * 4 * kDftJ; e += kDftThreads) {
             const int g = e / (4 * kDftJ), r = e % (4 * kDftJ);  // r = 4 jj + q: pixels in order
             const int jj = r / 4, q = r % 4;
@@ -129,63 +180,44 @@ __global__ __launch_bounds__(kDftThreads) void ring_dft_kernel(const T *__restri
         __syncthreads();
         double wr, wi;
         sincospi(-2.0 * (double)((kp * jb) % n4) / (double)n4, &wi, &wr);
-        for (int jj = 0; jj < cnt; ++jj) {
+        for (int jj = 0; jj < cnt; jj += H) {
 #pragma unroll
-            for (int g = 0; g < RG; ++g)
+            for (int h = 0; h < H; ++h) {  // jb is even, so the parity of j' is that of h
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const double x = xs[g][q][jj];
-                    ar[g][q] = fma(x, wr, ar[g][q]);
-                    ai[g][q] = fma(x, wi, ai[g][q]);
-                }
-            const double nr = fma(wr, wc, -(wi * ws));
-            const double ni = fma(wr, ws, wi * wc);
-            wr = nr;
-            wi = ni;
+                for (int g = 0; g < RG; ++g)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double x = xs[g][q][jj + h];
+                        ar[h][g][q] = fma(x, wr, ar[h][g][q]);
+                        ai[h][g][q] = fma(x, wi, ai[h][g][q]);
+                    }
+                const double nr = fma(wr, wc, -(wi * ws));
+                const double ni = fma(wr, ws, wi * wc);
+                wr = nr;
+                wi = ni;
+            }
         }
         __syncthreads();
     }
-    if (kp >= n4) return;
-    // e^{-2 pi i k' q / n}, q = 1, 2, 3
-    double s1, c1;
-    sincospi(-2.0 * (double)kp / (double)n, &s1, &c1);
-    const double c2 = c1 * c1 - s1 * s1, s2 = 2.0 * c1 * s1;
-    const double c3 = c2 * c1 - s2 * s1, s3 = c2 * s1 + s2 * c1;
+    if (kp >= nk) return;
 #pragma unroll
     for (int g = 0; g < RG; ++g) {
         if (!valid[g]) continue;
-        const double a0r = ar[g][0], a0i = ai[g][0];
-        const double a1r = ar[g][1] * c1 - ai[g][1] * s1, a1i = ar[g][1] * s1 + ai[g][1] * c1;
-        const double a2r = ar[g][2] * c2 - ai[g][2] * s2, a2i = ar[g][2] * s2 + ai[g][2] * c2;
-        const double a3r = ar[g][3] * c3 - ai[g][3] * s3, a3i = ar[g][3] * s3 + ai[g][3] * c3;
-        // radix-4 butterfly, (-i)(x + iy) = y - ix
-        double dr[4], di[4];
-        dr[0] = (a0r + a2r) + (a1r + a3r);
-        di[0] = (a0i + a2i) + (a1i + a3i);
-        dr[2] = (a0r + a2r) - (a1r + a3r);
-        di[2] = (a0i + a2i) - (a1i + a3i);
-        dr[1] = (a0r - a2r) + (a1i - a3i);
-        di[1] = (a0i - a2i) - (a1r - a3r);
-        dr[3] = (a0r - a2r) - (a1i - a3i);
-        di[3] = (a0i - a2i) + (a1r - a3r);
         const bool shift = ring_shift(N, ring[g]) != 0;
         const int64_t col = ring[g] - 1;
+        if (kSplit) {
+            double lo_r[4], lo_i[4], hi_r[4], hi_i[4];  // D_q[k'] = E + O, D_q[k' + n4/2] = E - O
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int64_t k = kp + t * n4;  // k < n
-            if (k > lmax) break;
-            double gr = dr[t], gi = di[t];
-            if (shift) {  // e^{-i pi k / n}
-                double s, c;
-                sincospi(-(double)k / (double)n, &s, &c);
-                gr = dr[t] * c - di[t] * s;
-                gi = dr[t] * s + di[t] * c;
+            for (int q = 0; q < 4; ++q) {
+                lo_r[q] = ar[0][g][q] + ar[H - 1][g][q];
+                lo_i[q] = ai[0][g][q] + ai[H - 1][g][q];
+                hi_r[q] = ar[0][g][q] - ar[H - 1][g][q];
+                hi_i[q] = ai[0][g][q] - ai[H - 1][g][q];
             }
-            // F(k + u n) = (-1)^{u s} G(k)
-            for (int64_t m = k, u = 0; m <= lmax; m += n, ++u) {
-                const double sg = (shift && (u & 1)) ? -1.0 : 1.0;
-                F[m * nring + col] = make_double2(sg * gr, sg * gi);
-            }
+            ring_dft_outputs(lo_r, lo_i, kp, n4, shift, col, nring, lmax, F);
+            ring_dft_outputs(hi_r, hi_i, kp + n4 / 2, n4, shift, col, nring, lmax, F);
+        } else {
+            ring_dft_outputs(ar[0][g], ai[0][g], kp, n4, shift, col, nring, lmax, F);
         }
     }
 }
@@ -652,10 +684,11 @@ __global__ __launch_bounds__(kLegThreads) void legendre_synth_kernel(const doubl
 //   map[4j' + q] = Re sum_{k'<n4} P_q[k'] e^{2 pi i k' j'/n4},
 //   P_q[k'] = e^{2 pi i k' q/n} sum_t i^{t q} H[k' + t n4].
 // Lane j' accumulates the four outputs of RG rings of equal length.
-template <typename T, bool kPolar>
+template <typename T, bool kPolar, bool kSplit>
 __global__ __launch_bounds__(kDftThreads) void ring_idft_kernel(const double2 *__restrict__ F, int64_t N,
                                                                 int32_t lmax, T *__restrict__ map) {
-    constexpr int RG = kPolar ? 2 : kEqRings;
+    constexpr int RG = kPolar ? 2 : (kSplit ? kEqRingsSplit : kEqRings);
+    constexpr int H = kSplit ? 2 : 1;  // with kSplit: sums over even and odd k' kept apart
     __shared__ double2 ps[RG][4][kDftJ];
     const int64_t nring = 4 * N - 1;
     int64_t ring[RG];
@@ -676,15 +709,19 @@ __global__ __launch_bounds__(kDftThreads) void ring_idft_kernel(const double2 *_
         }
         n4 = N;
     }
-    if ((int64_t)blockIdx.x * kDftThreads >= n4) return;
+    const int64_t nj = kSplit ? n4 / 2 : n4;  // lanes needed
+    if ((int64_t)blockIdx.x * kDftThreads >= nj) return;
     const int64_t jp = (int64_t)blockIdx.x * kDftThreads + threadIdx.x;  // j'
     const int64_t n = 4 * n4;
 
-    double acc[RG][4], acn[RG][4];  // sums of Re P cos and Im P sin; the output is their difference
+    // sums of Re P cos and Im P sin (the output is their difference), per parity of k'
+    double acc[H][RG][4], acn[H][RG][4];
 #pragma unroll
-    for (int g = 0; g < RG; ++g)
+    for (int h = 0; h < H; ++h)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[g][q] = acn[g][q] = 0.0;
+        for (int g = 0; g < RG; ++g)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[h][g][q] = acn[h][g][q] = 0.0;
     double ws, wc;  // step e^{2 pi i j' / n4}
     sincospi(2.0 * (double)(jp % n4) / (double)n4, &ws, &wc);
 
@@ -743,34 +780,48 @@ __global__ __launch_bounds__(kDftThreads) void ring_idft_kernel(const double2 *_
         __syncthreads();
         double wr, wi;
         sincospi(2.0 * (double)((jp * kb) % n4) / (double)n4, &wi, &wr);
-        for (int kk = 0; kk < cnt; ++kk) {
-            // all of this step's LDS reads first, so that they are in flight together
-            double2 P[RG][4];
+        for (int kk = 0; kk < cnt; kk += H) {
 #pragma unroll
-            for (int g = 0; g < RG; ++g)
+            for (int h = 0; h < H; ++h) {  // kb is even, so the parity of k' is that of h
+                // all of this step's LDS reads first, so that they are in flight together
+                double2 P[RG][4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) P[g][q] = ps[g][q][kk];
+                for (int g = 0; g < RG; ++g)
 #pragma unroll
-            for (int g = 0; g < RG; ++g)
+                    for (int q = 0; q < 4; ++q) P[g][q] = ps[g][q][kk + h];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    acc[g][q] = fma(P[g][q].x, wr, acc[g][q]);
-                    acn[g][q] = fma(P[g][q].y, wi, acn[g][q]);
-                }
-            const double nr = fma(wr, wc, -(wi * ws));
-            const double ni = fma(wr, ws, wi * wc);
-            wr = nr;
-            wi = ni;
+                for (int g = 0; g < RG; ++g)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        acc[h][g][q] = fma(P[g][q].x, wr, acc[h][g][q]);
+                        acn[h][g][q] = fma(P[g][q].y, wi, acn[h][g][q]);
+                    }
+                const double nr = fma(wr, wc, -(wi * ws));
+                const double ni = fma(wr, ws, wi * wc);
+                wr = nr;
+                wi = ni;
+            }
         }
         __syncthreads();
     }
-    if (jp >= n4) return;
+    if (jp >= nj) return;
 #pragma unroll
     for (int g = 0; g < RG; ++g) {
         if (!valid[g]) continue;
         T *dst = map + ring_first(N, ring[g]) + 4 * jp;
+        if (kSplit) {
+            // map[4 j' + q] = E + O, map[4 (j' + n4/2) + q] = E - O
+            T *dst2 = dst + 2 * n4;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dst[q] = (T)(acc[g][q] - acn[g][q]);
+            for (int q = 0; q < 4; ++q) {
+                const double e = acc[0][g][q] - acn[0][g][q], o = acc[H - 1][g][q] - acn[H - 1][g][q];
+                dst[q] = (T)(e + o);
+                dst2[q] = (T)(e - o);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dst[q] = (T)(acc[0][g][q] - acn[0][g][q]);
+        }
     }
 }
 
@@ -850,6 +901,42 @@ __global__ __launch_bounds__(kMomThreads) void moments_final_kernel(const double
 }
 
 // ------------------------------------------------------------------ host side
+// Inverse ring transforms of one map, in the same arrangement as launch_ring_dft.
+template <typename T>
+void launch_ring_idft(const double2 *F, int64_t N, int32_t lmax, T *mp, hipStream_t s) {
+    const unsigned dx = (unsigned)((N + kDftThreads - 1) / kDftThreads);
+    if (N > 1)
+        hipLaunchKernelGGL((ring_idft_kernel<T, true, false>), dim3(dx, (unsigned)(N - 1)), dim3(kDftThreads), 0, s, F,
+                           N, lmax, mp);
+    if (N % 2 == 0)
+        hipLaunchKernelGGL((ring_idft_kernel<T, false, true>),
+                           dim3((unsigned)((N / 2 + kDftThreads - 1) / kDftThreads),
+                                (unsigned)((2 * N + 1 + kEqRingsSplit - 1) / kEqRingsSplit)),
+                           dim3(kDftThreads), 0, s, F, N, lmax, mp);
+    else
+        hipLaunchKernelGGL((ring_idft_kernel<T, false, false>),
+                           dim3(dx, (unsigned)((2 * N + 1 + kEqRings - 1) / kEqRings)), dim3(kDftThreads), 0, s, F,
+                           N, lmax, mp);
+}
+
+// Ring DFTs of one map: polar ring pairs, then the equatorial rings (split when n4 = N is even).
+template <typename T>
+void launch_ring_dft(const T *mp, int64_t N, int32_t lmax, double2 *F, hipStream_t s) {
+    const unsigned dx = (unsigned)((N + kDftThreads - 1) / kDftThreads);
+    if (N > 1)
+        hipLaunchKernelGGL((ring_dft_kernel<T, true, false>), dim3(dx, (unsigned)(N - 1)), dim3(kDftThreads), 0, s, mp,
+                           N, lmax, F);
+    if (N % 2 == 0)
+        hipLaunchKernelGGL((ring_dft_kernel<T, false, true>),
+                           dim3((unsigned)((N / 2 + kDftThreads - 1) / kDftThreads),
+                                (unsigned)((2 * N + 1 + kEqRingsSplit - 1) / kEqRingsSplit)),
+                           dim3(kDftThreads), 0, s, mp, N, lmax, F);
+    else
+        hipLaunchKernelGGL((ring_dft_kernel<T, false, false>),
+                           dim3(dx, (unsigned)((2 * N + 1 + kEqRings - 1) / kEqRings)), dim3(kDftThreads), 0, s, mp,
+                           N, lmax, F);
+}
+
 struct ShtLayout {
     int64_t N, nring, npair, nalm;
     int32_t lmax, n_rb;
@@ -920,26 +1007,12 @@ extern "C" int ufalcon_map2alm(const void *maps, int dtype, int32_t n_maps, int6
                        lmax, coef);
     UFX_HIP_CHECK(hipGetLastError());
     const double w = 4.0 * M_PI / (double)npix;
-    const dim3 dft_x((unsigned)((N + kDftThreads - 1) / kDftThreads));
     for (int32_t t = 0; t < n_maps; ++t) {
         double2 *a = reinterpret_cast<double2 *>(alm) + (int64_t)t * L.nalm;
-        if (dtype == UFALCON_F32) {
-            const float *mp = static_cast<const float *>(maps) + t * npix;
-            if (N > 1)
-                hipLaunchKernelGGL((ring_dft_kernel<float, true>), dim3(dft_x.x, (unsigned)(N - 1)), dim3(kDftThreads),
-                                   0, s, mp, N, lmax, F);
-            hipLaunchKernelGGL((ring_dft_kernel<float, false>),
-                               dim3(dft_x.x, (unsigned)((2 * N + 1 + kEqRings - 1) / kEqRings)), dim3(kDftThreads), 0,
-                               s, mp, N, lmax, F);
-        } else {
-            const double *mp = static_cast<const double *>(maps) + t * npix;
-            if (N > 1)
-                hipLaunchKernelGGL((ring_dft_kernel<double, true>), dim3(dft_x.x, (unsigned)(N - 1)),
-                                   dim3(kDftThreads), 0, s, mp, N, lmax, F);
-            hipLaunchKernelGGL((ring_dft_kernel<double, false>),
-                               dim3(dft_x.x, (unsigned)((2 * N + 1 + kEqRings - 1) / kEqRings)), dim3(kDftThreads), 0,
-                               s, mp, N, lmax, F);
-        }
+        if (dtype == UFALCON_F32)
+            launch_ring_dft(static_cast<const float *>(maps) + t * npix, N, lmax, F, s);
+        else
+            launch_ring_dft(static_cast<const double *>(maps) + t * npix, N, lmax, F, s);
         double2 *dst = L.n_rb > 1 ? part : a;
         hipLaunchKernelGGL(legendre_kernel<kLegR>, dim3((unsigned)M, (unsigned)L.n_rb), dim3(kLegThreads), 0, s, F, seed,
                            seed_k, coef, N, lmax, w, dst, L.n_rb > 1 ? L.nalm : (int64_t)0);
@@ -1034,23 +1107,10 @@ extern "C" int ufalcon_alm2map(const double *alm, int32_t n_maps, int64_t nside,
         const double2 *a = reinterpret_cast<const double2 *>(alm) + (int64_t)t * L.nalm;
         hipLaunchKernelGGL(legendre_synth_kernel<kLegR>, dim3((unsigned)M, (unsigned)L.n_rb), dim3(kLegThreads), 0, s,
                            a, beam, seed, seed_k, coef, N, lmax, F);
-        if (dtype == UFALCON_F32) {
-            float *mp = static_cast<float *>(maps) + t * npix;
-            if (N > 1)
-                hipLaunchKernelGGL((ring_idft_kernel<float, true>), dim3(dx, (unsigned)(N - 1)), dim3(kDftThreads), 0,
-                                   s, F, N, lmax, mp);
-            hipLaunchKernelGGL((ring_idft_kernel<float, false>),
-                               dim3(dx, (unsigned)((2 * N + 1 + kEqRings - 1) / kEqRings)), dim3(kDftThreads), 0, s, F,
-                               N, lmax, mp);
-        } else {
-            double *mp = static_cast<double *>(maps) + t * npix;
-            if (N > 1)
-                hipLaunchKernelGGL((ring_idft_kernel<double, true>), dim3(dx, (unsigned)(N - 1)), dim3(kDftThreads), 0,
-                                   s, F, N, lmax, mp);
-            hipLaunchKernelGGL((ring_idft_kernel<double, false>),
-                               dim3(dx, (unsigned)((2 * N + 1 + kEqRings - 1) / kEqRings)), dim3(kDftThreads), 0, s, F,
-                               N, lmax, mp);
-        }
+        if (dtype == UFALCON_F32)
+            launch_ring_idft(F, N, lmax, static_cast<float *>(maps) + t * npix, s);
+        else
+            launch_ring_idft(F, N, lmax, static_cast<double *>(maps) + t * npix, s);
         UFX_HIP_CHECK(hipGetLastError());
     }
     return UFALCON_OK;
