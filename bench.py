@@ -52,7 +52,7 @@ FLOPS_PER_INSTANCE = 80
 # runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the same
 # counters read for a 1 GiB device copy (FETCH_SIZE reads half: x2.0;
 # WRITE_SIZE exact: x1.0).  Valid only for the kernel sources they were taken
-# on: the sha1 of csrc/ and include/ at that time is kept, and a mismatch
+# on: the sha1 of the kernel's sources at that time is kept, and a mismatch
 # reports traffic null.
 PMC_TRAFFIC = {
     "kernel": "keys_kernel<float>",
@@ -60,7 +60,7 @@ PMC_TRAFFIC = {
     "write_kib": 5073814.8,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
-    "sources_sha1": "bd0737e0342d40a25d6ba525e3152cab255a8aa8",
+    "sources_sha1": "1bf47961edffb47e7786e536a9a6f584200b6796",
     "profile": "profiles/keys_kernel_lognormal512_z05_nside1024_pmc.md",
 }
 
@@ -70,21 +70,25 @@ PMC_TRAFFIC = {
 PMC_VALU = {
     "instructions": 5.065e+09,
     "fp64_instructions": 1.638e+09,
-    "sources_sha1": "bd0737e0342d40a25d6ba525e3152cab255a8aa8",
+    "sources_sha1": "1bf47961edffb47e7786e536a9a6f584200b6796",
     "profile": "profiles/keys_kernel_lognormal512_z05_nside1024_instmix.md",
 }
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
+# The files keys_kernel is compiled from: partition.hip and what it includes.
+KEYS_KERNEL_SOURCES = ("paper_1801_05745_amd/csrc/partition.hip", "paper_1801_05745_amd/csrc/binning_core.hpp",
+                       "paper_1801_05745_amd/csrc/common.hpp", "paper_1801_05745_amd/csrc/exact.hpp",
+                       "paper_1801_05745_amd/csrc/internal.hpp", "paper_1801_05745_amd/csrc/ring.hpp",
+                       "include/ufalcon.h")
+
+
 def sources_sha1():
-    """sha1 over the library sources (csrc/*.hip, csrc/*.hpp, include/ufalcon.h)."""
-    import glob
+    """sha1 over the sources of keys_kernel (KEYS_KERNEL_SOURCES)."""
     import hashlib
 
     h = hashlib.sha1()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1801_05745_amd", "csrc", "*.hip")) +
-                   glob.glob(os.path.join(ROOT, "paper_1801_05745_amd", "csrc", "*.hpp")) +
-                   [os.path.join(ROOT, "include", "ufalcon.h")])
+    files = sorted(os.path.join(ROOT, f) for f in KEYS_KERNEL_SOURCES)
     for f in files:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
@@ -401,7 +405,8 @@ def main():
             "frac": sht_fl / (a2m_ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
             "moments_ms": mom_ms,
             "moments_GBs": 2 * 4 * uf.npix(nside) / (mom_ms / 1e3) / 1e9,
-            "s2_over_var_s2": mom[3] / mom[4],
+            "s2": mom[3],
+            "sigma_s2": math.sqrt(max(mom[4], 0.0)),
         },
         "instances_per_s": inst_per_step / (ms_per_step / 1e3),
         "guarded_per_step": st["n_guarded"] / args.steps,
