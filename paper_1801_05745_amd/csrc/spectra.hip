@@ -31,6 +31,7 @@ namespace {
 
 constexpr int kDftThreads = 256;
 constexpr int kDftJ = 64;      // pixels per staged chunk (and twiddle re-seed period)
+constexpr int kFoldBatch = 4;  // loads in flight per step of the inverse transform's folds
 constexpr int kEqRings = 4;    // equatorial rings (all 4N long) per workgroup
 constexpr int kEqRingsSplit = 2;  // the same with the even/odd split of the outputs
 constexpr int kLegThreads = 128;
@@ -685,7 +686,7 @@ __global__ __launch_bounds__(kLegThreads) void legendre_synth_kernel(const doubl
 //   P_q[k'] = e^{2 pi i k' q/n} sum_t i^{t q} H[k' + t n4].
 // Lane j' accumulates the four outputs of RG rings of equal length.
 template <typename T, bool kPolar, bool kSplit>
-__global__ __launch_bounds__(kDftThreads) void ring_idft_kernel(const double2 *__restrict__ F, int64_t N,
+__global__ __launch_bounds__(kDftThreads, kPolar ? 4 : (kSplit ? 3 : 1)) void ring_idft_kernel(const double2 *__restrict__ F, int64_t N,
                                                                 int32_t lmax, T *__restrict__ map) {
     constexpr int RG = kPolar ? 2 : (kSplit ? kEqRingsSplit : kEqRings);
     constexpr int H = kSplit ? 2 : 1;  // with kSplit: sums over even and odd k' kept apart
@@ -727,38 +728,62 @@ __global__ __launch_bounds__(kDftThreads) void ring_idft_kernel(const double2 *_
 
     for (int64_t kb = 0; kb < n4; kb += kDftJ) {
         const int cnt = (int)(n4 - kb < kDftJ ? n4 - kb : kDftJ);
+        // First the folded sums H_t[k'] = e^{i pi kf/n} sum_u c_m F_m over m = kf + u n,
+        // kf = k' + t n4 (c_0 = 1, otherwise 2, with the sign (-1)^u on shifted rings),
+        // one (ring, t, k') per work item, so that the long folds of the short polar
+        // rings spread over the workgroup, with kFoldBatch loads in flight per step.
+        for (int e = threadIdx.x; e < RG * 4 * kDftJ; e += kDftThreads) {
+            const int g = e / (4 * kDftJ), t = (e / kDftJ) % 4, kk = e % kDftJ;
+            double hr = 0.0, hi = 0.0;
+            if (kk < cnt) {
+                const int64_t kf = kb + kk + t * n4;  // < n
+                const bool shift = ring_shift(N, ring[g]) != 0;
+                const double2 *col = F + (ring[g] - 1);
+                if (kf == 0 && lmax >= 0) {  // c_0 = 1: start from -F_0, the first term adds 2 F_0
+                    hr = -col[0].x;
+                    hi = -col[0].y;
+                }
+                int64_t mm = kf;
+                for (; mm + (kFoldBatch - 1) * n <= lmax; mm += kFoldBatch * n) {  // u even at each start
+                    double2 f[kFoldBatch];
+#pragma unroll
+                    for (int v = 0; v < kFoldBatch; ++v) f[v] = col[(mm + v * n) * nring];
+#pragma unroll
+                    for (int v = 0; v < kFoldBatch; ++v) {
+                        const double cm = (shift && (v & 1)) ? -2.0 : 2.0;
+                        hr = fma(cm, f[v].x, hr);
+                        hi = fma(cm, f[v].y, hi);
+                    }
+                }
+                for (int v = 0; mm <= lmax; mm += n, ++v) {
+                    const double2 f = col[mm * nring];
+                    const double cm = (shift && (v & 1)) ? -2.0 : 2.0;
+                    hr = fma(cm, f.x, hr);
+                    hi = fma(cm, f.y, hi);
+                }
+                if (shift) {
+                    double sn, cs;
+                    sincospi((double)kf / (double)n, &sn, &cs);
+                    const double r0 = hr * cs - hi * sn;
+                    hi = hr * sn + hi * cs;
+                    hr = r0;
+                }
+            }
+            ps[g][t][kk] = make_double2(hr, hi);
+        }
+        __syncthreads();
+        // then P_q[k'] = e^{2 pi i k' q / n} sum_t i^{tq} H_t[k'], in place: each work
+        // item reads and writes only its own (ring, k') column
         for (int e = threadIdx.x; e < RG * kDftJ; e += kDftThreads) {
             const int g = e / kDftJ, kk = e % kDftJ;
             double2 P[4] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0),
                             make_double2(0.0, 0.0)};
             if (kk < cnt) {
-                const int64_t kp = kb + kk;
-                const bool shift = ring_shift(N, ring[g]) != 0;
-                // h0 = e^{i pi k'/n}: the shift phase of index k' + t n4 is h0 e^{i pi t/4},
-                // and h0^2 = e^{2 pi i k'/n} is the twiddle of q = 1
-                double s0, c0;
-                sincospi((double)kp / (double)n, &s0, &c0);
-                constexpr double kR = 0.70710678118654752440;  // cos(pi/4)
-                const double er[4] = {1.0, kR, 0.0, -kR}, ei[4] = {0.0, kR, 1.0, kR};
                 double2 Hh[4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int64_t kf = kp + t * n4;  // folded index, < n
-                    double hr = 0.0, hi = 0.0;
-                    for (int64_t mm = kf, u = 0; mm <= lmax; mm += n, ++u) {
-                        const double2 f = F[mm * nring + (ring[g] - 1)];
-                        const double cm = (mm == 0 ? 1.0 : 2.0) * ((shift && (u & 1)) ? -1.0 : 1.0);
-                        hr = fma(cm, f.x, hr);
-                        hi = fma(cm, f.y, hi);
-                    }
-                    if (shift) {  // e^{i pi kf / n}
-                        const double c = c0 * er[t] - s0 * ei[t], s = c0 * ei[t] + s0 * er[t];
-                        const double r0 = hr * c - hi * s;
-                        hi = hr * s + hi * c;
-                        hr = r0;
-                    }
-                    Hh[t] = make_double2(hr, hi);
-                }
+                for (int t = 0; t < 4; ++t) Hh[t] = ps[g][t][kk];
+                double s0, c0;
+                sincospi((double)(kb + kk) / (double)n, &s0, &c0);  // h0 = e^{i pi k'/n}
                 // sum_t i^{tq} H_t, i (x + iy) = -y + ix
                 const double ar = Hh[0].x + Hh[2].x, ai = Hh[0].y + Hh[2].y;
                 const double br = Hh[0].x - Hh[2].x, bi = Hh[0].y - Hh[2].y;
@@ -766,7 +791,7 @@ __global__ __launch_bounds__(kDftThreads) void ring_idft_kernel(const double2 *_
                 const double dr = Hh[1].x - Hh[3].x, di = Hh[1].y - Hh[3].y;
                 const double qr[4] = {ar + cr, br - di, ar - cr, br + di};
                 const double qi[4] = {ai + ci, bi + dr, ai - ci, bi - dr};
-                // e^{2 pi i k' q / n}
+                // e^{2 pi i k' q / n} from h0^2
                 const double c1 = c0 * c0 - s0 * s0, s1 = 2.0 * c0 * s0;
                 const double c2 = c1 * c1 - s1 * s1, s2 = 2.0 * c1 * s1;
                 const double c3 = c2 * c1 - s2 * s1, s3 = c2 * s1 + s2 * c1;
@@ -1102,7 +1127,6 @@ extern "C" int ufalcon_alm2map(const double *alm, int32_t n_maps, int64_t nside,
     hipLaunchKernelGGL(legendre_coef_kernel, dim3(blocks_for((M + kLegC - 1) / kLegC, 256), (unsigned)M), dim3(256), 0, s,
                        lmax, coef);
     UFX_HIP_CHECK(hipGetLastError());
-    const unsigned dx = (unsigned)((N + kDftThreads - 1) / kDftThreads);
     for (int32_t t = 0; t < n_maps; ++t) {
         const double2 *a = reinterpret_cast<const double2 *>(alm) + (int64_t)t * L.nalm;
         hipLaunchKernelGGL(legendre_synth_kernel<kLegR>, dim3((unsigned)M, (unsigned)L.n_rb), dim3(kLegThreads), 0, s,
