@@ -26,6 +26,8 @@
 #include "../../include/ufalcon.h"
 #include "internal.hpp"
 
+#include <type_traits>
+
 namespace ufx {
 namespace {
 
@@ -379,15 +381,25 @@ __global__ __launch_bounds__(kLegThreads) void legendre_kernel(const double2 *__
     // buffered): the global load for the next stage is issued at the start of
     // a stage and written to LDS half a stage later, hiding its latency.
     __shared__ double2 cst[2][kLegStage];
-    if (tid < kLegStage) cst[0][tid] = coef[base + min(m + tid, lmax)];
+    // entry of l, with g = 0 past lmax (the recurrence then stays bounded there)
+    auto coef_at = [&](int l) {
+        double2 c = coef[base + min(l, lmax)];
+        c.x = l <= lmax ? c.x : 0.0;
+        return c;
+    };
+    if (tid < kLegStage) cst[0][tid] = coef_at(m + tid);
     __syncthreads();
     double2 pre = make_double2(0.0, 0.0);
-    int buf = 0;
-    for (int l0 = m; l0 <= lmax; l0 += kLegC, buf ^= 1) {
+
+    // One chunk of kLegC values of l.  kRevive: some lane of the wave still has
+    // a pair below 2^-300; once none has, none will again, and the rest of the
+    // loop runs without that bookkeeping (the folded sums then stay in place).
+    auto chunk = [&](int l0, int buf, auto revive_tag) {
+        constexpr bool kRevive = decltype(revive_tag)::value;
         const int ci = (l0 - m) / kLegC;
         const int stage = ci / (kLegStage / kLegC), within = ci % (kLegStage / kLegC);
         const double2 *cs = cst[stage & 1] + within * kLegC;
-        if (within == 0 && tid < kLegStage) pre = coef[base + min(l0 + kLegStage + tid, lmax)];
+        if (within == 0 && tid < kLegStage) pre = coef_at(l0 + kLegStage + tid);
         if (within == kLegStage / kLegC / 2 && tid < kLegStage) cst[(stage + 1) & 1][tid] = pre;
         double2 cf[kLegC];
 #pragma unroll
@@ -396,7 +408,7 @@ __global__ __launch_bounds__(kLegThreads) void legendre_kernel(const double2 *__
 #pragma unroll
         for (int c = 0; c < kLegC; ++c) {
             acc[2 * c] = acc[2 * c + 1] = 0.0;
-            const double g = l0 + c <= lmax ? cf[c].x : 0.0;
+            const double g = cf[c].x;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const double v = fma(-g, S.prev[r], S.z[r] * S.cur[r]);
@@ -409,7 +421,7 @@ __global__ __launch_bounds__(kLegThreads) void legendre_kernel(const double2 *__
         }
         // hand the state to the next chunk: multiply by sigma at its last l
         const double sg = cf[kLegC - 1].y;
-        if (__builtin_amdgcn_ballot_w64(dead)) {
+        if (kRevive) {
             // pairs still below 2^-300 (times their scale) become live once they grow
             uint32_t revive = 0;
             dead = false;
@@ -447,7 +459,7 @@ __global__ __launch_bounds__(kLegThreads) void legendre_kernel(const double2 *__
 #pragma unroll
         for (int q = 0; q < 2 * kLegC; ++q) red[kLegBufs == 2 ? buf : 0][q][tid] = acc[q];
         __syncthreads();
-        // this lane's 16 values summed as a tree, then the 16 lanes of the row
+        // this lane's values summed as a tree, then the kLegLanes lanes of the group
         double v[kLegThreads / kLegLanes];
 #pragma unroll
         for (int t = 0; t < kLegThreads / kLegLanes; ++t) v[t] = red[kLegBufs == 2 ? buf : 0][o][part + kLegLanes * t];
@@ -462,7 +474,13 @@ __global__ __launch_bounds__(kLegThreads) void legendre_kernel(const double2 *__
             dst[o & 1] = (w * cs[o / 2].y) * s;
         }
         if (kLegBufs == 1) __syncthreads();
-    }
+    };
+    // Every chunk has the same barriers in both loops, so the waves of a
+    // workgroup may leave the first loop at different chunks.
+    int l0 = m, buf = 0;
+    for (; l0 <= lmax && __builtin_amdgcn_ballot_w64(dead) != 0; l0 += kLegC, buf ^= 1)
+        chunk(l0, buf, std::true_type{});
+    for (; l0 <= lmax; l0 += kLegC, buf ^= 1) chunk(l0, buf, std::false_type{});
 }
 
 // out[i] = sum_b part[b][i], b in order
@@ -600,9 +618,12 @@ __global__ __launch_bounds__(kLegThreads) void legendre_synth_kernel(const doubl
         }
         dead |= k[r] > 0;
     }
+    // entries of l: (g_l, sigma_l) with g = 0 past lmax (the recurrence then
+    // stays bounded there), and sigma_l b_l a_lm, zero past lmax
     auto stage_entry = [&](int l, double2 &c, double2 &a) {
         const int lc = min(l, lmax);
         c = coef[base + lc];
+        c.x = l <= lmax ? c.x : 0.0;
         const double2 v = alm[base + lc];
         const double f = l <= lmax ? c.y * (beam ? beam[lc] : 1.0) : 0.0;
         a = make_double2(f * v.x, m == 0 ? 0.0 : f * v.y);
@@ -622,7 +643,7 @@ __global__ __launch_bounds__(kLegThreads) void legendre_synth_kernel(const doubl
         }
 #pragma unroll
         for (int c = 0; c < kLegC; ++c) {
-            const double g = l0 + c <= lmax ? cs[c].x : 0.0;
+            const double g = cs[c].x;
             const double2 a = as[c];  // zero past lmax
 #pragma unroll
             for (int r = 0; r < R; ++r) {
