@@ -357,7 +357,8 @@ int ufalcon_alm2cl(const double *alm, int32_t n_maps, int32_t lmax, double *cl, 
  * cl device double [n_real][n_ell]; band_mean device [n_bands]; cov, corr
  * device [n_bands][n_bands] (corr may be NULL); ddof 0 or 1, n_real > ddof;
  * ell_min + n_bands * delta_ell <= n_ell; n_bands <= 65535.  workspace device,
- * at least ufalcon_cl_covariance_workspace_size() bytes (the band powers).
+ * at least ufalcon_cl_covariance_workspace_size() bytes (the band powers and
+ * the standard deviations sqrt(cov[b][b])).
  */
 size_t ufalcon_cl_covariance_workspace_size(int32_t n_real, int32_t n_bands);
 int ufalcon_cl_covariance(const double *cl, int32_t n_real, int32_t n_ell, int32_t ell_min, int32_t delta_ell,

@@ -545,7 +545,15 @@ __global__ void band_mean_kernel(const double *__restrict__ X, int32_t R, int32_
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nb) return;
     double s = 0.0;
-    for (int r = 0; r < R; ++r) s += X[(int64_t)r * nb + b];
+    int r = 0;
+    for (; r + 8 <= R; r += 8) {  // eight loads in flight, the sum still in order
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = X[(int64_t)(r + u) * nb + b];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; r < R; ++r) s += X[(int64_t)r * nb + b];
     mean[b] = s / (double)R;
 }
 
@@ -620,12 +628,18 @@ __global__ __launch_bounds__(64) void cov_kernel(const double *__restrict__ X, c
         }
 }
 
-__global__ void corr_kernel(const double *__restrict__ cov, int32_t nb, double *__restrict__ corr) {
+// sd[b] = sqrt(cov[b][b]), then corr[b][c] = cov[b][c] / (sd[b] sd[c])
+__global__ void sd_kernel(const double *__restrict__ cov, int32_t nb, double *__restrict__ sd) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nb) sd[b] = sqrt(cov[(int64_t)b * nb + b]);
+}
+
+__global__ void corr_kernel(const double *__restrict__ cov, const double *__restrict__ sd, int32_t nb,
+                            double *__restrict__ corr) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const int b = blockIdx.y;
     if (c >= nb) return;
-    const double sb = sqrt(cov[(int64_t)b * nb + b]), sc = sqrt(cov[(int64_t)c * nb + c]);
-    corr[(int64_t)b * nb + c] = cov[(int64_t)b * nb + c] / (sb * sc);
+    corr[(int64_t)b * nb + c] = cov[(int64_t)b * nb + c] / (sd[b] * sd[c]);
 }
 
 // ------------------------------------------------------------------ synthesis (alm2map)
@@ -1139,7 +1153,7 @@ extern "C" int ufalcon_alm2cl(const double *alm, int32_t n_maps, int32_t lmax, d
 
 extern "C" size_t ufalcon_cl_covariance_workspace_size(int32_t n_real, int32_t n_bands) {
     if (n_real < 1 || n_bands < 1) return 0;
-    return (size_t)n_real * (size_t)n_bands * sizeof(double);
+    return ((size_t)n_real + 1) * (size_t)n_bands * sizeof(double);  // band powers, then the deviations
 }
 
 extern "C" int ufalcon_cl_covariance(const double *cl, int32_t n_real, int32_t n_ell, int32_t ell_min,
@@ -1156,15 +1170,18 @@ extern "C" int ufalcon_cl_covariance(const double *cl, int32_t n_real, int32_t n
     double *X = static_cast<double *>(workspace);
     hipLaunchKernelGGL(band_kernel, dim3(blocks_for((int64_t)n_real * n_bands, 256)), dim3(256), 0, s, cl, n_real,
                        n_ell, ell_min, delta_ell, n_bands, X);
-    hipLaunchKernelGGL(band_mean_kernel, dim3(blocks_for(n_bands, 256)), dim3(256), 0, s, X, n_real, n_bands,
+    hipLaunchKernelGGL(band_mean_kernel, dim3(blocks_for(n_bands, 64)), dim3(64), 0, s, X, n_real, n_bands,
                        band_mean);
     hipLaunchKernelGGL((cov_kernel<kCovTB, kCovTC>),
                        dim3((unsigned)((n_bands + 16 * kCovTC - 1) / (16 * kCovTC)),
                             (unsigned)((n_bands + 16 * kCovTB - 1) / (16 * kCovTB))),
                        dim3(64), 0, s, X, band_mean, n_real, n_bands, (double)(n_real - ddof), cov);
-    if (corr)
-        hipLaunchKernelGGL(corr_kernel, dim3(blocks_for(n_bands, 256), (unsigned)n_bands), dim3(256), 0, s, cov,
+    if (corr) {
+        double *sd = X + (int64_t)n_real * n_bands;
+        hipLaunchKernelGGL(sd_kernel, dim3(blocks_for(n_bands, 256)), dim3(256), 0, s, cov, n_bands, sd);
+        hipLaunchKernelGGL(corr_kernel, dim3(blocks_for(n_bands, 256), (unsigned)n_bands), dim3(256), 0, s, cov, sd,
                            n_bands, corr);
+    }
     UFX_HIP_CHECK(hipGetLastError());
     return UFALCON_OK;
 }

@@ -129,7 +129,7 @@ def test_spectra_validation():
     assert lib.ufalcon_alm2cl(None, 1, 5, FAKE, None) == EINVAL
     assert lib.ufalcon_cl_covariance_workspace_size(0, 4) == 0
     ws = lib.ufalcon_cl_covariance_workspace_size(10, 4)
-    assert ws == 10 * 4 * 8
+    assert ws == (10 + 1) * 4 * 8   # band powers and standard deviations
 
     def cov(R=10, n_ell=20, l0=0, dl=5, nb=4, ddof=1, ws_bytes=ws):
         return lib.ufalcon_cl_covariance(FAKE, R, n_ell, l0, dl, nb, ddof, FAKE, FAKE, None, FAKE, ws_bytes, None)
