@@ -18,11 +18,14 @@
 //                       length per workgroup, the map chunk staged in LDS (FP32
 //                       or FP64 in, FP64 out) and read as broadcasts;
 //   lambda_seed_kernel  lambda_mm(z) of every ring pair for m = 0..lmax, carried
-//                       as value * 2^{-600 k} so sin^m(theta) cannot underflow;
-//   legendre_kernel     one workgroup per (m, block of 256 R ring pairs): the
-//                       three-term recurrence in l, R pairs per lane, partial
+//                       as value * 2^{-600 k} so sin^m(theta) cannot underflow,
+//                       one wave per segment of m;
+//   legendre_kernel     one workgroup per (m, block of kLegThreads R ring pairs):
+//                       the three-term recurrence in l, R pairs per lane, partial
 //                       sums over C consecutive l reduced through LDS;
-//   alm2cl / covariance small fixed-order reductions.
+//   alm2cl              fixed-order reductions;
+//   cov_kernel          the covariance of spectra over realisations on the FP64
+//                       matrix cores.
 #include "../../include/ufalcon.h"
 #include "internal.hpp"
 
@@ -226,36 +229,78 @@ __global__ __launch_bounds__(kDftThreads) void ring_dft_kernel(const T *__restri
 }
 
 // ------------------------------------------------------------------ lambda_mm seeds
-// lambda_mm = -sqrt((2m+1)/(2m)) sin(theta) lambda_{m-1,m-1}; the factors are
-// shared by all rings and staged in LDS per chunk of kSeedThreads values of m.
-constexpr int kSeedThreads = 256;
-__global__ __launch_bounds__(kSeedThreads) void lambda_seed_kernel(int64_t N, int32_t lmax, double *__restrict__ seed,
-                                                                   int32_t *__restrict__ seed_k) {
-    __shared__ double fac[kSeedThreads];
+// lambda_mm = -sqrt((2m+1)/(2m)) sin(theta) lambda_{m-1,m-1}, kept as v 2^{-600 k}
+// with v >= 2^-300.  A workgroup holds 64 ring pairs (one per lane) and
+// kSeedSegs waves; wave w owns the values of m in its segment.  Each wave first
+// forms the product of its segment's factors (rescaled the same way), the
+// products of the earlier segments then give its start value, and it runs the
+// segment again writing (v, k) for every m.
+constexpr int kSeedSegs = 16;
+__device__ __forceinline__ double seed_factor(int m, double st) {
+    return -sqrt((double)(2 * m + 3) / (double)(2 * m + 2)) * st;  // lambda_mm -> lambda_{m+1,m+1}
+}
+// Bring v back into [2^-300, 2^300) (the window the step-by-step product keeps):
+// up while it is below, down while it is at or above and k > 0 (the product of
+// two values of the window can reach 2^600).
+__device__ __forceinline__ void seed_rescale(double &v, int32_t &k) {
+    while (v != 0.0 && fabs(v) < kTiny) {
+        v *= kScaleUp;
+        ++k;
+    }
+    while (k > 0 && fabs(v) >= kBig) {
+        v *= kScaleDown;
+        --k;
+    }
+}
+__global__ __launch_bounds__(64 * kSeedSegs) void lambda_seed_kernel(int64_t N, int32_t lmax, double *__restrict__ seed,
+                                                                    int32_t *__restrict__ seed_k) {
+    __shared__ double prod[kSeedSegs][64];
+    __shared__ int32_t pexp[kSeedSegs][64];
+    __shared__ double fac[kSeedSegs][64];  // the next 64 factors of each segment, shared by the 64 rings
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t npair = 2 * N;
-    const int64_t p = (int64_t)blockIdx.x * kSeedThreads + threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * 64 + lane;
     double z = 0.0, st = 0.0;
     if (p < npair) ring_z_sin(N, p + 1, z, st);
-    double v = 0.28209479177387814;  // 1/sqrt(4 pi)
-    int32_t k = 0;
-    for (int m0 = 0; m0 <= lmax; m0 += kSeedThreads) {
+    const int len = (lmax + 1 + kSeedSegs - 1) / kSeedSegs;
+    const int m0 = w * len, m1 = min(m0 + len, lmax + 1);
+    // f(i0 .. i0 + 63) of this wave's segment into fac[w]; the same trip count in every wave
+    auto stage = [&](int i0) {
         __syncthreads();
-        {
-            const int m = m0 + threadIdx.x;  // factor taking lambda_mm to lambda_{m+1,m+1}
-            fac[threadIdx.x] = -sqrt((double)(2 * m + 3) / (double)(2 * m + 2));
-        }
+        const int m = m0 + i0 + lane;
+        fac[w][lane] = m < m1 ? seed_factor(m, 1.0) : 1.0;
         __syncthreads();
-        if (p >= npair) continue;
-        const int cnt = lmax - m0 + 1 < kSeedThreads ? lmax - m0 + 1 : kSeedThreads;
+        return max(0, min(64, m1 - (m0 + i0)));
+    };
+    // the factors taking lambda_{m0,m0} to lambda_{m1,m1}
+    double pv = 1.0;
+    int32_t pk = 0;
+    for (int i0 = 0; i0 < len; i0 += 64) {
+        const int cnt = stage(i0);
         for (int c = 0; c < cnt; ++c) {
-            const int64_t idx = (int64_t)(m0 + c) * npair + p;
+            pv *= fac[w][c] * st;
+            seed_rescale(pv, pk);
+        }
+    }
+    prod[w][lane] = pv;
+    pexp[w][lane] = pk;
+    __syncthreads();
+    double v = 0.28209479177387814;  // lambda_00 = 1/sqrt(4 pi)
+    int32_t k = 0;
+    for (int j = 0; j < w; ++j) {
+        v *= prod[j][lane];
+        k += pexp[j][lane];
+        seed_rescale(v, k);
+    }
+    for (int i0 = 0; i0 < len; i0 += 64) {
+        const int cnt = stage(i0);
+        if (p >= npair) continue;
+        for (int c = 0; c < cnt; ++c) {
+            const int64_t idx = (int64_t)(m0 + i0 + c) * npair + p;
             seed[idx] = v;
             seed_k[idx] = k;
-            v = v * fac[c] * st;
-            if (v != 0.0 && fabs(v) < kTiny) {
-                v *= kScaleUp;
-                ++k;
-            }
+            v *= fac[w][c] * st;
+            seed_rescale(v, k);
         }
     }
 }
@@ -1117,7 +1162,7 @@ extern "C" int ufalcon_map2alm(const void *maps, int dtype, int32_t n_maps, int6
     const int64_t N = nside, npix = npix_of(nside);
     const int64_t M = (int64_t)lmax + 1;
 
-    hipLaunchKernelGGL(lambda_seed_kernel, dim3(blocks_for(L.npair, kSeedThreads)), dim3(kSeedThreads), 0, s, N, lmax,
+    hipLaunchKernelGGL(lambda_seed_kernel, dim3(blocks_for(L.npair, 64)), dim3(64 * kSeedSegs), 0, s, N, lmax,
                        seed, seed_k);
     hipLaunchKernelGGL(legendre_coef_kernel, dim3(blocks_for((M + kLegC - 1) / kLegC, 256), (unsigned)M), dim3(256), 0, s,
                        lmax, coef);
@@ -1218,7 +1263,7 @@ extern "C" int ufalcon_alm2map(const double *alm, int32_t n_maps, int64_t nside,
     double2 *coef = reinterpret_cast<double2 *>(ws + L.off_coef);
     const int64_t N = nside, npix = npix_of(nside);
     const int64_t M = (int64_t)lmax + 1;
-    hipLaunchKernelGGL(lambda_seed_kernel, dim3(blocks_for(L.npair, kSeedThreads)), dim3(kSeedThreads), 0, s, N, lmax,
+    hipLaunchKernelGGL(lambda_seed_kernel, dim3(blocks_for(L.npair, 64)), dim3(64 * kSeedSegs), 0, s, N, lmax,
                        seed, seed_k);
     hipLaunchKernelGGL(legendre_coef_kernel, dim3(blocks_for((M + kLegC - 1) / kLegC, 256), (unsigned)M), dim3(256), 0, s,
                        lmax, coef);
