@@ -56,11 +56,11 @@ FLOPS_PER_INSTANCE = 80
 # reports traffic null.
 PMC_TRAFFIC = {
     "kernel": "keys_kernel<float>",
-    "fetch_kib": 786740.3,
-    "write_kib": 5073814.8,
+    "fetch_kib": 786738.0,
+    "write_kib": 5073815.0,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
-    "sources_sha1": "1bf47961edffb47e7786e536a9a6f584200b6796",
+    "sources_sha1": "15ff6b11cc7a090242447e20a2329fbdc9dc3d13",
     "profile": "profiles/keys_kernel_lognormal512_z05_nside1024_pmc.md",
 }
 
@@ -70,7 +70,7 @@ PMC_TRAFFIC = {
 PMC_VALU = {
     "instructions": 5.065e+09,
     "fp64_instructions": 1.638e+09,
-    "sources_sha1": "1bf47961edffb47e7786e536a9a6f584200b6796",
+    "sources_sha1": "15ff6b11cc7a090242447e20a2329fbdc9dc3d13",
     "profile": "profiles/keys_kernel_lognormal512_z05_nside1024_instmix.md",
 }
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
