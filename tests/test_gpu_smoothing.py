@@ -40,6 +40,8 @@ def _packed(full):
 @pytest.mark.parametrize("nside,lmax,beam_sigma,out_dtype", [
     (1, 2, None, torch.float64), (2, 5, None, torch.float64), (4, 11, 0.2, torch.float64),
     (4, 20, None, torch.float32), (16, 47, None, torch.float64), (32, 95, math.radians(2.0), torch.float64),
+    # odd Nside: unsplit equatorial transforms; odd and even polar rings
+    (3, 8, None, torch.float64), (5, 14, 0.1, torch.float64), (7, 20, None, torch.float32),
 ])
 def test_alm2map_full_parity(ufalcon, nside, lmax, beam_sigma, out_dtype):
     full = _alm(lmax, seed=nside)
@@ -59,6 +61,7 @@ def test_gaussian_beam(ufalcon):
 @pytest.mark.parametrize("nside,lmax,rings", [
     (1024, 1023, [0, 1, 500, 1023, 1024, 2047, 2048, 3000, 4094]),
     (2048, 300, [0, 7, 2047, 4095, 8190]),        # several ring-pair blocks
+    (513, 400, [0, 1, 2, 255, 256, 511, 512, 1025, 1536, 2049, 2050]),  # odd Nside, both polar parities
 ])
 def test_alm2map_sampled_rings(ufalcon, nside, lmax, rings):
     full = _alm(lmax, seed=nside + lmax)
