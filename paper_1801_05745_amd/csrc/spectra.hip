@@ -43,7 +43,7 @@ constexpr int kLegThreads = 128;
 constexpr int kLegR = 4;       // ring pairs per lane
 constexpr int kLegC = 8;       // l values per reduction chunk
 constexpr int kLegStage = kLegThreads < 128 ? kLegThreads : 128;  // l values per coefficient stage in LDS
-constexpr int kLegBufs = 2;    // reduction buffers (1: two barriers per chunk)
+constexpr int kLegBufs = 2;    // reduction buffers: a chunk's sums are read while the next chunk fills the other
 constexpr int kLegLanes = kLegThreads / (2 * kLegC);  // lanes summing one output
 static_assert(kLegLanes * 2 * kLegC == kLegThreads && (kLegLanes & (kLegLanes - 1)) == 0, "reduction layout");
 static_assert(kLegStage % kLegC == 0 && kLegStage / kLegC >= 2, "coefficient stages");
@@ -436,6 +436,26 @@ __global__ __launch_bounds__(kLegThreads) void legendre_kernel(const double2 *__
     __syncthreads();
     double2 pre = make_double2(0.0, 0.0);
 
+    // Reduction of a chunk: this lane's values summed as a tree, then the
+    // kLegLanes lanes of the group; the reads are issued at the end of the
+    // chunk and the sums taken after the next chunk's recurrence.
+    double vp[kLegThreads / kLegLanes];
+    double sigp = 0.0;
+    int l0p = 0;
+    bool pending = false;
+    auto finish = [&]() {
+#pragma unroll
+        for (int w2 = kLegThreads / kLegLanes / 2; w2 > 0; w2 /= 2)
+#pragma unroll
+            for (int t = 0; t < w2; ++t) vp[t] += vp[t + w2];
+        const double s = lane_group_sum<kLegLanes>(vp[0]);
+        const int l = l0p + o / 2;
+        if (part == 0 && l <= lmax) {
+            double *dst = reinterpret_cast<double *>(out + base + l);
+            dst[o & 1] = (w * sigp) * s;
+        }
+    };
+
     // One chunk of kLegC values of l.  kRevive: some lane of the wave still has
     // a pair below 2^-300; once none has, none will again, and the rest of the
     // loop runs without that bookkeeping (the folded sums then stay in place).
@@ -501,24 +521,18 @@ __global__ __launch_bounds__(kLegThreads) void legendre_kernel(const double2 *__
                 S.prev[r] *= sg;
             }
         }
+        // the previous chunk's sums, whose LDS reads were issued a chunk ago
+        if (pending) finish();
 #pragma unroll
-        for (int q = 0; q < 2 * kLegC; ++q) red[kLegBufs == 2 ? buf : 0][q][tid] = acc[q];
+        for (int q = 0; q < 2 * kLegC; ++q) red[buf][q][tid] = acc[q];
         __syncthreads();
-        // this lane's values summed as a tree, then the kLegLanes lanes of the group
-        double v[kLegThreads / kLegLanes];
+        // issue this chunk's reads now; they are summed after the next chunk's
+        // recurrence (red is double buffered: the next writes go to the other half)
 #pragma unroll
-        for (int t = 0; t < kLegThreads / kLegLanes; ++t) v[t] = red[kLegBufs == 2 ? buf : 0][o][part + kLegLanes * t];
-#pragma unroll
-        for (int w2 = kLegThreads / kLegLanes / 2; w2 > 0; w2 /= 2)
-#pragma unroll
-            for (int t = 0; t < w2; ++t) v[t] += v[t + w2];
-        const double s = lane_group_sum<kLegLanes>(v[0]);
-        const int l = l0 + o / 2;
-        if (part == 0 && l <= lmax) {
-            double *dst = reinterpret_cast<double *>(out + base + l);
-            dst[o & 1] = (w * cs[o / 2].y) * s;
-        }
-        if (kLegBufs == 1) __syncthreads();
+        for (int t = 0; t < kLegThreads / kLegLanes; ++t) vp[t] = red[buf][o][part + kLegLanes * t];
+        sigp = cs[o / 2].y;
+        l0p = l0;
+        pending = true;
     };
     // Every chunk has the same barriers in both loops, so the waves of a
     // workgroup may leave the first loop at different chunks.
@@ -526,6 +540,7 @@ __global__ __launch_bounds__(kLegThreads) void legendre_kernel(const double2 *__
     for (; l0 <= lmax && __builtin_amdgcn_ballot_w64(dead) != 0; l0 += kLegC, buf ^= 1)
         chunk(l0, buf, std::true_type{});
     for (; l0 <= lmax; l0 += kLegC, buf ^= 1) chunk(l0, buf, std::false_type{});
+    if (pending) finish();
 }
 
 // out[i] = sum_b part[b][i], b in order
