@@ -836,11 +836,18 @@ __global__ __launch_bounds__(kLegThreads) void legendre_synth_kernel(const doubl
 //   map[4j' + q] = Re sum_{k'<n4} P_q[k'] e^{2 pi i k' j'/n4},
 //   P_q[k'] = e^{2 pi i k' q/n} sum_t i^{t q} H[k' + t n4].
 // Lane j' accumulates the four outputs of RG rings of equal length.
-template <typename T, bool kPolar, bool kSplit>
-__global__ __launch_bounds__(kDftThreads, kPolar ? (kSplit ? 3 : 4) : (kSplit ? 3 : 1)) void ring_idft_kernel(const double2 *__restrict__ F, int64_t N,
-                                                                int32_t lmax, T *__restrict__ map) {
-    constexpr int RG = kPolar ? 2 : (kSplit ? kEqRingsSplit : kEqRings);
-    constexpr int H = kSplit ? 2 : 1;  // with kSplit: sums over even and odd k' kept apart
+// K output classes: lane j' < n4/K writes pixels j' + s n4/K, s < K, from the
+// sums over k' = h mod K kept apart: e^{2 pi i (j' + s n4/K) k' / n4} =
+// e^{2 pi i j' k' / n4} e^{2 pi i s h / K}.  K = 2 needs only the real parts
+// Re P cos and Im P sin (the factors are +-1); K = 4 keeps the complex sums,
+// as the factors include +-i.
+template <typename T, bool kPolar, int K>
+__global__ __launch_bounds__(kDftThreads, kPolar ? (K > 1 ? 3 : 4) : (K > 1 ? 3 : 1)) void ring_idft_kernel(
+    const double2 *__restrict__ F, int64_t N, int32_t lmax, T *__restrict__ map) {
+    static_assert(K == 1 || K == 2 || (K == 4 && !kPolar), "output classes");
+    constexpr bool kSplit = K > 1;
+    constexpr int RG = kPolar ? 2 : (K == 4 ? 1 : (K == 2 ? kEqRingsSplit : kEqRings));
+    constexpr int H = K;
     __shared__ double2 ps[RG][4][kDftJ];
     const int64_t nring = 4 * N - 1;
     int64_t ring[RG];
@@ -861,12 +868,13 @@ __global__ __launch_bounds__(kDftThreads, kPolar ? (kSplit ? 3 : 4) : (kSplit ? 
         }
         n4 = N;
     }
-    const int64_t nj = kSplit ? n4 / 2 : n4;  // lanes needed
+    const int64_t nj = n4 / K;  // lanes needed
     if ((int64_t)blockIdx.x * kDftThreads >= nj) return;
     const int64_t jp = (int64_t)blockIdx.x * kDftThreads + threadIdx.x;  // j'
     const int64_t n = 4 * n4;
 
-    // sums of Re P cos and Im P sin (the output is their difference), per parity of k'
+    // per class h of k': K <= 2, the sums of Re P cos and Im P sin (the output is
+    // their difference); K = 4, the real and imaginary parts of sum P w
     double acc[H][RG][4], acn[H][RG][4];
 #pragma unroll
     for (int h = 0; h < H; ++h)
@@ -958,7 +966,7 @@ __global__ __launch_bounds__(kDftThreads, kPolar ? (kSplit ? 3 : 4) : (kSplit ? 
         sincospi(2.0 * (double)((jp * kb) % n4) / (double)n4, &wi, &wr);
         for (int kk = 0; kk < cnt; kk += H) {
 #pragma unroll
-            for (int h = 0; h < H; ++h) {  // kb is even, so the parity of k' is that of h
+            for (int h = 0; h < H; ++h) {  // kb is a multiple of K, so k' = h mod K
                 // all of this step's LDS reads first, so that they are in flight together
                 double2 P[RG][4];
 #pragma unroll
@@ -969,8 +977,13 @@ __global__ __launch_bounds__(kDftThreads, kPolar ? (kSplit ? 3 : 4) : (kSplit ? 
                 for (int g = 0; g < RG; ++g)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        acc[h][g][q] = fma(P[g][q].x, wr, acc[h][g][q]);
-                        acn[h][g][q] = fma(P[g][q].y, wi, acn[h][g][q]);
+                        if constexpr (K == 4) {
+                            acc[h][g][q] = fma(-P[g][q].y, wi, fma(P[g][q].x, wr, acc[h][g][q]));
+                            acn[h][g][q] = fma(P[g][q].y, wr, fma(P[g][q].x, wi, acn[h][g][q]));
+                        } else {
+                            acc[h][g][q] = fma(P[g][q].x, wr, acc[h][g][q]);
+                            acn[h][g][q] = fma(P[g][q].y, wi, acn[h][g][q]);
+                        }
                     }
                 const double nr = fma(wr, wc, -(wi * ws));
                 const double ni = fma(wr, ws, wi * wc);
@@ -985,7 +998,24 @@ __global__ __launch_bounds__(kDftThreads, kPolar ? (kSplit ? 3 : 4) : (kSplit ? 
     for (int g = 0; g < RG; ++g) {
         if (!valid[g]) continue;
         T *dst = map + ring_first(N, ring[g]) + 4 * jp;
-        if (kSplit) {
+        if constexpr (K == 4) {
+            // pixel j' + s n4/4: sum_h Re(i^{s h} E_h), in h order
+#pragma unroll
+            for (int sc = 0; sc < 4; ++sc) {
+                T *d = dst + sc * n4;  // 4 (j' + sc n4/4)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+                        const int e = (sc * h) & 3;  // i^e: Re E, -Im E, -Re E, Im E
+                        const double t = (e & 1) ? acn[h][g][q] : acc[h][g][q];
+                        v += (e == 1 || e == 2) ? -t : t;
+                    }
+                    d[q] = (T)v;
+                }
+            }
+        } else if (kSplit) {
             // map[4 j' + q] = E + O, map[4 (j' + n4/2) + q] = E - O
             T *dst2 = dst + 2 * n4;
 #pragma unroll
@@ -1084,19 +1114,24 @@ void launch_ring_idft(const double2 *F, int64_t N, int32_t lmax, T *mp, hipStrea
     // polar rings i < N: odd i directly, even i with the even/odd split (polar
     // 0.71 -> 0.39 + 0.24 ms at Nside 1024)
     if (N > 1)
-        hipLaunchKernelGGL((ring_idft_kernel<T, true, false>), dim3(dx, (unsigned)(N / 2)), dim3(kDftThreads), 0, s, F,
-                           N, lmax, mp);
+        hipLaunchKernelGGL((ring_idft_kernel<T, true, 1>), dim3(dx, (unsigned)(N / 2)), dim3(kDftThreads), 0, s, F, N,
+                           lmax, mp);
     if ((N - 1) / 2 > 0)
-        hipLaunchKernelGGL((ring_idft_kernel<T, true, true>),
+        hipLaunchKernelGGL((ring_idft_kernel<T, true, 2>),
                            dim3((unsigned)((N / 2 + kDftThreads - 1) / kDftThreads), (unsigned)((N - 1) / 2)),
                            dim3(kDftThreads), 0, s, F, N, lmax, mp);
-    if (N % 2 == 0)
-        hipLaunchKernelGGL((ring_idft_kernel<T, false, true>),
+    // equatorial rings (n4 = N): four output classes when 4 | N, two when 2 | N
+    if (N % 4 == 0)
+        hipLaunchKernelGGL((ring_idft_kernel<T, false, 4>),
+                           dim3((unsigned)((N / 4 + kDftThreads - 1) / kDftThreads), (unsigned)(2 * N + 1)),
+                           dim3(kDftThreads), 0, s, F, N, lmax, mp);
+    else if (N % 2 == 0)
+        hipLaunchKernelGGL((ring_idft_kernel<T, false, 2>),
                            dim3((unsigned)((N / 2 + kDftThreads - 1) / kDftThreads),
                                 (unsigned)((2 * N + 1 + kEqRingsSplit - 1) / kEqRingsSplit)),
                            dim3(kDftThreads), 0, s, F, N, lmax, mp);
     else
-        hipLaunchKernelGGL((ring_idft_kernel<T, false, false>),
+        hipLaunchKernelGGL((ring_idft_kernel<T, false, 1>),
                            dim3(dx, (unsigned)((2 * N + 1 + kEqRings - 1) / kEqRings)), dim3(kDftThreads), 0, s, F,
                            N, lmax, mp);
 }
