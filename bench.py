@@ -132,17 +132,20 @@ def parse():
     return ap.parse_args()
 
 
-def sht_flops(nside, lmax):
-    """Algorithmic FP64 flops of one map2alm: the ring DFTs as four direct
-    length-n/4 DFTs per ring (4 flops per real-by-complex multiply-add; on the
-    equatorial rings of an even Nside the even/odd split of the outputs halves
-    that) and the Legendre step, 7 flops per (l, m, ring pair): the three-term
-    recurrence (3) and the complex multiply-add with the folded ring sum (4)."""
+def sht_flops(nside, lmax, inverse=False):
+    """Algorithmic FP64 flops of one map2alm (or, inverse=True, one alm2map): the
+    ring transforms as four direct length-n/4 DFTs per ring (4 flops per
+    real-by-complex multiply-add), divided by the number K of output classes the
+    kernels use (equatorial rings: K = 4 when 4 | Nside, 2 when Nside is even;
+    polar rings of the inverse: K = 2 on even rings), and the Legendre step,
+    7 flops per (l, m, ring pair): the three-term recurrence (3) and the complex
+    multiply-add with the folded ring sum (4)."""
     N = nside
     n_alm = (lmax + 1) * (lmax + 2) // 2
     legendre = 7 * n_alm * 2 * N
-    dft_eq = (2 * N + 1) * 4 * N * N * (2 if N % 2 == 0 else 4)
-    dft_polar = sum(2 * 4 * i * i * 4 for i in range(1, N))
+    k_eq = 4 if N % 4 == 0 else (2 if N % 2 == 0 else 1)
+    dft_eq = (2 * N + 1) * 16 * N * N // k_eq
+    dft_polar = sum(2 * 16 * i * i // (2 if inverse and i % 2 == 0 else 1) for i in range(1, N))
     return float(legendre + dft_eq + dft_polar)
 
 
@@ -274,6 +277,7 @@ def main():
     sht_ms = ev_sh[0].elapsed_time(ev_sh[1]) / 3
     cl_ms = ev_sh[1].elapsed_time(ev_sh[2]) / 3
     sht_fl = sht_flops(nside, lmax)
+    a2m_fl = sht_flops(nside, lmax, inverse=True)
     n_real = 150
     jitter = synth.uniform64(n_real * (lmax + 1), seed=5, stream=7, device=dev).reshape(n_real, lmax + 1)
     cls = cl[None, :] * (0.5 + jitter)
@@ -401,8 +405,9 @@ def main():
             "kernel": "ufalcon_alm2map (Legendre synthesis + inverse ring DFTs, FP64), Gaussian beam",
             "sigma_arcmin": 10.8, "lmax": lmax,
             "alm2map_ms": a2m_ms,
-            "achieved": sht_fl / (a2m_ms / 1e3) / 1e12,
-            "frac": sht_fl / (a2m_ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+            "algorithmic_flops": a2m_fl,
+            "achieved": a2m_fl / (a2m_ms / 1e3) / 1e12,
+            "frac": a2m_fl / (a2m_ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
             "moments_ms": mom_ms,
             "moments_GBs": 2 * 4 * uf.npix(nside) / (mom_ms / 1e3) / 1e9,
             "s2": mom[3],

@@ -86,10 +86,11 @@ __device__ __forceinline__ void ring_z_sin(int64_t N, int64_t i, double &z, doub
 // and F(m) = e^{-i pi m s / n} DFT[m mod n] (aliasing for m >= n).  Lane k'
 // accumulates D_0..D_3 of RG rings of equal length (the twiddle advancing by
 // one complex multiply per j', re-seeded exactly every kDftJ steps), then
-// writes F(m) for every m = k' + t n4 + u n <= lmax.  With kSplit (n4 even),
-// lane k' < n4/2 also yields D_q[k' + n4/2]: the sums over even and odd j' are
-// kept apart, D_q[k'] = E + O and D_q[k' + n4/2] = E - O, so every product
-// x w serves two outputs.
+// writes F(m) for every m = k' + t n4 + u n <= lmax.  With K output classes
+// (K = 2 when n4 is even, 4 when 4 | n4; equatorial rings), lane k' < n4/K
+// also yields D_q[k' + s n4/K]: the sums over the classes of j' mod K are kept
+// apart (for K = 2, D_q[k'] = E + O and D_q[k' + n4/2] = E - O), so every
+// product x w serves K outputs and each LDS read K times as many.
 
 // F(m) of one ring from its four D_q[kp].
 __device__ __forceinline__ void ring_dft_outputs(const double (&ar)[4], const double (&ai)[4], int64_t kp, int64_t n4,
@@ -134,11 +135,16 @@ __device__ __forceinline__ void ring_dft_outputs(const double (&ar)[4], const do
     }
 }
 
-template <typename T, bool kPolar, bool kSplit>
+// K output classes: lane k' < n4/K yields D_q[k' + s n4/K], s < K, from the
+// sums over j' = h mod K kept apart (E_h): D_q[k' + s n4/K] =
+// sum_h e^{-2 pi i s h / K} E_h, the factors +-1 for K = 2 and also +-i for K = 4.
+template <typename T, bool kPolar, int K>
 __global__ __launch_bounds__(kDftThreads) void ring_dft_kernel(const T *__restrict__ map, int64_t N, int32_t lmax,
                                                                double2 *__restrict__ F) {
-    constexpr int RG = kPolar ? 2 : (kSplit ? kEqRingsSplit : kEqRings);
-    constexpr int H = kSplit ? 2 : 1;  // accumulators per output pair: even and odd j'
+    static_assert(K == 1 || K == 2 || (K == 4 && !kPolar), "output classes");
+    constexpr bool kSplit = K > 1;
+    constexpr int RG = kPolar ? 2 : (K == 4 ? 1 : (K == 2 ? kEqRingsSplit : kEqRings));
+    constexpr int H = K;  // accumulators per output: one per class of j'
     __shared__ double xs[RG][4][kDftJ];
     const int64_t nring = 4 * N - 1;
     int64_t ring[RG];
@@ -159,7 +165,7 @@ __global__ __launch_bounds__(kDftThreads) void ring_dft_kernel(const T *__restri
         }
         n4 = N;
     }
-    const int64_t nk = kSplit ? n4 / 2 : n4;                  // lanes needed
+    const int64_t nk = n4 / K;                                // lanes needed
     if ((int64_t)blockIdx.x * kDftThreads >= nk) return;  // whole workgroup past this ring length
     const int64_t kp = (int64_t)blockIdx.x * kDftThreads + threadIdx.x;  // k'
     int64_t first[RG];
@@ -177,7 +183,7 @@ __global__ __launch_bounds__(kDftThreads) void ring_dft_kernel(const T *__restri
     sincospi(-2.0 * (double)(kp % n4) / (double)n4, &ws, &wc);
 
     for (int64_t jb = 0; jb < n4; jb += kDftJ) {
-        const int cnt = (int)(n4 - jb < kDftJ ? n4 - jb : kDftJ);  // even with kSplit
+        const int cnt = (int)(n4 - jb < kDftJ ? n4 - jb : kDftJ);  // a multiple of K
         for (int e = threadIdx.x; e < RG * 4 * kDftJ; e += kDftThreads) {
             const int g = e / (4 * kDftJ), r = e % (4 * kDftJ);  // r = 4 jj + q: pixels in order
             const int jj = r / 4, q = r % 4;
@@ -188,7 +194,7 @@ __global__ __launch_bounds__(kDftThreads) void ring_dft_kernel(const T *__restri
         sincospi(-2.0 * (double)((kp * jb) % n4) / (double)n4, &wi, &wr);
         for (int jj = 0; jj < cnt; jj += H) {
 #pragma unroll
-            for (int h = 0; h < H; ++h) {  // jb is even, so the parity of j' is that of h
+            for (int h = 0; h < H; ++h) {  // jb is a multiple of K, so j' = h mod K
 #pragma unroll
                 for (int g = 0; g < RG; ++g)
 #pragma unroll
@@ -211,7 +217,27 @@ __global__ __launch_bounds__(kDftThreads) void ring_dft_kernel(const T *__restri
         if (!valid[g]) continue;
         const bool shift = ring_shift(N, ring[g]) != 0;
         const int64_t col = ring[g] - 1;
-        if (kSplit) {
+        if constexpr (K == 4) {
+            // D_q[k' + s n4/4] = sum_h (-i)^{s h} E_h, in h order; (-i)(x + iy) = y - ix
+#pragma unroll
+            for (int sc = 0; sc < 4; ++sc) {
+                double dr[4], di[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    double vr = 0.0, vi = 0.0;
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+                        const int e = (sc * h) & 3;
+                        const double xr = ar[h][g][q], xi = ai[h][g][q];
+                        vr += e == 0 ? xr : (e == 1 ? xi : (e == 2 ? -xr : -xi));
+                        vi += e == 0 ? xi : (e == 1 ? -xr : (e == 2 ? -xi : xr));
+                    }
+                    dr[q] = vr;
+                    di[q] = vi;
+                }
+                ring_dft_outputs(dr, di, kp + sc * (n4 / 4), n4, shift, col, nring, lmax, F);
+            }
+        } else if (kSplit) {
             double lo_r[4], lo_i[4], hi_r[4], hi_i[4];  // D_q[k'] = E + O, D_q[k' + n4/2] = E - O
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -1144,15 +1170,20 @@ void launch_ring_dft(const T *mp, int64_t N, int32_t lmax, double2 *F, hipStream
     // even/odd split of the outputs, as the inverse does, the two launches took
     // 0.30 + 0.28 ms against 0.47 ms at Nside 1024)
     if (N > 1)
-        hipLaunchKernelGGL((ring_dft_kernel<T, true, false>), dim3(dx, (unsigned)(N - 1)), dim3(kDftThreads), 0, s, mp,
-                           N, lmax, F);
-    if (N % 2 == 0)
-        hipLaunchKernelGGL((ring_dft_kernel<T, false, true>),
+        hipLaunchKernelGGL((ring_dft_kernel<T, true, 1>), dim3(dx, (unsigned)(N - 1)), dim3(kDftThreads), 0, s, mp, N,
+                           lmax, F);
+    // equatorial rings (n4 = N): four output classes when 4 | N, two when 2 | N
+    if (N % 4 == 0)
+        hipLaunchKernelGGL((ring_dft_kernel<T, false, 4>),
+                           dim3((unsigned)((N / 4 + kDftThreads - 1) / kDftThreads), (unsigned)(2 * N + 1)),
+                           dim3(kDftThreads), 0, s, mp, N, lmax, F);
+    else if (N % 2 == 0)
+        hipLaunchKernelGGL((ring_dft_kernel<T, false, 2>),
                            dim3((unsigned)((N / 2 + kDftThreads - 1) / kDftThreads),
                                 (unsigned)((2 * N + 1 + kEqRingsSplit - 1) / kEqRingsSplit)),
                            dim3(kDftThreads), 0, s, mp, N, lmax, F);
     else
-        hipLaunchKernelGGL((ring_dft_kernel<T, false, false>),
+        hipLaunchKernelGGL((ring_dft_kernel<T, false, 1>),
                            dim3(dx, (unsigned)((2 * N + 1 + kEqRings - 1) / kEqRings)), dim3(kDftThreads), 0, s, mp,
                            N, lmax, F);
 }
