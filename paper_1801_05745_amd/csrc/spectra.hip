@@ -36,6 +36,7 @@ namespace {
 
 constexpr int kDftThreads = 256;
 constexpr int kDftJ = 64;      // pixels per staged chunk (and twiddle re-seed period)
+constexpr int kDftShort = 64;  // polar rings up to this n4 write their aliased outputs with the whole workgroup
 constexpr int kFoldBatch = 4;  // loads in flight per step of the inverse transform's folds
 constexpr int kEqRings = 4;    // equatorial rings (all 4N long) per workgroup
 constexpr int kEqRingsSplit = 2;  // the same with the even/odd split of the outputs
@@ -93,9 +94,11 @@ __device__ __forceinline__ void ring_z_sin(int64_t N, int64_t i, double &z, doub
 // product x w serves K outputs and each LDS read K times as many.
 
 // F(m) of one ring from its four D_q[kp].
+// With gs (short rings), G(k) goes to gs[k] instead, and the workgroup writes
+// the aliased F(m) afterwards (ring_dft_spread).
 __device__ __forceinline__ void ring_dft_outputs(const double (&ar)[4], const double (&ai)[4], int64_t kp, int64_t n4,
                                                  bool shift, int64_t col, int64_t nring, int32_t lmax,
-                                                 double2 *__restrict__ F) {
+                                                 double2 *__restrict__ F, double2 *gs = nullptr) {
     const int64_t n = 4 * n4;
     // e^{-2 pi i k' q / n}, q = 1, 2, 3
     double s1, c1;
@@ -127,11 +130,27 @@ __device__ __forceinline__ void ring_dft_outputs(const double (&ar)[4], const do
             gr = dr[t] * c - di[t] * s;
             gi = dr[t] * s + di[t] * c;
         }
+        if (gs) {
+            gs[k] = make_double2(gr, gi);
+            continue;
+        }
         // F(k + u n) = (-1)^{u s} G(k)
         for (int64_t m = k, u = 0; m <= lmax; m += n, ++u) {
             const double sg = (shift && (u & 1)) ? -1.0 : 1.0;
             F[m * nring + col] = make_double2(sg * gr, sg * gi);
         }
+    }
+}
+
+// F(m) = (-1)^{u s} G(m - u n), u = m / n, for every m <= lmax, one m per thread:
+// a short ring has few lanes and lmax / n aliases per k, too many for one lane.
+__device__ __forceinline__ void ring_dft_spread(const double2 *gs, int64_t n, bool shift, int64_t col, int64_t nring,
+                                                int32_t lmax, double2 *__restrict__ F) {
+    for (int64_t m = threadIdx.x; m <= lmax; m += kDftThreads) {
+        const int64_t u = m / n;
+        const double2 g = gs[m - u * n];
+        const double sg = (shift && (u & 1)) ? -1.0 : 1.0;
+        F[m * nring + col] = make_double2(sg * g.x, sg * g.y);
     }
 }
 
@@ -146,12 +165,14 @@ __global__ __launch_bounds__(kDftThreads) void ring_dft_kernel(const T *__restri
     constexpr int RG = kPolar ? 2 : (K == 4 ? 1 : (K == 2 ? kEqRingsSplit : kEqRings));
     constexpr int H = K;  // accumulators per output: one per class of j'
     __shared__ double xs[RG][4][kDftJ];
+    __shared__ double2 gsm[kPolar ? RG : 1][kPolar ? 4 * kDftShort : 1];  // G(k) of short polar rings
     const int64_t nring = 4 * N - 1;
     int64_t ring[RG];
     bool valid[RG];
     int64_t n4;
     if (kPolar) {
-        const int64_t i = (int64_t)blockIdx.y + 1;
+        // polar ring i, the longest first so that the short ones fill the tail of the launch
+        const int64_t i = (N - 1) - (int64_t)blockIdx.y;
         ring[0] = i;
         ring[RG - 1] = 4 * N - i;
         valid[0] = valid[RG - 1] = true;
@@ -211,10 +232,12 @@ __global__ __launch_bounds__(kDftThreads) void ring_dft_kernel(const T *__restri
         }
         __syncthreads();
     }
-    if (kp >= nk) return;
+    // polar rings of at most kDftShort pixels per quarter: G(k) through LDS, then
+    // the aliased outputs with the whole workgroup (uniform over the workgroup)
+    const bool short_ring = kPolar && n4 <= kDftShort;
 #pragma unroll
     for (int g = 0; g < RG; ++g) {
-        if (!valid[g]) continue;
+        if (!valid[g] || kp >= nk) continue;
         const bool shift = ring_shift(N, ring[g]) != 0;
         const int64_t col = ring[g] - 1;
         if constexpr (K == 4) {
@@ -249,8 +272,15 @@ __global__ __launch_bounds__(kDftThreads) void ring_dft_kernel(const T *__restri
             ring_dft_outputs(lo_r, lo_i, kp, n4, shift, col, nring, lmax, F);
             ring_dft_outputs(hi_r, hi_i, kp + n4 / 2, n4, shift, col, nring, lmax, F);
         } else {
-            ring_dft_outputs(ar[0][g], ai[0][g], kp, n4, shift, col, nring, lmax, F);
+            ring_dft_outputs(ar[0][g], ai[0][g], kp, n4, shift, col, nring, lmax, F,
+                             short_ring ? gsm[kPolar ? g : 0] : nullptr);
         }
+    }
+    if (kPolar && short_ring) {
+        __syncthreads();
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
+            ring_dft_spread(gsm[kPolar ? g : 0], 4 * n4, ring_shift(N, ring[g]) != 0, ring[g] - 1, nring, lmax, F);
     }
 }
 
@@ -880,7 +910,10 @@ __global__ __launch_bounds__(kDftThreads, kPolar ? (K > 1 ? 3 : 4) : (K > 1 ? 3 
     bool valid[RG];
     int64_t n4;
     if (kPolar) {
-        const int64_t i = kSplit ? 2 * ((int64_t)blockIdx.y + 1) : 2 * (int64_t)blockIdx.y + 1;  // even / odd rings
+        // the even (K = 2) or odd (K = 1) polar rings i < N, the longest first so
+        // that the short ones fill the tail of the launch
+        const int64_t imax = ((N - 1) % 2 == (kSplit ? 0 : 1)) ? N - 1 : N - 2;
+        const int64_t i = imax - 2 * (int64_t)blockIdx.y;
         ring[0] = i;
         ring[RG - 1] = 4 * N - i;
         valid[0] = valid[RG - 1] = true;
