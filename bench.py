@@ -137,7 +137,7 @@ def sht_flops(nside, lmax, inverse=False):
     ring transforms as four direct length-n/4 DFTs per ring (4 flops per
     real-by-complex multiply-add), divided by the number K of output classes the
     kernels use (equatorial rings: K = 4 when 4 | Nside, 2 when Nside is even;
-    polar rings of the inverse: K = 2 on even rings), and the Legendre step,
+    polar rings: K = 2 on even rings), and the Legendre step,
     7 flops per (l, m, ring pair): the three-term recurrence (3) and the complex
     multiply-add with the folded ring sum (4)."""
     N = nside
@@ -145,7 +145,7 @@ def sht_flops(nside, lmax, inverse=False):
     legendre = 7 * n_alm * 2 * N
     k_eq = 4 if N % 4 == 0 else (2 if N % 2 == 0 else 1)
     dft_eq = (2 * N + 1) * 16 * N * N // k_eq
-    dft_polar = sum(2 * 16 * i * i // (2 if inverse and i % 2 == 0 else 1) for i in range(1, N))
+    dft_polar = sum(2 * 16 * i * i // (2 if i % 2 == 0 else 1) for i in range(1, N))
     return float(legendre + dft_eq + dft_polar)
 
 

@@ -171,8 +171,10 @@ __global__ __launch_bounds__(kDftThreads) void ring_dft_kernel(const T *__restri
     bool valid[RG];
     int64_t n4;
     if (kPolar) {
-        // polar ring i, the longest first so that the short ones fill the tail of the launch
-        const int64_t i = (N - 1) - (int64_t)blockIdx.y;
+        // the even (K = 2) or odd (K = 1) polar rings i < N, the longest first so
+        // that the short ones fill the tail of the launch
+        const int64_t imax = ((N - 1) % 2 == (kSplit ? 0 : 1)) ? N - 1 : N - 2;
+        const int64_t i = imax - 2 * (int64_t)blockIdx.y;
         ring[0] = i;
         ring[RG - 1] = 4 * N - i;
         valid[0] = valid[RG - 1] = true;
@@ -269,8 +271,9 @@ __global__ __launch_bounds__(kDftThreads) void ring_dft_kernel(const T *__restri
                 hi_r[q] = ar[0][g][q] - ar[H - 1][g][q];
                 hi_i[q] = ai[0][g][q] - ai[H - 1][g][q];
             }
-            ring_dft_outputs(lo_r, lo_i, kp, n4, shift, col, nring, lmax, F);
-            ring_dft_outputs(hi_r, hi_i, kp + n4 / 2, n4, shift, col, nring, lmax, F);
+            double2 *gs = short_ring ? gsm[kPolar ? g : 0] : nullptr;
+            ring_dft_outputs(lo_r, lo_i, kp, n4, shift, col, nring, lmax, F, gs);
+            ring_dft_outputs(hi_r, hi_i, kp + n4 / 2, n4, shift, col, nring, lmax, F, gs);
         } else {
             ring_dft_outputs(ar[0][g], ai[0][g], kp, n4, shift, col, nring, lmax, F,
                              short_ring ? gsm[kPolar ? g : 0] : nullptr);
@@ -1203,8 +1206,12 @@ void launch_ring_dft(const T *mp, int64_t N, int32_t lmax, double2 *F, hipStream
     // even/odd split of the outputs, as the inverse does, the two launches took
     // 0.30 + 0.28 ms against 0.47 ms at Nside 1024)
     if (N > 1)
-        hipLaunchKernelGGL((ring_dft_kernel<T, true, 1>), dim3(dx, (unsigned)(N - 1)), dim3(kDftThreads), 0, s, mp, N,
+        hipLaunchKernelGGL((ring_dft_kernel<T, true, 1>), dim3(dx, (unsigned)(N / 2)), dim3(kDftThreads), 0, s, mp, N,
                            lmax, F);
+    if ((N - 1) / 2 > 0)
+        hipLaunchKernelGGL((ring_dft_kernel<T, true, 2>),
+                           dim3((unsigned)((N / 2 + kDftThreads - 1) / kDftThreads), (unsigned)((N - 1) / 2)),
+                           dim3(kDftThreads), 0, s, mp, N, lmax, F);
     // equatorial rings (n4 = N): four output classes when 4 | N, two when 2 | N
     if (N % 4 == 0)
         hipLaunchKernelGGL((ring_dft_kernel<T, false, 4>),
