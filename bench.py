@@ -132,8 +132,8 @@ def parse():
     return ap.parse_args()
 
 
-def sht_flops(nside, lmax, inverse=False):
-    """Algorithmic FP64 flops of one map2alm (or, inverse=True, one alm2map): the
+def sht_flops(nside, lmax):
+    """Algorithmic FP64 flops of one map2alm (and of one alm2map, its mirror): the
     ring transforms as four direct length-n/4 DFTs per ring (4 flops per
     real-by-complex multiply-add), divided by the number K of output classes the
     kernels use (equatorial rings: K = 4 when 4 | Nside, 2 when Nside is even;
@@ -277,7 +277,7 @@ def main():
     sht_ms = ev_sh[0].elapsed_time(ev_sh[1]) / 3
     cl_ms = ev_sh[1].elapsed_time(ev_sh[2]) / 3
     sht_fl = sht_flops(nside, lmax)
-    a2m_fl = sht_flops(nside, lmax, inverse=True)
+    a2m_fl = sht_flops(nside, lmax)  # the synthesis mirrors the analysis
     n_real = 150
     jitter = synth.uniform64(n_real * (lmax + 1), seed=5, stream=7, device=dev).reshape(n_real, lmax + 1)
     cls = cl[None, :] * (0.5 + jitter)
