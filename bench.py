@@ -132,18 +132,21 @@ def parse():
     return ap.parse_args()
 
 
-def sht_flops(nside, lmax):
-    """Algorithmic FP64 flops of one map2alm (and of one alm2map, its mirror): the
-    ring transforms as four direct length-n/4 DFTs per ring (4 flops per
+def sht_flops(nside, lmax, inverse=False):
+    """Algorithmic FP64 flops of one map2alm (inverse=False) or alm2map: the ring
+    transforms as four direct length-n/4 DFTs per ring (4 flops per
     real-by-complex multiply-add), divided by the number K of output classes the
     kernels use (equatorial rings: K = 4 when 4 | Nside, 2 when Nside is even;
-    polar rings: K = 2 on even rings), and the Legendre step,
-    7 flops per (l, m, ring pair): the three-term recurrence (3) and the complex
+    polar rings: K = 2 on even rings; the inverse gains nothing past K = 2, as
+    four classes need the complex sums), and the Legendre step, 7 flops per
+    (l, m, ring pair): the three-term recurrence (3) and the complex
     multiply-add with the folded ring sum (4)."""
     N = nside
     n_alm = (lmax + 1) * (lmax + 2) // 2
     legendre = 7 * n_alm * 2 * N
     k_eq = 4 if N % 4 == 0 else (2 if N % 2 == 0 else 1)
+    if inverse:
+        k_eq = min(k_eq, 2)
     dft_eq = (2 * N + 1) * 16 * N * N // k_eq
     dft_polar = sum(2 * 16 * i * i // (2 if i % 2 == 0 else 1) for i in range(1, N))
     return float(legendre + dft_eq + dft_polar)
@@ -277,7 +280,7 @@ def main():
     sht_ms = ev_sh[0].elapsed_time(ev_sh[1]) / 3
     cl_ms = ev_sh[1].elapsed_time(ev_sh[2]) / 3
     sht_fl = sht_flops(nside, lmax)
-    a2m_fl = sht_flops(nside, lmax)  # the synthesis mirrors the analysis
+    a2m_fl = sht_flops(nside, lmax, inverse=True)
     n_real = 150
     jitter = synth.uniform64(n_real * (lmax + 1), seed=5, stream=7, device=dev).reshape(n_real, lmax + 1)
     cls = cl[None, :] * (0.5 + jitter)
