@@ -1,6 +1,7 @@
 // Spherical-harmonic analysis of HEALPix RING maps, angular power spectra and
 // their covariance over realisations (section 3.1 eq. (9); section 3.2
-// eqs. (10) and (11)).
+// eqs. (10) and (11)); synthesis with a Gaussian beam and the one-point
+// moments of the smoothed maps (section 3.3 eqs. (12) and (13)).
 //
 // a_lm = (4 pi / N_pix) sum_p map_p lambda_lm(z_p) e^{-i m phi_p}: the pixel
 // quadrature that ANAFAST evaluates without iterative refinement.  Pixels of
@@ -14,9 +15,10 @@
 //
 // Kernels:
 //   ring_dft_kernel     ring DFTs by one radix-4 decimation (every ring holds
-//                       4 n4 pixels): one lane per k' < n4, RG rings of equal
-//                       length per workgroup, the map chunk staged in LDS (FP32
-//                       or FP64 in, FP64 out) and read as broadcasts;
+//                       4 n4 pixels): one lane per k' < n4/K (K output classes),
+//                       RG rings of equal length per workgroup, the map chunk
+//                       staged in LDS (FP32 or FP64 in, FP64 out) and read as
+//                       broadcasts;
 //   lambda_seed_kernel  lambda_mm(z) of every ring pair for m = 0..lmax, carried
 //                       as value * 2^{-600 k} so sin^m(theta) cannot underflow,
 //                       one wave per segment of m;
@@ -25,7 +27,11 @@
 //                       sums over C consecutive l reduced through LDS;
 //   alm2cl              fixed-order reductions;
 //   cov_kernel          the covariance of spectra over realisations on the FP64
-//                       matrix cores.
+//                       matrix cores;
+//   legendre_synth_kernel, ring_idft_kernel   the synthesis: per m and ring pair
+//                       E and O of the beam-weighted a_lm, then the aliasing folds
+//                       and the inverse ring transforms;
+//   moments_*           mean, then the central moments, in fixed-size blocks.
 #include "../../include/ufalcon.h"
 #include "internal.hpp"
 
