@@ -904,14 +904,15 @@ __global__ __launch_bounds__(kLegThreads) void legendre_synth_kernel(const doubl
 // K output classes: lane j' < n4/K writes pixels j' + s n4/K, s < K, from the
 // sums over k' = h mod K kept apart: e^{2 pi i (j' + s n4/K) k' / n4} =
 // e^{2 pi i j' k' / n4} e^{2 pi i s h / K}.  K = 2 needs only the real parts
-// Re P cos and Im P sin (the factors are +-1); K = 4 keeps the complex sums,
-// as the factors include +-i.
-template <typename T, bool kPolar, int K>
-__global__ __launch_bounds__(kDftThreads, kPolar ? (K > 1 ? 3 : 4) : (K > 1 ? 3 : 1)) void ring_idft_kernel(
+// Re P cos and Im P sin (the factors are +-1); K = 4 and 8 keep the complex
+// sums, as the factors include +-i and (+-1 +-i)/sqrt(2).  TH threads per
+// workgroup (128 for K = 8, whose n4/8 lanes would leave half of 256 idle).
+template <typename T, bool kPolar, int K, int TH = kDftThreads>
+__global__ __launch_bounds__(TH, kPolar ? (K > 1 ? 3 : 4) : (K == 8 ? 2 : (K > 1 ? 3 : 1))) void ring_idft_kernel(
     const double2 *__restrict__ F, int64_t N, int32_t lmax, T *__restrict__ map) {
-    static_assert(K == 1 || K == 2 || (K == 4 && !kPolar), "output classes");
+    static_assert(K == 1 || K == 2 || ((K == 4 || K == 8) && !kPolar), "output classes");
     constexpr bool kSplit = K > 1;
-    constexpr int RG = kPolar ? 2 : (K == 4 ? 1 : (K == 2 ? kEqRingsSplit : kEqRings));
+    constexpr int RG = kPolar ? 2 : (K >= 4 ? 1 : (K == 2 ? kEqRingsSplit : kEqRings));
     constexpr int H = K;
     __shared__ double2 ps[RG][4][kDftJ];
     const int64_t nring = 4 * N - 1;
@@ -937,12 +938,12 @@ __global__ __launch_bounds__(kDftThreads, kPolar ? (K > 1 ? 3 : 4) : (K > 1 ? 3 
         n4 = N;
     }
     const int64_t nj = n4 / K;  // lanes needed
-    if ((int64_t)blockIdx.x * kDftThreads >= nj) return;
-    const int64_t jp = (int64_t)blockIdx.x * kDftThreads + threadIdx.x;  // j'
+    if ((int64_t)blockIdx.x * TH >= nj) return;
+    const int64_t jp = (int64_t)blockIdx.x * TH + threadIdx.x;  // j'
     const int64_t n = 4 * n4;
 
     // per class h of k': K <= 2, the sums of Re P cos and Im P sin (the output is
-    // their difference); K = 4, the real and imaginary parts of sum P w
+    // their difference); K >= 4, the real and imaginary parts of sum P w
     double acc[H][RG][4], acn[H][RG][4];
 #pragma unroll
     for (int h = 0; h < H; ++h)
@@ -959,7 +960,7 @@ __global__ __launch_bounds__(kDftThreads, kPolar ? (K > 1 ? 3 : 4) : (K > 1 ? 3 
         // kf = k' + t n4 (c_0 = 1, otherwise 2, with the sign (-1)^u on shifted rings),
         // one (ring, t, k') per work item, so that the long folds of the short polar
         // rings spread over the workgroup, with kFoldBatch loads in flight per step.
-        for (int e = threadIdx.x; e < RG * 4 * kDftJ; e += kDftThreads) {
+        for (int e = threadIdx.x; e < RG * 4 * kDftJ; e += TH) {
             const int g = e / (4 * kDftJ), t = (e / kDftJ) % 4, kk = e % kDftJ;
             double hr = 0.0, hi = 0.0;
             if (kk < cnt) {
@@ -1001,7 +1002,7 @@ __global__ __launch_bounds__(kDftThreads, kPolar ? (K > 1 ? 3 : 4) : (K > 1 ? 3 
         __syncthreads();
         // then P_q[k'] = e^{2 pi i k' q / n} sum_t i^{tq} H_t[k'], in place: each work
         // item reads and writes only its own (ring, k') column
-        for (int e = threadIdx.x; e < RG * kDftJ; e += kDftThreads) {
+        for (int e = threadIdx.x; e < RG * kDftJ; e += TH) {
             const int g = e / kDftJ, kk = e % kDftJ;
             double2 P[4] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0),
                             make_double2(0.0, 0.0)};
@@ -1045,7 +1046,7 @@ __global__ __launch_bounds__(kDftThreads, kPolar ? (K > 1 ? 3 : 4) : (K > 1 ? 3 
                 for (int g = 0; g < RG; ++g)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        if constexpr (K == 4) {
+                        if constexpr (K >= 4) {
                             acc[h][g][q] = fma(-P[g][q].y, wi, fma(P[g][q].x, wr, acc[h][g][q]));
                             acn[h][g][q] = fma(P[g][q].y, wr, fma(P[g][q].x, wi, acn[h][g][q]));
                         } else {
@@ -1066,19 +1067,27 @@ __global__ __launch_bounds__(kDftThreads, kPolar ? (K > 1 ? 3 : 4) : (K > 1 ? 3 
     for (int g = 0; g < RG; ++g) {
         if (!valid[g]) continue;
         T *dst = map + ring_first(N, ring[g]) + 4 * jp;
-        if constexpr (K == 4) {
-            // pixel j' + s n4/4: sum_h Re(i^{s h} E_h), in h order
+        if constexpr (K >= 4) {
+            // pixel j' + s n4/K: sum_h Re(w^{s h} E_h), w = e^{2 pi i / K}, in h order;
+            // w^e = e^{i pi e' / 4} with e' = e 8/K: Re(w^e E) = cos Re E - sin Im E
+            constexpr double kR = 0.70710678118654752440;  // cos(pi/4)
+            constexpr double c8[8] = {1.0, kR, 0.0, -kR, -1.0, -kR, 0.0, kR};
+            constexpr double s8[8] = {0.0, kR, 1.0, kR, 0.0, -kR, -1.0, -kR};
 #pragma unroll
-            for (int sc = 0; sc < 4; ++sc) {
-                T *d = dst + sc * n4;  // 4 (j' + sc n4/4)
+            for (int sc = 0; sc < K; ++sc) {
+                T *d = dst + sc * (4 * n4 / K);  // 4 (j' + sc n4/K)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     double v = 0.0;
 #pragma unroll
-                    for (int h = 0; h < 4; ++h) {
-                        const int e = (sc * h) & 3;  // i^e: Re E, -Im E, -Re E, Im E
-                        const double t = (e & 1) ? acn[h][g][q] : acc[h][g][q];
-                        v += (e == 1 || e == 2) ? -t : t;
+                    for (int h = 0; h < K; ++h) {
+                        const int e = ((sc * h) % K) * (8 / K);
+                        if (s8[e] == 0.0)
+                            v += c8[e] * acc[h][g][q];
+                        else if (c8[e] == 0.0)
+                            v -= s8[e] * acn[h][g][q];
+                        else
+                            v += c8[e] * acc[h][g][q] - s8[e] * acn[h][g][q];
                     }
                     d[q] = (T)v;
                 }
@@ -1188,8 +1197,13 @@ void launch_ring_idft(const double2 *F, int64_t N, int32_t lmax, T *mp, hipStrea
         hipLaunchKernelGGL((ring_idft_kernel<T, true, 2>),
                            dim3((unsigned)((N / 2 + kDftThreads - 1) / kDftThreads), (unsigned)((N - 1) / 2)),
                            dim3(kDftThreads), 0, s, F, N, lmax, mp);
-    // equatorial rings (n4 = N): four output classes when 4 | N, two when 2 | N
-    if (N % 4 == 0)
+    // equatorial rings (n4 = N): eight output classes when 8 | N, four when 4 | N,
+    // two when 2 | N
+    if (N % 8 == 0)
+        hipLaunchKernelGGL((ring_idft_kernel<T, false, 8, 128>),
+                           dim3((unsigned)((N / 8 + 127) / 128), (unsigned)(2 * N + 1)), dim3(128), 0, s, F, N, lmax,
+                           mp);
+    else if (N % 4 == 0)
         hipLaunchKernelGGL((ring_idft_kernel<T, false, 4>),
                            dim3((unsigned)((N / 4 + kDftThreads - 1) / kDftThreads), (unsigned)(2 * N + 1)),
                            dim3(kDftThreads), 0, s, F, N, lmax, mp);
