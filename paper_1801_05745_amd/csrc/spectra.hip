@@ -907,10 +907,13 @@ __global__ __launch_bounds__(kLegThreads) void legendre_synth_kernel(const doubl
 // Re P cos and Im P sin (the factors are +-1); K = 4 and 8 keep the complex
 // sums, as the factors include +-i and (+-1 +-i)/sqrt(2).  TH threads per
 // workgroup (128 for K = 8, whose n4/8 lanes would leave half of 256 idle).
-template <typename T, bool kPolar, int K, int TH = kDftThreads>
-__global__ __launch_bounds__(TH, kPolar ? (K > 1 ? 3 : 4) : (K == 8 ? 2 : (K > 1 ? 3 : 1))) void ring_idft_kernel(
+// J = 2 (with K = 1, any n4): each lane also takes pixel j' + ceil(n4/2), with a
+// second twiddle chain, so that every LDS read serves two outputs.
+template <typename T, bool kPolar, int K, int TH = kDftThreads, int J = 1>
+__global__ __launch_bounds__(TH, kPolar ? (J > 1 ? 2 : (K > 1 ? 3 : 4)) : (K == 8 ? 2 : (K > 1 ? 3 : 1))) void ring_idft_kernel(
     const double2 *__restrict__ F, int64_t N, int32_t lmax, T *__restrict__ map) {
     static_assert(K == 1 || K == 2 || ((K == 4 || K == 8) && !kPolar), "output classes");
+    static_assert(J == 1 || (J == 2 && K == 1), "two pixels per lane without output classes");
     constexpr bool kSplit = K > 1;
     constexpr int RG = kPolar ? 2 : (K >= 4 ? 1 : (K == 2 ? kEqRingsSplit : kEqRings));
     constexpr int H = K;
@@ -937,9 +940,10 @@ __global__ __launch_bounds__(TH, kPolar ? (K > 1 ? 3 : 4) : (K == 8 ? 2 : (K > 1
         }
         n4 = N;
     }
-    const int64_t nj = n4 / K;  // lanes needed
+    const int64_t nj = J == 2 ? (n4 + 1) / 2 : n4 / K;  // lanes needed
     if ((int64_t)blockIdx.x * TH >= nj) return;
     const int64_t jp = (int64_t)blockIdx.x * TH + threadIdx.x;  // j'
+    const int64_t jb = jp + nj;                                  // the second pixel (J = 2)
     const int64_t n = 4 * n4;
 
     // per class h of k': K <= 2, the sums of Re P cos and Im P sin (the output is
@@ -951,6 +955,13 @@ __global__ __launch_bounds__(TH, kPolar ? (K > 1 ? 3 : 4) : (K == 8 ? 2 : (K > 1
         for (int g = 0; g < RG; ++g)
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[h][g][q] = acn[h][g][q] = 0.0;
+    double acc2[RG][4], acn2[RG][4];  // J = 2: the sums of pixel jb
+#pragma unroll
+    for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc2[g][q] = acn2[g][q] = 0.0;
+    double ws2 = 0.0, wc2 = 1.0;  // J = 2: step e^{2 pi i jb / n4}
+    if (J == 2) sincospi(2.0 * (double)(jb % n4) / (double)n4, &ws2, &wc2);
     double ws, wc;  // step e^{2 pi i j' / n4}
     sincospi(2.0 * (double)(jp % n4) / (double)n4, &ws, &wc);
 
@@ -1031,8 +1042,9 @@ __global__ __launch_bounds__(TH, kPolar ? (K > 1 ? 3 : 4) : (K == 8 ? 2 : (K > 1
             for (int q = 0; q < 4; ++q) ps[g][q][kk] = P[q];
         }
         __syncthreads();
-        double wr, wi;
+        double wr, wi, wr2 = 1.0, wi2 = 0.0;
         sincospi(2.0 * (double)((jp * kb) % n4) / (double)n4, &wi, &wr);
+        if (J == 2) sincospi(2.0 * (double)((jb * kb) % n4) / (double)n4, &wi2, &wr2);
         for (int kk = 0; kk < cnt; kk += H) {
 #pragma unroll
             for (int h = 0; h < H; ++h) {  // kb is a multiple of K, so k' = h mod K
@@ -1052,12 +1064,22 @@ __global__ __launch_bounds__(TH, kPolar ? (K > 1 ? 3 : 4) : (K == 8 ? 2 : (K > 1
                         } else {
                             acc[h][g][q] = fma(P[g][q].x, wr, acc[h][g][q]);
                             acn[h][g][q] = fma(P[g][q].y, wi, acn[h][g][q]);
+                            if (J == 2) {
+                                acc2[g][q] = fma(P[g][q].x, wr2, acc2[g][q]);
+                                acn2[g][q] = fma(P[g][q].y, wi2, acn2[g][q]);
+                            }
                         }
                     }
                 const double nr = fma(wr, wc, -(wi * ws));
                 const double ni = fma(wr, ws, wi * wc);
                 wr = nr;
                 wi = ni;
+                if (J == 2) {
+                    const double nr2 = fma(wr2, wc2, -(wi2 * ws2));
+                    const double ni2 = fma(wr2, ws2, wi2 * wc2);
+                    wr2 = nr2;
+                    wi2 = ni2;
+                }
             }
         }
         __syncthreads();
@@ -1104,6 +1126,11 @@ __global__ __launch_bounds__(TH, kPolar ? (K > 1 ? 3 : 4) : (K == 8 ? 2 : (K > 1
         } else {
 #pragma unroll
             for (int q = 0; q < 4; ++q) dst[q] = (T)(acc[0][g][q] - acn[0][g][q]);
+            if (J == 2 && jb < n4) {
+                T *dstb = map + ring_first(N, ring[g]) + 4 * jb;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) dstb[q] = (T)(acc2[g][q] - acn2[g][q]);
+            }
         }
     }
 }
@@ -1191,8 +1218,9 @@ void launch_ring_idft(const double2 *F, int64_t N, int32_t lmax, T *mp, hipStrea
     // polar rings i < N: odd i directly, even i with the even/odd split (polar
     // 0.71 -> 0.39 + 0.24 ms at Nside 1024)
     if (N > 1)
-        hipLaunchKernelGGL((ring_idft_kernel<T, true, 1>), dim3(dx, (unsigned)(N / 2)), dim3(kDftThreads), 0, s, F, N,
-                           lmax, mp);
+        hipLaunchKernelGGL((ring_idft_kernel<T, true, 1, kDftThreads, 2>),
+                           dim3((unsigned)((N / 2 + kDftThreads - 1) / kDftThreads), (unsigned)(N / 2)),
+                           dim3(kDftThreads), 0, s, F, N, lmax, mp);
     if ((N - 1) / 2 > 0)
         hipLaunchKernelGGL((ring_idft_kernel<T, true, 2>),
                            dim3((unsigned)((N / 2 + kDftThreads - 1) / kDftThreads), (unsigned)((N - 1) / 2)),
