@@ -137,17 +137,19 @@ def sht_flops(nside, lmax, inverse=False):
     transforms as four direct length-n/4 DFTs per ring (4 flops per
     real-by-complex multiply-add), divided by the number K of output classes the
     kernels use (equatorial rings: K = 4 when 4 | Nside, 2 when Nside is even;
-    polar rings: K = 2 on even rings; the inverse gains nothing past K = 2, as
-    four classes need the complex sums), and the Legendre step, 7 flops per
-    (l, m, ring pair): the three-term recurrence (3) and the complex
-    multiply-add with the folded ring sum (4)."""
+    polar rings: K = 2 on even rings; the inverse uses K = 8 when 8 | Nside and
+    keeps complex sums from K = 4 on, which doubles the flops per class), and the
+    Legendre step, 7 flops per (l, m, ring pair): the three-term recurrence (3)
+    and the complex multiply-add with the folded ring sum (4)."""
     N = nside
     n_alm = (lmax + 1) * (lmax + 2) // 2
     legendre = 7 * n_alm * 2 * N
-    k_eq = 4 if N % 4 == 0 else (2 if N % 2 == 0 else 1)
     if inverse:
-        k_eq = min(k_eq, 2)
-    dft_eq = (2 * N + 1) * 16 * N * N // k_eq
+        k_eq = 8 if N % 8 == 0 else (4 if N % 4 == 0 else (2 if N % 2 == 0 else 1))
+        dft_eq = (2 * N + 1) * 16 * N * N // k_eq * (2 if k_eq >= 4 else 1)
+    else:
+        k_eq = 4 if N % 4 == 0 else (2 if N % 2 == 0 else 1)
+        dft_eq = (2 * N + 1) * 16 * N * N // k_eq
     dft_polar = sum(2 * 16 * i * i // (2 if i % 2 == 0 else 1) for i in range(1, N))
     return float(legendre + dft_eq + dft_polar)
 
