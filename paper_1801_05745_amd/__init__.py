@@ -149,7 +149,7 @@ def _dtype_code(dt):
         return F32
     if dt == torch.float64:
         return F64
-    raise TypeError(f"unsupported dtype {dt}")
+    raise ValueError(f"unsupported dtype {dt} (float32 or float64)")
 
 
 def _host_doubles(vals):
@@ -387,15 +387,61 @@ def inv_nbar(n_src, box_L, chi_edges, nside, mode=NBAR_EXACT_VOLUME, shell_begin
     return out
 
 
-def born_kappa(counts, W, inv_nbar_, out_dtype=torch.float32):
-    """kappa [T][npix] = sum_b W[t][b] (counts[b] * inv_nbar[b] - 1)."""
-    lib = load()
+def _nside_of(npx: int) -> int:
+    nside = int(round((npx / 12) ** 0.5))
+    if nside < 1 or npix(nside) != npx:
+        raise ValueError(f"{npx} is not a HEALPix pixel count 12 nside^2")
+    return nside
+
+
+def _check_counts(counts):
+    """(B, npix, nside) of a count map; raises ValueError unless it is a contiguous
+    uint32 device tensor [B][12 nside^2].  Shapes and dtypes are checked before the
+    device, so every defect is reported on any machine."""
+    if not isinstance(counts, torch.Tensor) or counts.dim() != 2:
+        raise ValueError("counts must be a 2-d tensor [n_shells][12 nside^2]")
+    if counts.dtype != torch.uint32:
+        raise ValueError(f"counts must be uint32 (got {counts.dtype}); the kernels read 32-bit counts")
     B, npx = counts.shape
+    if B < 1 or B > MAX_SHELLS:
+        raise ValueError(f"counts has {B} shells; 1..{MAX_SHELLS} are supported")
+    return B, npx, _nside_of(npx)
+
+
+def _check_device(where, ref, *tensors):
+    """Every tensor contiguous and on ref's CUDA device."""
+    for t in (ref,) + tensors:
+        if not t.is_contiguous():
+            raise ValueError(f"{where}: tensors must be contiguous")
+        if not t.is_cuda or t.device != ref.device:
+            raise ValueError(f"{where}: tensors must live on one CUDA device (got {t.device} and {ref.device})")
+
+
+def _check_inv_nbar(inv_nbar_, B):
+    if not isinstance(inv_nbar_, torch.Tensor) or inv_nbar_.dtype != torch.float64 or inv_nbar_.numel() != B:
+        raise ValueError(f"inv_nbar must be a float64 tensor of {B} values (one per shell)")
+
+
+def born_kappa(counts, W, inv_nbar_, out_dtype=torch.float32):
+    """kappa [T][npix] = sum_b W[t][b] (counts[b] * inv_nbar[b] - 1).
+
+    counts: uint32 [B][12 nside^2]; W: float64 [T][B] or [B]; inv_nbar: float64 [B];
+    all contiguous on one device (ValueError otherwise)."""
+    lib = load()
+    B, npx, nside = _check_counts(counts)
+    if not isinstance(W, torch.Tensor) or W.dim() not in (1, 2) or W.shape[-1] != B:
+        raise ValueError(f"W must be [T][{B}] or [{B}] (one weight per shell)")
+    if not W.dtype.is_floating_point:
+        raise ValueError("W must be floating point")
+    _check_inv_nbar(inv_nbar_, B)
     W = W.to(torch.float64).contiguous()
     if W.dim() == 1:
         W = W[None, :]
     T = W.shape[0]
-    nside = int(round((npx / 12) ** 0.5))
+    if T < 1 or T > MAX_BINS:
+        raise ValueError(f"{T} source bins; 1..{MAX_BINS} are supported")
+    _dtype_code(out_dtype)
+    _check_device("born_kappa", counts, W, inv_nbar_)
     out = torch.empty((T, npx), dtype=out_dtype, device=counts.device)
     _check(lib.ufalcon_born_kappa(_ptr(counts), B, nside, _ptr(W), _ptr(inv_nbar_), T, _ptr(out),
                                   _dtype_code(out_dtype), _stream(counts.device)), "ufalcon_born_kappa")
@@ -403,10 +449,15 @@ def born_kappa(counts, W, inv_nbar_, out_dtype=torch.float32):
 
 
 def overdensity(counts, chi_edges, inv_nbar_, out_dtype=torch.float32):
+    """Projected overdensity [npix]: the Born sum with weights Delta chi_b / sum Delta chi_b."""
     lib = load()
-    B, npx = counts.shape
-    nside = int(round((npx / 12) ** 0.5))
-    e, _ = _host_doubles(chi_edges)
+    B, npx, nside = _check_counts(counts)
+    e, ne = _host_doubles(chi_edges)
+    if ne != B + 1:
+        raise ValueError(f"chi_edges must hold {B + 1} values for {B} shells (got {ne})")
+    _check_inv_nbar(inv_nbar_, B)
+    _dtype_code(out_dtype)
+    _check_device("overdensity", counts, inv_nbar_)
     out = torch.empty(npx, dtype=out_dtype, device=counts.device)
     _check(lib.ufalcon_overdensity(_ptr(counts), B, nside, e, _ptr(inv_nbar_), _ptr(out), _dtype_code(out_dtype),
                                    _stream(counts.device)), "ufalcon_overdensity")
@@ -414,18 +465,26 @@ def overdensity(counts, chi_edges, inv_nbar_, out_dtype=torch.float32):
 
 
 def born_kappa_adjoint(counts, inv_nbar_, grad_kappa):
-    """grad_W [T][B] = sum_p grad_kappa[t][p] (counts[b][p] inv_nbar[b] - 1), deterministic."""
+    """grad_W [T][B] = sum_p grad_kappa[t][p] (counts[b][p] inv_nbar[b] - 1), deterministic.
+
+    grad_kappa: float32 or float64 [T][npix] or [npix], on the counts' device."""
     lib = load()
-    B, npx = counts.shape
-    nside = int(round((npx / 12) ** 0.5))
+    B, npx, nside = _check_counts(counts)
+    _check_inv_nbar(inv_nbar_, B)
+    if not isinstance(grad_kappa, torch.Tensor) or grad_kappa.dim() not in (1, 2) or grad_kappa.shape[-1] != npx:
+        raise ValueError(f"grad_kappa must be [T][{npx}] or [{npx}]")
     g = grad_kappa.contiguous()
     if g.dim() == 1:
         g = g[None, :]
     T = g.shape[0]
+    if T < 1 or T > MAX_BINS:
+        raise ValueError(f"{T} source bins; 1..{MAX_BINS} are supported")
+    code = _dtype_code(g.dtype)
+    _check_device("born_kappa_adjoint", counts, inv_nbar_, g)
     nbytes = int(lib.ufalcon_born_kappa_adjoint_workspace_size(B, nside, T))
     ws = _workspace(nbytes, counts.device, "adjoint")
     out = torch.empty((T, B), dtype=torch.float64, device=counts.device)
-    _check(lib.ufalcon_born_kappa_adjoint(_ptr(counts), B, nside, _ptr(inv_nbar_), _ptr(g), _dtype_code(g.dtype), T,
+    _check(lib.ufalcon_born_kappa_adjoint(_ptr(counts), B, nside, _ptr(inv_nbar_), _ptr(g), code, T,
                                           _ptr(out), _ptr(ws), ws.numel(), _stream(counts.device)),
            "ufalcon_born_kappa_adjoint")
     return out

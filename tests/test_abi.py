@@ -158,3 +158,40 @@ def test_synthesis_and_moments_validation():
     assert lib.ufalcon_map_moments(FAKE, 0, 2, 0, FAKE, FAKE, mw, None) == EINVAL
     assert lib.ufalcon_map_moments(FAKE, 5, 2, 10, FAKE, FAKE, mw, None) == EINVAL
     assert lib.ufalcon_map_moments(FAKE, 0, 2, 10, FAKE, FAKE, mw - 8, None) == EWORKSPACE
+
+
+def test_binding_rejects_malformed_born_inputs():
+    # shapes and dtypes are checked before the device, so CPU tensors exercise every case
+    import torch
+
+    c32 = torch.zeros((3, 192), dtype=torch.uint32)
+    inb = torch.ones(3, dtype=torch.float64)
+    W = torch.ones((1, 3), dtype=torch.float64)
+    with pytest.raises(ValueError, match="uint32"):
+        uf.born_kappa(torch.zeros((3, 192), dtype=torch.int64), W, inb)   # int64 counts
+    with pytest.raises(ValueError, match="HEALPix"):
+        uf.born_kappa(torch.zeros((3, 190), dtype=torch.uint32), W, inb)  # not 12 nside^2
+    with pytest.raises(ValueError, match="one weight per shell"):
+        uf.born_kappa(c32, torch.ones((1, 2), dtype=torch.float64), inb)  # W narrower than B
+    with pytest.raises(ValueError, match="inv_nbar"):
+        uf.born_kappa(c32, W, torch.ones(2, dtype=torch.float64))
+    with pytest.raises(ValueError, match="inv_nbar"):
+        uf.born_kappa(c32, W, torch.ones(3, dtype=torch.float32))
+    with pytest.raises(ValueError, match="source bins"):
+        uf.born_kappa(c32, torch.ones((9, 3), dtype=torch.float64), inb)
+    with pytest.raises(ValueError, match="dtype"):
+        uf.born_kappa(c32, W, inb, out_dtype=torch.float16)
+    with pytest.raises(ValueError, match="CUDA device"):
+        uf.born_kappa(c32, W, inb)                                         # well formed, but on the host
+    with pytest.raises(ValueError, match="contiguous"):
+        uf.born_kappa(torch.zeros((192, 3), dtype=torch.uint32).t(), W, inb)
+    with pytest.raises(ValueError, match="chi_edges"):
+        uf.overdensity(c32, [1.0, 2.0, 3.0], inb)
+    with pytest.raises(ValueError, match="uint32"):
+        uf.overdensity(c32.to(torch.int32), [1.0, 2.0, 3.0, 4.0], inb)
+    with pytest.raises(ValueError, match="grad_kappa"):
+        uf.born_kappa_adjoint(c32, inb, torch.ones((1, 191)))
+    with pytest.raises(ValueError, match="dtype"):
+        uf.born_kappa_adjoint(c32, inb, torch.ones((1, 192), dtype=torch.float16))
+    with pytest.raises(ValueError, match="uint32"):
+        uf.BornKappa.apply(W, c32.to(torch.int64), inb)

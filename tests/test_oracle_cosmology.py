@@ -188,11 +188,130 @@ def test_adjoint_is_gradient_of_quadratic_loss():
     assert float((Jv * gk).sum()) == pytest.approx(float((v * co.grad_W(counts, nb, gk)).sum()), rel=1e-12)
 
 
-def test_weight_derivative_omega_m_matches_finite_difference_of_closed_form_limit():
-    # Richardson derivative agrees with a plain central difference at a smaller step
-    chi = [co.chi(z, 0.3) for z in (0.1, 0.3, 0.5)]
-    src = co.DeltaSource(0.6)
-    d = co.weight_derivative(chi, 0.3, src, "omega_m")
-    h = 1e-5
-    fd = (co.lensing_weights(chi, 0.3 + h, src) - co.lensing_weights(chi, 0.3 - h, src)) / (2 * h)
-    assert np.allclose(d, fd, rtol=1e-6)
+def _dW_domega_delta_mp(chi_edges, om, zs, dps=25):
+    """dW_b/dOmega_m of a delta source with frozen comoving edges, by forward
+    sensitivities at 25 digits (independent of the oracle's differences).
+
+    In the dimensionless distance D the edges D_b = chi_b H0/c do not move, so
+        W_b = (3/2) Om int_{D_b}^{min(D_{b+1}, D_s)} (1 + z(D)) D (D_s - D)/D_s dD
+    with dz/dD = E(z; Om).  Differentiating: y = dz/dOm at fixed D obeys
+    dy/dD = (dE/dz) y + dE/dOm, y(0) = 0, and dD_s/dOm = -int_0^zs (dE/dOm)/E^2 dz;
+    the moving upper limit D_s adds nothing (the integrand vanishes there)."""
+    C = co.C_OVER_H0
+    with mpmath.workdps(dps):
+        Om = mpmath.mpf(om)
+        E = lambda z: mpmath.sqrt(Om * (1 + z) ** 3 + 1 - Om)
+        dEdz = lambda z: 3 * Om * (1 + z) ** 2 / (2 * E(z))
+        dEdO = lambda z: ((1 + z) ** 3 - 1) / (2 * E(z))
+        Ds = mpmath.quad(lambda z: 1 / E(z), [0, zs])
+        dDs = -mpmath.quad(lambda z: dEdO(z) / E(z) ** 2, [0, zs])
+        sol = mpmath.odefun(lambda D, v: [E(v[0]), dEdz(v[0]) * v[1] + dEdO(v[0])], 0,
+                            [mpmath.mpf(0), mpmath.mpf(0)])
+        W, dW = [], []
+        for b in range(len(chi_edges) - 1):
+            lo = mpmath.mpf(chi_edges[b]) / C
+            hi = min(mpmath.mpf(chi_edges[b + 1]) / C, Ds)
+            if lo >= Ds:
+                W.append(0.0)
+                dW.append(0.0)
+                continue
+            f = lambda D: (1 + sol(D)[0]) * D * (Ds - D) / Ds
+            g = lambda D: sol(D)[1] * D * (Ds - D) / Ds + (1 + sol(D)[0]) * D * D / Ds ** 2 * dDs
+            Wb = mpmath.fraction(3, 2) * Om * mpmath.quad(f, [lo, hi])
+            W.append(float(Wb))
+            dW.append(float(Wb / Om + mpmath.fraction(3, 2) * Om * mpmath.quad(g, [lo, hi])))
+    return np.array(W), np.array(dW)
+
+
+def test_weight_derivative_omega_m_frozen_chi_edges():
+    # the Omega_m derivative with comoving edges fixed (their redshifts move):
+    # against the sensitivity-equation value above, including a shell cut by the source
+    chi = [co.chi(z, 0.3) for z in (0.1, 0.3, 0.5, 0.7)]
+    W_mp, dW_mp = _dW_domega_delta_mp(chi, 0.3, 0.6)
+    assert np.allclose(co.lensing_weights(chi, 0.3, co.DeltaSource(0.6)), W_mp, rtol=1e-12)
+    got = co.weight_derivative(chi, 0.3, co.DeltaSource(0.6), "omega_m")
+    assert np.allclose(got, dW_mp, rtol=1e-8)
+    # the pin tells the readings apart: with the redshift edges held fixed instead,
+    # the derivative is off by 8 % to 200 %
+    ze = co.shell_z_edges(chi, 0.3)
+    h = 1e-4
+    Wz = lambda om: np.array([co.weight_delta(ze[b], ze[b + 1], 0.6, om) for b in range(3)])
+    frozen_z = (Wz(0.3 + h) - Wz(0.3 - h)) / (2 * h)
+    assert np.all(np.abs(frozen_z - dW_mp) > 0.05 * np.abs(dW_mp))
+
+
+def test_weight_derivative_smail_z0_analytic():
+    # d/dz0 of a Smail source: the z0 derivative of the normalised n(z) written out,
+    # (dn nrm - n dnrm)/nrm^2 with dn/dz0 = n beta (z/z0)^beta / z0, integrated at 20
+    # digits with D(z) from an ODE solution (no differences involved)
+    chi = [co.chi(z, 0.3) for z in (0.1, 0.3, 0.5, 0.7)]
+    C = co.C_OVER_H0
+    with mpmath.workdps(20):
+        Om = mpmath.mpf("0.3")
+        E = lambda z: mpmath.sqrt(Om * (1 + z) ** 3 + 1 - Om)
+        Dz = mpmath.odefun(lambda z, D: 1 / E(z), 0, mpmath.mpf(0))
+        a, b, s, zmax = mpmath.mpf(2), mpmath.mpf("1.5"), mpmath.mpf("0.3"), mpmath.mpf(1)
+        n = lambda z: z ** a * mpmath.exp(-(z / s) ** b) if z > 0 else mpmath.mpf(0)
+        dn = lambda z: n(z) * b * (z / s) ** b / s
+        nrm, dnrm = mpmath.quad(n, [0, zmax]), mpmath.quad(dn, [0, zmax])
+        ze = [mpmath.findroot(lambda z: Dz(z) - mpmath.mpf(c) / C, 0.3) for c in chi]
+        want = []
+        for k in range(3):
+            def dq(z):
+                Dzz = Dz(z)
+                return mpmath.quad(lambda zp: (dn(zp) * nrm - n(zp) * dnrm) / nrm ** 2 * (1 - Dzz / Dz(zp)),
+                                   [z, zmax])
+            want.append(float(mpmath.fraction(3, 2) * Om *
+                              mpmath.quad(lambda z: (1 + z) * Dz(z) / E(z) * dq(z), [ze[k], ze[k + 1]])))
+    got = co.weight_derivative(chi, 0.3, co.SmailSource(2.0, 1.5, 0.3, 1.0), "z0")
+    assert np.allclose(got, want, rtol=1e-8)
+
+
+def _eq7_literal(counts, z_edges, om, n_part, L, nside):
+    """Eq. (7) evaluated as printed, term by term:
+    delta = sum_b [ N_pix/(4 pi) (V/N) (H0/c)^2 n_p / D^2(z_b) - (c/H0) Delta D_b ] / sum_b (c/H0) Delta D_b,
+    with D(z) by 30-digit quadrature and z_b the lower edge of shell b."""
+    C = mpmath.mpf(co.C_OVER_H0)
+    npx = 12 * nside * nside
+    with mpmath.workdps(30):
+        D = [mpmath.quad(lambda t: 1 / mpmath.sqrt(om * (1 + t) ** 3 + 1 - om), [0, z]) for z in z_edges]
+        dD = [D[b + 1] - D[b] for b in range(len(D) - 1)]
+        den = sum(C * d for d in dD)
+        pre = [npx / (4 * mpmath.pi) * (mpmath.mpf(L) ** 3 / n_part) / C ** 2 / D[b] ** 2 for b in range(len(dD))]
+        out = np.empty(counts.shape[1])
+        for p in range(counts.shape[1]):
+            out[p] = float(sum(pre[b] * int(counts[b, p]) - C * dD[b] for b in range(len(dD))) / den)
+    return out, [float(C * d) for d in D]
+
+
+def test_overdensity_is_printed_eq7():
+    # the oracle's overdensity with the lower-edge nbar equals eq. (7) as printed
+    om, L, N, nside = 0.3, 700.0, 250000, 4
+    z_edges = [0.04, 0.07, 0.1, 0.14]
+    rng = np.random.default_rng(7)
+    counts = rng.integers(0, 40, size=(3, 12 * nside * nside))
+    want, chi = _eq7_literal(counts, z_edges, om, N, L, nside)
+    got = co.overdensity(counts, chi, co.nbar(N, L, chi, nside, mode="lower_edge"))
+    tol = 1e-12 * np.abs(want).max()
+    assert np.abs(got - want).max() <= tol
+    # what the pin rejects: shells weighted by Delta z instead of Delta chi, or the
+    # sum left without its normalisation
+    dz = np.diff(z_edges)
+    nb = co.nbar(N, L, chi, nside, mode="lower_edge")
+    by_dz = co.kappa(counts, dz[None, :] / dz.sum(), nb)[0]
+    unnormalised = co.kappa(counts, np.diff(chi)[None, :], nb)[0]
+    assert np.abs(by_dz - want).max() > 1e6 * tol
+    assert np.abs(unnormalised - want).max() > 1e6 * tol
+
+
+def test_overdensity_single_particle_closed_form():
+    # one particle in shell 1 at pixel 5 (Nside 1, 12 pixels): eq. (7) reduces to
+    #   delta[5] = 3 L^3 / (pi N chi_1^2 (chi_3 - chi_0)) - 1,  delta = -1 elsewhere
+    chi = [100.0, 200.0, 400.0, 450.0]
+    L, N = 1000.0, 1000
+    counts = np.zeros((3, 12), dtype=np.int64)
+    counts[1, 5] = 1
+    got = co.overdensity(counts, chi, co.nbar(N, L, chi, 1, mode="lower_edge"))
+    want5 = 3.0 * L ** 3 / (math.pi * N * chi[1] ** 2 * (chi[3] - chi[0])) - 1.0
+    assert got[5] == pytest.approx(want5, rel=1e-14)
+    assert np.all(np.delete(got, 5) == -1.0)
