@@ -57,6 +57,8 @@ typedef struct ufalcon_status {
     unsigned long long n_invalid;    /* particles skipped for a non-finite coordinate */
     unsigned long long n_guarded;    /* instances decided by the exact path (near a boundary) */
     unsigned long long n_unresolved; /* instances the exact path could not certify (expected 0) */
+    unsigned long long n_fallback;   /* instances of the partitioned path added by a global atomic because
+                                        the chunk's key buffer was full (exact, but slow; expected 0) */
 } ufalcon_status;
 
 const char *ufalcon_strerror(int code);

@@ -40,7 +40,8 @@ class UfalconError(RuntimeError):
 
 class Status(ctypes.Structure):
     _fields_ = [("n_instances", ctypes.c_ulonglong), ("n_invalid", ctypes.c_ulonglong),
-                ("n_guarded", ctypes.c_ulonglong), ("n_unresolved", ctypes.c_ulonglong)]
+                ("n_guarded", ctypes.c_ulonglong), ("n_unresolved", ctypes.c_ulonglong),
+                ("n_fallback", ctypes.c_ulonglong)]
 
 
 class Source(ctypes.Structure):
@@ -206,14 +207,16 @@ def partition_workspace(n, n_rep, shells_in_range, nside, max_keys=None, device=
     return _workspace(nbytes, device, "partition")
 
 
+STATUS_FIELDS = ("n_instances", "n_invalid", "n_guarded", "n_unresolved", "n_fallback")
+
+
 def new_status(device="cuda"):
-    """A zeroed device ufalcon_status (4 x uint64)."""
-    return torch.zeros(4, dtype=torch.int64, device=device)
+    """A zeroed device ufalcon_status (one uint64 per field of STATUS_FIELDS)."""
+    return torch.zeros(len(STATUS_FIELDS), dtype=torch.int64, device=device)
 
 
 def status_dict(st: torch.Tensor):
-    v = st.cpu().tolist()
-    return {"n_instances": v[0], "n_invalid": v[1], "n_guarded": v[2], "n_unresolved": v[3]}
+    return dict(zip(STATUS_FIELDS, st.cpu().tolist()))
 
 
 # ---------------------------------------------------------------- entry points

@@ -112,7 +112,7 @@ struct BinParams {
 // Per-lane event counts, flushed into the status by flush_stats (also whenever a
 // lane's instance count passes 2^30, see bin_wave_range).
 struct LaneStats {
-    uint32_t inst = 0, guarded = 0, unresolved = 0, invalid = 0;
+    uint32_t inst = 0, guarded = 0, unresolved = 0, invalid = 0, fallback = 0;
 };
 
 struct Shared {
@@ -143,12 +143,13 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 // Add the wave's counts to the status and reset them.  Reached by all 64 lanes.
 __device__ __forceinline__ void flush_stats(ufalcon_status *status, LaneStats &st) {
     const unsigned long long a = wave_sum(st.inst), b = wave_sum(st.guarded), c = wave_sum(st.unresolved),
-                             d = wave_sum(st.invalid);
+                             d = wave_sum(st.invalid), f = wave_sum(st.fallback);
     if (status && (threadIdx.x & 63) == 0) {
         if (a) atomicAdd(&status->n_instances, a);
         if (b) atomicAdd(&status->n_guarded, b);
         if (c) atomicAdd(&status->n_unresolved, c);
         if (d) atomicAdd(&status->n_invalid, d);
+        if (f) atomicAdd(&status->n_fallback, f);
     }
     st = LaneStats{};
 }
@@ -230,13 +231,16 @@ __device__ __forceinline__ uint32_t bin_instance(const BinCore &c, const Shared 
 
 // Wave-cooperative append of the lanes' keys (kNoKey lanes skip).  Must be
 // reached by all 64 lanes of the wave.
-__device__ __forceinline__ void emit_keys(Emitter &em, const BinCore &c, uint32_t key) {
+__device__ __forceinline__ void emit_keys(Emitter &em, const BinCore &c, uint32_t key, LaneStats &st) {
     const int lane = threadIdx.x & 63;
     const bool has = key != kNoKey;
     const unsigned long long m = wave_ballot(has);
     if (m == 0ull) return;
     if (em.full) {  // buffer exhausted earlier: count directly
-        if (has) atomicAdd(c.counts + key, 1u);
+        if (has) {
+            atomicAdd(c.counts + key, 1u);
+            ++st.fallback;
+        }
         return;
     }
     const int n = __popcll(m);
@@ -258,7 +262,10 @@ __device__ __forceinline__ void emit_keys(Emitter &em, const BinCore &c, uint32_
         // chunk-aligned capacity: this reservation lies wholly outside the buffer
         em.full = true;
         em.fill = kKeyChunk;
-        if (has && rank >= room) atomicAdd(c.counts + key, 1u);
+        if (has && rank >= room) {
+            atomicAdd(c.counts + key, 1u);
+            ++st.fallback;
+        }
         return;
     }
     em.base = b;
@@ -312,7 +319,7 @@ __device__ __forceinline__ void take_batch(const BinCore &c, const Shared &sh, c
     else
         q.nc = rest;
     const uint32_t key = bin_instance<kMode, kBelt>(c, sh, E, Nd, ax, ay, az, st);
-    if (kMode == kEmit) emit_keys(em, c, key);
+    if (kMode == kEmit) emit_keys(em, c, key, st);
 }
 
 // Per-wave core: this wave handles particles base, base + stride, ... (64 at a
@@ -401,11 +408,11 @@ __device__ __forceinline__ void drain_queue(const BinCore &c, const Shared &sh, 
     uint32_t key = kNoKey;
     if (lane < q.nb)
         key = bin_instance<kMode, true>(c, sh, E, Nd, q.q[lane], q.q[kQueue + lane], q.q[2 * kQueue + lane], st);
-    if (kMode == kEmit) emit_keys(em, c, key);
+    if (kMode == kEmit) emit_keys(em, c, key, st);
     key = kNoKey;
     const int t = kQueue - 1 - lane;
     if (lane < q.nc) key = bin_instance<kMode, false>(c, sh, E, Nd, q.q[t], q.q[kQueue + t], q.q[2 * kQueue + t], st);
-    if (kMode == kEmit) emit_keys(em, c, key);
+    if (kMode == kEmit) emit_keys(em, c, key, st);
     wave_lds_sync();
     q.nb = 0;
     q.nc = 0;

@@ -108,7 +108,10 @@ static bool plan_layout(PartLayout &L, int64_t n, int64_t ncells, int img_bound,
     L.off_thist = o; o = align256(o + sizeof(uint32_t) * (size_t)wide * L.hist_rows);
     const size_t fixed = o;
     L.cap = cap;
-    L.budget = cap - slack;
+    // a chunk's planned bound can pass the budget by up to one group's bound
+    // (the plan cuts at group boundaries), and every wave may leave one partly
+    // filled reservation: both fit below cap
+    L.budget = cap - slack - gmax;
     L.off_keysa = fixed;
     L.off_keysb = align256(fixed + sizeof(uint32_t) * cap);
     L.total = align256(L.off_keysb + sizeof(uint32_t) * cap);
@@ -144,7 +147,21 @@ static int image_bound(const BinCore &c, const double *e, int nb) {
 
 // ------------------------------------------------------------------ kernels
 
-// 0a. upper bound of in-range images per group of kGroup particles
+// 0a. upper bound of in-range images per group of kGroup particles.  Per
+// particle and image column (sx, sy), the images sz in [-R, R] with
+// lo2 <= rho^2 + dz^2 < hi2 are counted in closed form: dz = bz + sz L must
+// satisfy |dz| < h = sqrt(hi2 - rho^2) and, when rho^2 < lo2, not |dz| < g =
+// sqrt(lo2 - rho^2).  h is widened and g narrowed by a relative 1e-6 (plus
+// 1e-9 L), so rounding can only add images to the count: it bounds the keys
+// the key pass emits, which is all the chunk plan needs.
+__device__ __forceinline__ int count_in_slab(double bz, double half, double invL, int R) {
+    // integers s in [-R, R] with -half <= bz + s L <= half
+    if (R == 0) return fabs(bz) <= half ? 1 : 0;
+    const double lo = ceil((-half - bz) * invL), hi = floor((half - bz) * invL);
+    const double a = fmax(lo, (double)-R), b = fmin(hi, (double)R);
+    return b >= a ? (int)(b - a) + 1 : 0;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void count_groups_kernel(BinCore c, uint32_t *grp) {
     __shared__ unsigned int red[4];
@@ -154,6 +171,8 @@ __global__ __launch_bounds__(256) void count_groups_kernel(BinCore c, uint32_t *
     const int64_t g = blockIdx.x;
     const int64_t beg = g * kGroup;
     const int64_t end = beg + kGroup < c.n ? beg + kGroup : c.n;
+    const double invL = c.R > 0 ? 1.0 / c.L : 0.0;
+    const double pad = 1e-9 * c.L;
     unsigned int cnt = 0;
     for (int64_t i = beg + threadIdx.x; i < end; i += 256) {
         const double x = (double)X[i], y = (double)Y[i], z = (double)Z[i];
@@ -163,11 +182,17 @@ __global__ __launch_bounds__(256) void count_groups_kernel(BinCore c, uint32_t *
             const double dx = bx + (double)sx * c.L;
             for (int sy = -c.R; sy <= c.R; ++sy) {
                 const double dy = by + (double)sy * c.L;
-                for (int sz = -c.R; sz <= c.R; ++sz) {
-                    const double dz = bz + (double)sz * c.L;
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    cnt += (r2 >= c.lo2 && r2 < c.hi2) ? 1u : 0u;
+                const double rho2 = dx * dx + dy * dy;
+                if (rho2 >= c.hi2 * (1.0 + 1e-6)) continue;
+                const double h = sqrt(fmax(c.hi2 - rho2, 0.0)) * (1.0 + 1e-6) + pad;
+                int k = count_in_slab(bz, h, invL, c.R);
+                if (rho2 < c.lo2) {
+                    const double gg = sqrt(c.lo2 - rho2) * (1.0 - 1e-6) - pad;
+                    // strictly inside the inner sphere: |dz| < gg, counted as the closed slab
+                    // of half-width gg shrunk once more by pad
+                    if (gg > pad) k -= count_in_slab(bz, gg - pad, invL, c.R);
                 }
+                cnt += (unsigned)k;
             }
         }
     }
@@ -177,8 +202,10 @@ __global__ __launch_bounds__(256) void count_groups_kernel(BinCore c, uint32_t *
     if (threadIdx.x == 0) grp[g] = red[0] + red[1] + red[2] + red[3];
 }
 
-// 0b. chunk plan: chunk k covers groups [chunk[k], chunk[k+1]); every chunk's
-// bound stays below the budget (each group's bound is far below it).
+// 0b. chunk plan: chunk k covers groups [chunk[k], chunk[k+1]), the groups whose
+// exclusive prefix of bounds lies in [k budget, (k+1) budget); a chunk's bound
+// therefore stays below budget + one group's bound, which the layout keeps
+// below the key buffer's capacity.
 __global__ __launch_bounds__(1024) void plan_chunks_kernel(const uint32_t *grp, int64_t ngroups,
                                                            unsigned long long budget, int kmax, uint32_t *chunk,
                                                            PartHeader *hdr) {
@@ -403,45 +430,66 @@ __global__ __launch_bounds__(256) void bucket_scan_kernel(PartStep ps, int chunk
 }
 
 // exclusive scan of the bucket totals (one workgroup, running carry); for level 1
-// also the first super-tile of every level-2 segment
+// also the first super-tile of every level-2 segment.  Each thread scans kPer
+// consecutive totals serially; the thread sums are scanned across the wave
+// with shuffles and across the 16 waves through LDS: two barriers per
+// 1024 * kPer totals.
 __global__ __launch_bounds__(1024) void bucket_base_kernel(const uint32_t *tot, int64_t nbkt, uint32_t *base,
                                                            uint32_t *tiles, const PartHeader *hdr, int chunk_k,
                                                            int kmax) {
-    __shared__ unsigned long long a[1024], bt[1024];
-    __shared__ unsigned long long carry, carry_t;
+    constexpr int kPer = 8;
+    constexpr int kW = 1024 / 64;
+    __shared__ unsigned long long wh[kW], wt[kW];
     if (chunk_k >= (int)hdr->n_chunks && chunk_k != kmax - 1) return;
-    if (threadIdx.x == 0) {
-        carry = 0;
-        carry_t = 0;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    unsigned long long carry = 0, carry_t = 0;  // uniform over the workgroup
+    for (int64_t s = 0; s < nbkt; s += 1024 * kPer) {
+        const int64_t i0 = s + (int64_t)tid * kPer;
+        uint32_t h[kPer];
+        unsigned long long sh = 0, st = 0;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            h[u] = i0 + u < nbkt ? tot[i0 + u] : 0u;
+            sh += h[u];
+            st += (h[u] + kSuper - 1) / kSuper;
+        }
+        unsigned long long xh = sh, xt = st;  // inclusive scan over the wave
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned long long yh = __shfl_up(xh, off, 64), yt = __shfl_up(xt, off, 64);
+            if (lane >= off) {
+                xh += yh;
+                xt += yt;
+            }
+        }
+        if (lane == 63) {
+            wh[w] = xh;
+            wt[w] = xt;
+        }
+        __syncthreads();
+        unsigned long long ph = carry + xh - sh, pt = carry_t + xt - st;
+        unsigned long long seg_h = 0, seg_t = 0;
+        for (int k = 0; k < kW; ++k) {
+            if (k < w) {
+                ph += wh[k];
+                pt += wt[k];
+            }
+            seg_h += wh[k];
+            seg_t += wt[k];
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            if (i0 + u < nbkt) {
+                base[i0 + u] = (uint32_t)ph;
+                if (tiles) tiles[i0 + u] = (uint32_t)pt;
+            }
+            ph += h[u];
+            pt += (h[u] + kSuper - 1) / kSuper;
+        }
+        carry += seg_h;
+        carry_t += seg_t;
+        __syncthreads();  // wh/wt are rewritten by the next segment
     }
-    __syncthreads();
-    for (int64_t s = 0; s < nbkt; s += 1024) {
-        const int64_t i = s + threadIdx.x;
-        const unsigned long long h = i < nbkt ? tot[i] : 0ull;
-        const unsigned long long nt = (h + kSuper - 1) / kSuper;
-        a[threadIdx.x] = h;
-        bt[threadIdx.x] = nt;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const unsigned long long x = threadIdx.x >= off ? a[threadIdx.x - off] : 0ull;
-            const unsigned long long y = threadIdx.x >= off ? bt[threadIdx.x - off] : 0ull;
-            __syncthreads();
-            a[threadIdx.x] += x;
-            bt[threadIdx.x] += y;
-            __syncthreads();
-        }
-        if (i < nbkt) {
-            base[i] = (uint32_t)(carry + a[threadIdx.x] - h);
-            if (tiles) tiles[i] = (uint32_t)(carry_t + bt[threadIdx.x] - nt);
-        }
-        __syncthreads();
-        if (threadIdx.x == 1023) {
-            carry += a[1023];
-            carry_t += bt[1023];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         base[nbkt] = (uint32_t)carry;
         if (tiles) tiles[nbkt] = (uint32_t)carry_t;
     }
