@@ -68,6 +68,16 @@ int ufalcon_version(void);
 int ufalcon_fill_u32(uint32_t *p, int64_t n, uint32_t value, ufalcon_stream_t stream);
 
 /*
+ * Count maps as int64 (section 2.3 eq. (5): n_p counts particles; a caller
+ * that keeps 64-bit maps, or adds more calls into one map than a uint32 cell
+ * can hold, bins each call into uint32 and widens or accumulates here):
+ *   out[i] = counts[i]            (accumulate = 0)
+ *   out[i] = out[i] + counts[i]   (accumulate = 1)
+ * counts device uint32[n]; out device int64[n].  Errors: EINVAL, EHIP.
+ */
+int ufalcon_counts_to_i64(const uint32_t *counts, int64_t n, int64_t *out, int accumulate, ufalcon_stream_t stream);
+
+/*
  * Shell binning (section 2.3 eq. (5): n_p(pix, Delta chi_b), the number of
  * particles of shell b in pixel pix; section 2.4 eq. (8): shells by comoving
  * radius with the observer at the box centre; section 2.4: HEALPix RING

@@ -207,12 +207,22 @@ def overdensity(counts, chi_edges, nb):
     return kappa(counts, dchi[None, :] / dchi.sum(), nb)[0]
 
 
-def grad_W(counts, nb, grad_kappa):
-    """dL/dW[t,b] = sum_p g_t[p] (n_b[p]/nbar_b - 1) for a loss L with dL/dkappa = g."""
+def grad_W(counts, nb, grad_kappa, summation="exact"):
+    """dL/dW[t,b] = sum_p g_t[p] (n_b[p]/nbar_b - 1) for a loss L with dL/dkappa = g.
+
+    summation="exact": math.fsum (correctly rounded); "pairwise": numpy's pairwise
+    sum, relative error of order log2(N_pix) ulp of sum |terms| -- for maps too
+    large for fsum to finish in seconds."""
     counts = np.asarray(counts)
     g = np.atleast_2d(np.asarray(grad_kappa, dtype=np.float64))
     out = np.zeros((g.shape[0], counts.shape[0]))
     for t in range(g.shape[0]):
         for b in range(counts.shape[0]):
-            out[t, b] = math.fsum(g[t] * (counts[b].astype(np.float64) / nb[b] - 1.0))
+            terms = g[t] * (counts[b].astype(np.float64) / nb[b] - 1.0)
+            if summation == "exact":
+                out[t, b] = math.fsum(terms)
+            elif summation == "pairwise":
+                out[t, b] = float(np.sum(terms))
+            else:
+                raise ValueError(summation)
     return out

@@ -70,6 +70,7 @@ _SIGS = {
     "ufalcon_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "ufalcon_version": (ctypes.c_int, []),
     "ufalcon_fill_u32": (ctypes.c_int, [_P, _I64, ctypes.c_uint32, _P]),
+    "ufalcon_counts_to_i64": (ctypes.c_int, [_P, _I64, _P, ctypes.c_int, _P]),
     "ufalcon_bin_shells_workspace_size": (_SZ, [_I64]),
     "ufalcon_bin_shells_workspace_size_partitioned": (_SZ, [_I64, _I32, _I32, _I64, _I64]),
     "ufalcon_bin_shells": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, ctypes.POINTER(_D), _D, _I32,
@@ -228,6 +229,22 @@ def fill_u32(t: torch.Tensor, value: int = 0):
     return t
 
 
+def counts_to_i64(counts: torch.Tensor, out: torch.Tensor = None, accumulate: bool = False):
+    """int64 copy of a uint32 count map (or, with accumulate, out += counts)."""
+    lib = load()
+    if counts.dtype != torch.uint32 or not counts.is_contiguous() or not counts.is_cuda:
+        raise ValueError("counts must be a contiguous uint32 device tensor")
+    if out is None:
+        if accumulate:
+            raise ValueError("accumulate needs an out tensor")
+        out = torch.empty(counts.shape, dtype=torch.int64, device=counts.device)
+    if out.dtype != torch.int64 or not out.is_contiguous() or out.numel() != counts.numel() or out.device != counts.device:
+        raise ValueError("out must be a contiguous int64 tensor of the counts' size on their device")
+    _check(lib.ufalcon_counts_to_i64(_ptr(counts), counts.numel(), _ptr(out), 1 if accumulate else 0,
+                                     _stream(counts.device)), "ufalcon_counts_to_i64")
+    return out
+
+
 def new_counts(n_shells: int, nside: int, device="cuda"):
     t = torch.empty((n_shells, npix(nside)), dtype=torch.uint32, device=device)
     return fill_u32(t, 0)
@@ -312,6 +329,65 @@ def bin_shells(x, y, z, chi_edges, nside, observer=None, box_L=0.0, n_rep=0, she
     else:
         _check(lib.ufalcon_bin_shells_timed(*args, timer.handle), "ufalcon_bin_shells_timed")
     return counts
+
+
+class HostStream:
+    """Bins particles held in pinned host memory: chunks of `chunk` particles are
+    copied to two device staging slots on a copy stream, and each chunk is binned
+    on the caller's stream as soon as its copy lands, so the copy of chunk k+1
+    overlaps the binning of chunk k (the subvolume decomposition of section 2.4:
+    chunk maps add up in the count map).  The slots and the binning workspace are
+    allocated once, at construction.  copy_ms() reads the copy engine's busy time
+    (HIP events on the copy stream) of the last run."""
+
+    def __init__(self, chunk, n_rep_max, shells_max, nside, device="cuda", dtype=torch.float32):
+        self.chunk = int(chunk)
+        self.device = torch.device(device)
+        self.slots = [[torch.empty(self.chunk, dtype=dtype, device=self.device) for _ in range(3)]
+                      for _ in range(2)]
+        self.ws = partition_workspace(self.chunk, n_rep_max, shells_max, nside, device=self.device, cached=False)
+        self.copy = torch.cuda.Stream(self.device)
+        self._events = []
+
+    def run(self, boxes, chi_edges, nside, counts, status=None):
+        """boxes: dicts with host (pinned) x, y, z, box_L, n_rep, shell_begin, shell_end
+        (and optionally observer); every chunk is added to `counts`."""
+        compute = torch.cuda.current_stream(self.device)
+        free = [None, None]
+        self._events = []
+        j = 0
+        for b in boxes:
+            hx, hy, hz = b["x"], b["y"], b["z"]
+            for t in (hx, hy, hz):
+                if t.is_cuda or not t.is_pinned():
+                    raise ValueError("HostStream needs pinned host tensors")
+            n = hx.numel()
+            for k in range(0, n, self.chunk):
+                m = min(self.chunk, n - k)
+                s = j & 1
+                ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                with torch.cuda.stream(self.copy):
+                    if free[s] is not None:
+                        self.copy.wait_event(free[s])
+                    ev[0].record(self.copy)
+                    for a, h in enumerate((hx, hy, hz)):
+                        self.slots[s][a][:m].copy_(h[k:k + m], non_blocking=True)
+                    ev[1].record(self.copy)
+                compute.wait_event(ev[1])
+                bin_shells(self.slots[s][0][:m], self.slots[s][1][:m], self.slots[s][2][:m], chi_edges, nside,
+                           observer=b.get("observer"), box_L=b["box_L"], n_rep=b["n_rep"],
+                           shell_begin=b.get("shell_begin", 0), shell_end=b.get("shell_end"), counts=counts,
+                           status=status, workspace=self.ws)
+                done = torch.cuda.Event()
+                done.record(compute)
+                free[s] = done
+                self._events.append(ev)
+                j += 1
+        return counts
+
+    def copy_ms(self):
+        """Milliseconds the copy stream spent in the last run's copies (waits for them)."""
+        return sum(a.elapsed_time(b) for a, b in self._events)
 
 
 def comoving_distance(z: torch.Tensor, omega_m: float):

@@ -98,6 +98,13 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
     if (i < n - tail0) p[tail0 + i] = v;
 }
 
+// out[i] (+)= counts[i] widened to int64
+__global__ void widen_counts_kernel(const uint32_t *c, int64_t n, int64_t *out, int accumulate) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = (accumulate ? out[i] : 0) + (int64_t)c[i];
+}
+
 // ------------------------------------------------------------------ batched
 struct BatchItemDev {
     BinCore c;
@@ -316,6 +323,16 @@ extern "C" int ufalcon_fill_u32(uint32_t *p, int64_t n, uint32_t value, ufalcon_
     return UFALCON_OK;
 }
 
+extern "C" int ufalcon_counts_to_i64(const uint32_t *counts, int64_t n, int64_t *out, int accumulate,
+                                     ufalcon_stream_t stream) {
+    if (n < 0 || (n > 0 && (!counts || !out)) || (accumulate != 0 && accumulate != 1)) return UFALCON_EINVAL;
+    if (n == 0) return UFALCON_OK;
+    hipLaunchKernelGGL(widen_counts_kernel, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, as_stream(stream), counts,
+                       n, out, accumulate);
+    UFX_HIP_CHECK(hipGetLastError());
+    return UFALCON_OK;
+}
+
 static int bin_shells_entry(const void *x, const void *y, const void *z, int64_t n, int dtype,
                             const double *observer, double box_L, int32_t n_rep, const double *chi_edges,
                             int32_t n_shells, int32_t shell_begin, int32_t shell_end, int64_t nside, uint32_t *counts,
@@ -392,8 +409,9 @@ struct ufalcon_batch_plan {
     int accumulation = UFALCON_ACCUMULATE_PARTITIONED;
     // partitioned accumulation: two lanes (the caller's stream and aux_stream),
     // each with its own workspace; realisations alternate between them, and the
-    // key pass of realisation k waits for that of k-1 (keys_done[k-1]), so one
-    // realisation's partition and accumulation overlap the next one's key pass
+    // first key pass of realisation k waits for the first one of k-1
+    // (keys_done[k-1]), so one realisation's partitions and later chunks overlap
+    // the next one's key passes
     void *d_part = nullptr;  // workspace of lane 0
     void *d_part2 = nullptr; // workspace of lane 1
     size_t part_bytes = 0;

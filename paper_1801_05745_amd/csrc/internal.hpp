@@ -43,8 +43,10 @@ inline unsigned blocks_for(int64_t work, int64_t per_block, unsigned cap = 1u <<
 }
 
 // Cross-stream ordering hooks of a partitioned binning call (batched pipelines):
-// the first key pass waits for `wait_keys`, and `done_keys` is recorded after
-// the last one.  Null events are skipped.
+// the first key pass waits for `wait_keys`, and `done_keys` is recorded right
+// after it, so that consecutive realisations on two streams start their key
+// passes one after another and the rest of their work overlaps.  Null events
+// are skipped.
 struct PartHooks {
     hipEvent_t wait_keys = nullptr;
     hipEvent_t done_keys = nullptr;

@@ -262,7 +262,7 @@ __global__ __launch_bounds__(kBinBlock, 6) void keys_kernel(KeyParams kp) {
     const BinParams &p = kp.p;
     __shared__ EdgeLds E;
     __shared__ double qbuf[kBinWaves][3 * kQueue];
-    if (kp.k >= (int)kp.hdr->n_chunks && kp.k != kp.kmax - 1) return;  // uniform: empty chunk
+    if (kp.k >= (int)kp.hdr->n_chunks) return;  // uniform: a chunk the plan left empty
     const int64_t p0 = (int64_t)kp.chunk[kp.k] * kGroup;
     int64_t p1 = (int64_t)kp.chunk[kp.k + 1] * kGroup;
     if (p1 > p.c.n) p1 = p.c.n;
@@ -360,7 +360,7 @@ constexpr int kHistUnroll = 16;
 __global__ __launch_bounds__(kPartThreads) void tile_hist_kernel(PartStep ps, int chunk_k, int kmax) {
     constexpr int kW = kPartThreads / 64;
     __shared__ uint32_t wh[kW][kMaxBins];
-    if (chunk_k >= (int)ps.hdr->n_chunks && chunk_k != kmax - 1) return;
+    if (chunk_k >= (int)ps.hdr->n_chunks) return;
     const int tid = threadIdx.x, w = tid >> 6;
     const int64_t ntiles = step_tiles(ps);
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(kPartThreads) void tile_hist_kernel(PartStep ps, in
 // bucket's keys over the super-tiles of its segment, and the bucket total
 __global__ __launch_bounds__(256) void bucket_scan_kernel(PartStep ps, int chunk_k, int kmax) {
     __shared__ uint32_t wsum[4];
-    if (chunk_k >= (int)ps.hdr->n_chunks && chunk_k != kmax - 1) return;
+    if (chunk_k >= (int)ps.hdr->n_chunks) return;
     const int64_t g = blockIdx.x;
     const int seg = (int)(g / ps.nbins), b = (int)(g % ps.nbins);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(1024) void bucket_base_kernel(const uint32_t *tot, 
     constexpr int kPer = 8;
     constexpr int kW = 1024 / 64;
     __shared__ unsigned long long wh[kW], wt[kW];
-    if (chunk_k >= (int)hdr->n_chunks && chunk_k != kmax - 1) return;
+    if (chunk_k >= (int)hdr->n_chunks) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     unsigned long long carry = 0, carry_t = 0;  // uniform over the workgroup
     for (int64_t s = 0; s < nbkt; s += 1024 * kPer) {
@@ -517,7 +517,7 @@ __global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, i
     __shared__ uint32_t dst[kMaxBins];       // global position of sorted slot 0 of the bucket (mod 2^32)
     __shared__ uint32_t skeys[kSub];
     __shared__ uint32_t wsum[kW];
-    if (chunk_k >= (int)ps.hdr->n_chunks && chunk_k != kmax - 1) return;
+    if (chunk_k >= (int)ps.hdr->n_chunks) return;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int64_t ntiles = step_tiles(ps);
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -601,7 +601,7 @@ __global__ __launch_bounds__(kAccThreads) void accumulate_kernel(const uint16_t 
                                                                  int64_t nblk, int64_t ncells, uint32_t *counts,
                                                                  const PartHeader *hdr, int chunk_k, int kmax) {
     __shared__ uint32_t h[kBlockCells];
-    if (chunk_k >= (int)hdr->n_chunks && chunk_k != kmax - 1) return;
+    if (chunk_k >= (int)hdr->n_chunks) return;
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         const uint32_t lo = offb[blk], hi = offb[blk + 1];
         if (lo == hi) continue;  // uniform over the block
@@ -774,7 +774,7 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
         kp.k = k;
         if (k == 0 && hooks && hooks->wait_keys) UFX_HIP_CHECK(hipStreamWaitEvent(s, hooks->wait_keys, 0));
         hipLaunchKernelGGL((keys_kernel<T>), dim3(key_grid), dim3(kBinBlock), 0, s, kp);
-        if (k == L.kmax - 1 && hooks && hooks->done_keys) UFX_HIP_CHECK(hipEventRecord(hooks->done_keys, s));
+        if (k == 0 && hooks && hooks->done_keys) UFX_HIP_CHECK(hipEventRecord(hooks->done_keys, s));
         timer_mark(timer, UFALCON_PHASE_DECIDE, s);
         // level 1: by key >> s1
         hipLaunchKernelGGL(tile_hist_kernel, dim3(hist_grid), dim3(kPartThreads), 0, s, l1, k, L.kmax);

@@ -1,14 +1,22 @@
-"""GPU parity at the larger workloads' full sizes (the batched draw's largest
-realisation, the nested Nside-2048 lightcone, the covariance batch), where the
-oracle cannot pixelise every instance inside a test: count maps are checked
-bit for bit against the oracle on the first 2^20-2^21 particles (same geometry,
-same launch path), and at full size through properties that hold at any size:
-two independent accumulations agree, streamed chunks compose, the Born sum of
-the full maps equals the oracle's Born sum of the same maps, and gradients match
-the oracle gradient and central differences.
+"""GPU parity at the larger workloads' full sizes, against the oracle binning every
+instance on the host's cores (particles split into contiguous subvolumes
+processed concurrently into one map: section 2.4's decomposition; integer counts
+make the split irrelevant):
+
+  * the batched draw's largest realisation (266M particles, 49 shells over
+    z = 0.1-1.0, Nside 1024, images {-2..2}^3): partitioned and atomic maps;
+  * the nested Nside-2048 lightcone (2 x 768^3 particles, 47 shells), streamed
+    from pinned host memory in 2^28-particle chunks on a copy stream: the whole
+    map, then the four tomographic FP32 kappa maps;
+  * the differentiable covariance batch at its stated size: 150 realisations of
+    256^3 particles bound into one batch plan (forward graph), realisations 0, 1
+    and 149 bit-exact against the oracle, then L = sum_r sum_p kappa_r^2
+    backpropagated to W, Omega_m and z0 against the oracle gradient on the
+    plan's counts and against central differences of the FP64 forward.
 """
 
 import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -25,25 +33,22 @@ DEV = "cuda"
 
 
 def _threads():
-    return max(1, min(16, os.cpu_count() or 1))
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
-def _subset_bit_exact(x, y, z, L, R, edges, nside, m, b0=0, b1=None):
-    xs, ys, zs = (t[:m].contiguous() for t in (x, y, z))
-    got = uf.bin_shells(xs, ys, zs, edges, nside, box_L=L, n_rep=R, shell_begin=b0, shell_end=b1)
-    torch.cuda.synchronize()
-    ref, _ = obin.bin_shells(*(t.cpu().numpy() for t in (xs, ys, zs)), (L / 2,) * 3, L, R, edges, nside,
-                             shell_begin=b0, shell_end=b1, threads=_threads())
-    g = got.cpu().numpy().astype(np.int64)
-    if b1 is not None or b0:
-        g = g[b0:(b1 if b1 is not None else len(edges) - 1)]
-    assert np.array_equal(g, ref)
+def _log(msg):
+    print(f"[largeconfigs] {msg}", flush=True)
 
 
 @pytest.mark.timeout(1200)
-def test_batched_draw_largest_realisation(ufalcon):
+def test_batched_draw_largest_realisation_full_size(ufalcon):
     sizes, shells = config3_draw()
     r = int(np.argmax(sizes))
+    _log(f"config 3 realisation {r}: {sizes[r]} particles, {shells[r]} shells")
     c = config3_realisation(r, device=DEV)
     x, y, z, L, R, edges, nside = c["x"], c["y"], c["z"], c["L"], c["n_rep"], c["edges"], c["nside"]
     assert R == obin.default_n_rep(edges, L)
@@ -51,85 +56,121 @@ def test_batched_draw_largest_realisation(ufalcon):
     part = uf.bin_shells(x, y, z, edges, nside, box_L=L, n_rep=R, status=st_p, method="partition")
     atom = uf.bin_shells(x, y, z, edges, nside, box_L=L, n_rep=R, status=st_a, method="atomic")
     torch.cuda.synchronize()
-    # two accumulations (keys + radix partition + LDS histograms; one atomic per instance)
     assert torch.equal(part, atom)
     sp, sa = uf.status_dict(st_p), uf.status_dict(st_a)
     assert sp["n_instances"] == sa["n_instances"] == int(part.sum(dtype=torch.int64))
-    assert sp["n_unresolved"] == 0 and sp["n_invalid"] == 0
+    assert sp["n_unresolved"] == 0 and sp["n_invalid"] == 0 and sp["n_fallback"] == 0
+    got = part.cpu().numpy()
     del part, atom
-    _subset_bit_exact(x, y, z, L, R, edges, nside, 1 << 21)
+    xh, yh, zh = (t.cpu().numpy() for t in (x, y, z))
+    del x, y, z, c
+    uf.release_workspaces()
+    torch.cuda.empty_cache()
+    _log(f"oracle on {_threads()} threads")
+    ref, rst = obin.bin_shells(xh, yh, zh, (L / 2,) * 3, L, R, edges, nside, threads=_threads())
+    assert rst["instances"] == sp["n_instances"]
+    eq = got.astype(np.int64) == ref
+    assert eq.all(), f"{(~eq).sum()} cells differ"
 
 
 @pytest.mark.timeout(1200)
-def test_nested_lightcone_streamed(ufalcon):
+def test_nested_lightcone_host_streamed_full_size(ufalcon):
     c = config4(device=DEV)
     edges, nside, chunk = c["edges"], c["nside"], c["chunk"]
     B = len(edges) - 1
-    streamed = uf.new_counts(B, nside, DEV)
-    whole = uf.new_counts(B, nside, DEV)
+    feed = []
     for box in c["boxes"]:
         L, b0, b1 = box["L"], box["shell_begin"], box["shell_end"]
-        R = obin.default_n_rep(edges[b0:b1 + 1], L)
-        for k in range(0, box["n"], chunk):
-            sl = slice(k, min(k + chunk, box["n"]))
-            uf.bin_shells(box["x"][sl], box["y"][sl], box["z"][sl], edges, nside, box_L=L, n_rep=R,
-                          shell_begin=b0, shell_end=b1, counts=streamed)
-        uf.bin_shells(box["x"], box["y"], box["z"], edges, nside, box_L=L, n_rep=R, shell_begin=b0,
-                      shell_end=b1, counts=whole)
-        box["R"] = R
+        box["R"] = obin.default_n_rep(edges[b0:b1 + 1], L)
+        host = []
+        for k in ("x", "y", "z"):
+            h = torch.empty(box["n"], dtype=torch.float32, pin_memory=True)
+            h.copy_(box[k])
+            host.append(h)
+        feed.append(dict(x=host[0], y=host[1], z=host[2], box_L=L, n_rep=box["R"], shell_begin=b0, shell_end=b1))
+    _log("config 4: streaming both boxes from pinned host memory")
+    streamed = uf.new_counts(B, nside, DEV)
+    st = uf.new_status(DEV)
+    hs = uf.HostStream(chunk, max(b["R"] for b in c["boxes"]), B, nside, device=DEV)
+    hs.run(feed, edges, nside, streamed, status=st)
     torch.cuda.synchronize()
-    # counts accumulate: chunks of the stream compose into the one-call map
+    assert hs.copy_ms() > 0.0
+    del hs
+    # the same boxes binned in one call each from device memory compose the same map
+    whole = uf.new_counts(B, nside, DEV)
+    for box in c["boxes"]:
+        uf.bin_shells(box["x"], box["y"], box["z"], edges, nside, box_L=box["L"], n_rep=box["R"],
+                      shell_begin=box["shell_begin"], shell_end=box["shell_end"], counts=whole)
+    torch.cuda.synchronize()
     assert torch.equal(streamed, whole)
     del whole
     for box in c["boxes"]:
-        _subset_bit_exact(box["x"], box["y"], box["z"], box["L"], box["R"], edges, nside, 1 << 20,
-                          box["shell_begin"], box["shell_end"])
+        del box["x"], box["y"], box["z"]
+    uf.release_workspaces()
+    torch.cuda.empty_cache()
+    got = streamed.cpu().numpy()
+    s = uf.status_dict(st)
+    assert s["n_unresolved"] == 0 and s["n_fallback"] == 0 and s["n_instances"] == int(got.sum(dtype=np.int64))
 
-    # the four tomographic bins' FP32 kappa of the full maps against the oracle's
-    # Born sum of the same maps (each box's density in its shells)
+    _log(f"oracle on {_threads()} threads")
+    total = 0
+    for box, f in zip(c["boxes"], feed):
+        b0, b1, L = box["shell_begin"], box["shell_end"], box["L"]
+        ref, rst = obin.bin_shells(f["x"].numpy(), f["y"].numpy(), f["z"].numpy(), (L / 2,) * 3, L, box["R"], edges,
+                                   nside, shell_begin=b0, shell_end=b1, threads=_threads())
+        eq = got[b0:b1].astype(np.int64) == ref
+        assert eq.all(), f"box L={L}: {(~eq).sum()} cells differ"
+        total += rst["instances"]
+        del ref
+    assert total == s["n_instances"]
+
+    # four tomographic bins: FP32 kappa of the verified map against the oracle's Born sum
     srcs = [uf.SourceSpec("smail", alpha=2.0, beta=1.5, z0=z0, z_max=1.5) for z0 in c["z0s"]]
     W = uf.lensing_weights(OMEGA_M, srcs, edges, device=DEV)
     inb = torch.cat([uf.inv_nbar(box["n"], box["L"], edges[box["shell_begin"]:box["shell_end"] + 1], nside,
                                  device=DEV) for box in c["boxes"]])
-    kap = uf.born_kappa(streamed, W, inb, out_dtype=torch.float32)
-    torch.cuda.synchronize()
+    kap = uf.born_kappa(streamed, W, inb, out_dtype=torch.float32).cpu().numpy().astype(np.float64)
     Wr = np.array([ocos.lensing_weights(edges, OMEGA_M, ocos.SmailSource(2.0, 1.5, z0, 1.5)) for z0 in c["z0s"]])
     assert np.allclose(W.cpu().numpy(), Wr, rtol=1e-11, atol=0.0)
     nb = np.concatenate([ocos.nbar(box["n"], box["L"], edges[box["shell_begin"]:box["shell_end"] + 1], nside)
                          for box in c["boxes"]])
-    counts_h = streamed.cpu().numpy()
-    del streamed
-    kr = ocos.kappa(counts_h, Wr, nb)
+    kr = ocos.kappa(got, Wr, nb)  # the map verified cell by cell above
     rms = np.sqrt((kr ** 2).mean(axis=1))
-    err = np.abs(kap.cpu().numpy().astype(np.float64) - kr).max(axis=1)
+    err = np.abs(kap - kr).max(axis=1)
     assert (err <= 1e-5 * rms).all(), (err, rms)
 
 
 @pytest.mark.timeout(1200)
-def test_covariance_batch_gradients(ufalcon):
-    # two realisations of the covariance batch at full size: counts through the batched
-    # plan, realisation 0 bit-exact against the oracle; L = sum_r sum_p kappa_r^2 back to
-    # W, Omega_m and z0 against the oracle gradient (on the verified counts) and central
-    # differences of the FP64 forward (step 1e-4)
-    reals = [config5_realisation(r, device=DEV) for r in (0, 1)]
-    edges, nside, L, R = reals[0]["edges"], reals[0]["nside"], reals[0]["L"], reals[0]["n_rep"]
+def test_covariance_batch_150_realisations(ufalcon):
+    n_real = 150
+    _log("config 5: generating 150 realisations")
+    reals = [config5_realisation(r, device=DEV) for r in range(n_real)]
+    edges, nside, L, R, n = reals[0]["edges"], reals[0]["nside"], reals[0]["L"], reals[0]["n_rep"], reals[0]["n"]
     assert R == obin.default_n_rep(edges, L)
     B = len(edges) - 1
-    items = [dict(x=c["x"], y=c["y"], z=c["z"], chi_edges=edges, box_L=L, n_rep=R,
-                  counts=uf.new_counts(B, nside, DEV)) for c in reals]
-    plan = uf.BatchPlan(items, nside, T=0)
-    plan.clear()
-    plan.bin()
-    torch.cuda.synchronize()
-    plan.close()
-    ref0, _ = obin.bin_shells(*(reals[0][k].cpu().numpy() for k in ("x", "y", "z")), (L / 2,) * 3, L, R, edges,
-                              nside, threads=_threads())
-    assert np.array_equal(items[0]["counts"].cpu().numpy().astype(np.int64), ref0)
-
-    n = reals[0]["n"]
     inb = uf.inv_nbar(n, L, edges, nside, device=DEV)
     base = uf.SourceSpec("smail", alpha=2.0, beta=1.5, z0=0.3, z_max=1.5)
+    W0 = uf.lensing_weights(OMEGA_M, [base], edges, device=DEV)
+    items = [dict(x=c["x"], y=c["y"], z=c["z"], chi_edges=edges, box_L=L, n_rep=R,
+                  counts=torch.empty((B, uf.npix(nside)), dtype=torch.uint32, device=DEV), W=W0, inv_nbar=inb,
+                  kappa=torch.empty((1, uf.npix(nside)), dtype=torch.float32, device=DEV)) for c in reals]
+    plan = uf.BatchPlan(items, nside, T=1)
+    st = uf.new_status(DEV)
+    plan.run_graph(st)                                   # forward: clear + bin + Born of all 150
+    torch.cuda.synchronize()
+    plan.close()
+    s = uf.status_dict(st)
+    assert s["n_unresolved"] == 0 and s["n_fallback"] == 0
 
+    _log("oracle: realisations 0, 1 and 149 at full size")
+    for r in (0, 1, n_real - 1):
+        ref, rst = obin.bin_shells(*(reals[r][k].cpu().numpy() for k in ("x", "y", "z")), (L / 2,) * 3, L, R, edges,
+                                   nside, threads=_threads())
+        assert np.array_equal(items[r]["counts"].cpu().numpy().astype(np.int64), ref), f"realisation {r}"
+    for c in reals:
+        del c["x"], c["y"], c["z"]
+
+    # backward of L = sum_r sum_p kappa_r^2 through the autograd functions
     def loss(om, params, out_dtype):
         W = uf.LensingWeights.apply(om, params, [base], edges, DEV)
         tot = 0.0
@@ -144,15 +185,23 @@ def test_covariance_batch_gradients(ufalcon):
     W.retain_grad()
     Lv.backward()
     g_om, g_z0 = om.grad.item(), params.grad[0, 2].item()
+    # the plan's batched Born pass gives the same FP32 maps as the single-map calls
+    with torch.no_grad():
+        for r in (0, n_real - 1):
+            assert torch.equal(items[r]["kappa"], uf.born_kappa(items[r]["counts"], W.detach(), inb))
 
+    _log("oracle gradient over the 150 count maps")
     osrc = ocos.SmailSource(2.0, 1.5, 0.3, 1.5)
     Wr = ocos.lensing_weights(edges, OMEGA_M, osrc)
     nb = ocos.nbar(n, L, edges, nside)
-    gW_ref = np.zeros(B)
-    for it in items:
-        ch = it["counts"].cpu().numpy().astype(np.int64)
+
+    def grad_of(it):
+        ch = it["counts"].cpu().numpy()
         kr = ocos.kappa(ch, Wr[None, :], nb)
-        gW_ref += ocos.grad_W(ch, nb, 2.0 * kr)[0]
+        return ocos.grad_W(ch, nb, 2.0 * kr, summation="pairwise")[0]
+
+    with ThreadPoolExecutor(max_workers=_threads()) as ex:
+        gW_ref = np.sum(list(ex.map(grad_of, items)), axis=0)
     assert np.linalg.norm(W.grad.cpu().numpy()[0] - gW_ref) <= 1e-4 * np.linalg.norm(gW_ref)
     ref_om = float(gW_ref @ ocos.weight_derivative(edges, OMEGA_M, osrc, "omega_m"))
     ref_z0 = float(gW_ref @ ocos.weight_derivative(edges, OMEGA_M, osrc, "z0"))

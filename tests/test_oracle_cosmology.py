@@ -315,3 +315,14 @@ def test_overdensity_single_particle_closed_form():
     want5 = 3.0 * L ** 3 / (math.pi * N * chi[1] ** 2 * (chi[3] - chi[0])) - 1.0
     assert got[5] == pytest.approx(want5, rel=1e-14)
     assert np.all(np.delete(got, 5) == -1.0)
+
+
+def test_adjoint_pairwise_summation_matches_exact():
+    rng = np.random.default_rng(3)
+    counts = rng.integers(0, 50, size=(3, 200000))
+    nb = np.array([4.0, 11.0, 23.0])
+    g = rng.normal(size=(2, 200000))
+    ex = co.grad_W(counts, nb, g)
+    pw = co.grad_W(counts, nb, g, summation="pairwise")
+    scale = np.abs(g).sum() * 50.0 / nb.min()
+    assert np.abs(pw - ex).max() <= 1e-13 * scale
