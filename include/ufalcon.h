@@ -125,6 +125,29 @@ int ufalcon_bin_shells(const void *x, const void *y, const void *z, int64_t n, i
                        void *workspace, size_t workspace_bytes, ufalcon_stream_t stream);
 
 /*
+ * Binning without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and results as ufalcon_bin_shells minus
+ * the workspace; counts are accumulated by one global atomic per instance (the
+ * path ufalcon_bin_shells takes with a small workspace).  Its scratch memory
+ * (a 256-byte guard-list header and up to UFALCON_NOALLOC_GUARD_ENTRIES listed
+ * guarded instances of 32 bytes: 2 MiB + 256 bytes) is a
+ * file-scope device array that every GPU the library runs on holds until the
+ * process ends; no input size needs more (instances beyond the list's capacity
+ * are decided by the rescue pass).  The first call on a device looks the array
+ * up (hipGetSymbolAddress); no call allocates or frees memory.  All calls on
+ * one GPU share that GPU's array: calls that overlap in time on one GPU (on
+ * different streams, or from different threads) race and must be serialised
+ * by the caller.  Errors: those of ufalcon_bin_shells except EWORKSPACE; EHIP
+ * also when the array's address cannot be obtained.
+ */
+#define UFALCON_NOALLOC_GUARD_ENTRIES 65536
+int ufalcon_bin_shells_noalloc(const void *x, const void *y, const void *z, int64_t n, int dtype,
+                               const double *observer, double box_L, int32_t n_rep,
+                               const double *chi_edges, int32_t n_shells, int32_t shell_begin, int32_t shell_end,
+                               int64_t nside, uint32_t *counts, ufalcon_status *status, ufalcon_stream_t stream);
+
+/*
  * Phase timing of a binning call (diagnostics: results do not depend on it).
  * A timer owns HIP events created on the device current at
  * ufalcon_phase_timer_create.  ufalcon_bin_shells_timed takes the same

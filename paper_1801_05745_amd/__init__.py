@@ -78,6 +78,8 @@ _SIGS = {
     "ufalcon_bin_shells_timed": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, ctypes.POINTER(_D), _D, _I32,
                                                 ctypes.POINTER(_D), _I32, _I32, _I32, _I64, _P, _P, _P, _SZ, _P,
                                                 _P]),
+    "ufalcon_bin_shells_noalloc": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, ctypes.POINTER(_D), _D, _I32,
+                                                  ctypes.POINTER(_D), _I32, _I32, _I32, _I64, _P, _P, _P]),
     "ufalcon_phase_timer_create": (ctypes.c_int, [ctypes.POINTER(_P)]),
     "ufalcon_phase_timer_destroy": (ctypes.c_int, [_P]),
     "ufalcon_phase_timer_read": (ctypes.c_int, [_P, ctypes.POINTER(_D)]),
@@ -328,6 +330,34 @@ def bin_shells(x, y, z, chi_edges, nside, observer=None, box_L=0.0, n_rep=0, she
         _check(lib.ufalcon_bin_shells(*args), "ufalcon_bin_shells")
     else:
         _check(lib.ufalcon_bin_shells_timed(*args, timer.handle), "ufalcon_bin_shells_timed")
+    return counts
+
+
+def bin_shells_noalloc(x, y, z, chi_edges, nside, observer=None, box_L=0.0, n_rep=0, shell_begin=0,
+                       shell_end=None, counts=None, status=None):
+    """bin_shells through the allocation-free entry point (atomic accumulation, library-held
+    scratch).  `counts` must be given (the call itself allocates nothing)."""
+    lib = load()
+    if counts is None:
+        raise ValueError("bin_shells_noalloc needs a caller-allocated counts tensor")
+    if not (x.dtype == y.dtype == z.dtype) or not (x.numel() == y.numel() == z.numel()):
+        raise ValueError("x, y, z must share dtype and length")
+    for t in (x, y, z):
+        if not (t.is_cuda and t.is_contiguous()):
+            raise ValueError("positions must be contiguous device tensors")
+    e, ne = _host_doubles(chi_edges)
+    n_shells = ne - 1
+    if shell_end is None:
+        shell_end = n_shells
+    if observer is None:
+        observer = (0.5 * box_L,) * 3
+    obs, _ = _host_doubles(observer)
+    if counts.dtype != torch.uint32 or not counts.is_contiguous() or counts.numel() != n_shells * npix(nside):
+        raise ValueError("counts must be contiguous uint32 [n_shells][12 nside^2]")
+    _check(lib.ufalcon_bin_shells_noalloc(_ptr(x), _ptr(y), _ptr(z), x.numel(), _dtype_code(x.dtype), obs,
+                                          float(box_L), int(n_rep), e, n_shells, int(shell_begin), int(shell_end),
+                                          int(nside), _ptr(counts), _ptr(status), _stream(x.device)),
+           "ufalcon_bin_shells_noalloc")
     return counts
 
 

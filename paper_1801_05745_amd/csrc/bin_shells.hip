@@ -379,6 +379,63 @@ extern "C" int ufalcon_bin_shells_timed(const void *x, const void *y, const void
                             nside, counts, status, workspace, workspace_bytes, stream, timer);
 }
 
+// ------------------------------------------------------------------ allocation-free binning
+// The workspace of the atomic accumulation path (guard-list header + listed
+// guarded instances) kept in a file-scope device array instead of a caller
+// buffer.  Each GPU holds its own copy for the life of the process; host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device (the array's name is not a device address on the host).
+constexpr size_t kScratchBytes = kGuardHeader + (size_t)UFALCON_NOALLOC_GUARD_ENTRIES * sizeof(GuardEntry);
+static_assert(kScratchBytes % 256 == 0, "scratch keeps the workspace's 256-byte granularity");
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kScratchMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchMaxDevices] = {};
+
+// Device address of this device's scratch array, looked up on the first call
+// with the device current and kept per device.
+int scratch_for_current_device(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchMaxDevices) return UFALCON_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return UFALCON_EHIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return UFALCON_OK;
+}
+}  // namespace
+
+extern "C" int ufalcon_bin_shells_noalloc(const void *x, const void *y, const void *z, int64_t n, int dtype,
+                                          const double *observer, double box_L, int32_t n_rep,
+                                          const double *chi_edges, int32_t n_shells, int32_t shell_begin,
+                                          int32_t shell_end, int64_t nside, uint32_t *counts,
+                                          ufalcon_status *status, ufalcon_stream_t stream) {
+    if (dtype != UFALCON_F32 && dtype != UFALCON_F64) return UFALCON_EINVAL;
+    BinParams p;
+    int rc = fill_core(p.c, p.e, x, y, z, n, observer, box_L, n_rep, chi_edges, n_shells, shell_begin, shell_end,
+                       nside, counts);
+    if (rc) return rc;
+    void *ws = nullptr;
+    if ((rc = scratch_for_current_device(&ws))) return rc;
+    p.nside = nside;
+    p.npix = npix_of(nside);
+    p.eps = floor_margin((double)nside);
+    p.status = status;
+    p.guard = static_cast<GuardList *>(ws);
+    p.guard_cap = UFALCON_NOALLOC_GUARD_ENTRIES;
+    if (p.c.n == 0 || p.c.nb == 0) return UFALCON_OK;
+    // the guard list is reset by a kernel at the start of the call; more guarded
+    // instances than it holds are decided by the rescue pass, so no input size
+    // needs more scratch than this
+    hipStream_t s = as_stream(stream);
+    return dtype == UFALCON_F32 ? launch_bin_t<float>(p, s, nullptr) : launch_bin_t<double>(p, s, nullptr);
+}
+
 // ------------------------------------------------------------------ batch plan
 namespace ufx {
 struct BornItemDev {
