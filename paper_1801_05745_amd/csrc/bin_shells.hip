@@ -250,7 +250,7 @@ int fill_core(BinCore &c, double *e_out, const void *x, const void *y, const voi
     double e2[UFALCON_MAX_SHELLS + 1];
     for (int j = 0; j <= c.nb; ++j) e2[j] = e_out[j] * e_out[j];
     c.tab_n = shell_table_cells(e2, c.nb, c.lo2, c.hi2);
-    c.pad = 0;
+    c.key32 = (int64_t)c.nb * npix_of(nside) < (int64_t)0xFFFFFFFF ? 1 : 0;
     c.tab_lo = c.lo2;
     c.tab_h = c.tab_n ? (c.hi2 - c.lo2) / c.tab_n : 0.0;
     c.tab_scale = c.tab_n ? c.tab_n / (c.hi2 - c.lo2) : 0.0;

@@ -4,7 +4,8 @@
 // whose squared radius falls in the (guard-widened) shell range in LDS, and
 // whenever 64 are queued every lane takes one and decides its shell and RING
 // pixel in FP64 (ring.hpp).  What happens to a decided instance depends on the mode:
-//   kAtomic  add 1 to its count cell with a global atomic;
+//   kAtomic  add 1 to its count cell with a global atomic (equal keys of the
+//            wave's batch aggregated into one atomic when the keys fit 32 bits);
 //   kEmit    emit its key b * npix + pix into a key buffer (partitioned
 //            accumulation: the keys are grouped by cell block later and counted
 //            in LDS, see partition.hip);
@@ -64,7 +65,7 @@ struct BinCore {
     int32_t item;         // realisation index (batched) or 0
     uint32_t *counts;     // row of the first shell in range
     int32_t tab_n;        // cells of the shell lookup table (0: binary search)
-    int32_t pad;
+    int32_t key32;        // the range's cells fit 32-bit keys (atomic accumulation aggregates equal keys)
     double tab_lo, tab_h, tab_scale;  // table over r^2 from tab_lo, cell width tab_h = 1 / tab_scale
 };
 
@@ -95,7 +96,8 @@ __device__ inline void load_edges(EdgeLds &E, const BinCore &c, const double *e)
     if (threadIdx.x < kTtTerms) E.ttc[threadIdx.x] = kTtCoef[threadIdx.x];
     __syncthreads();
     for (int t = threadIdx.x; t < c.tab_n; t += blockDim.x)
-        E.tab[t] = (int16_t)shell_of_r2(E.e2(), c.nb, c.steps, c.tab_lo + (double)t * c.tab_h);
+        E.tab[t] = shell_table_entry(E.e2(), c.nb, c.steps, c.tab_lo + (double)t * c.tab_h,
+                                     t + 1 < c.tab_n ? c.tab_lo + (double)(t + 1) * c.tab_h : c.hi2);
     __syncthreads();
 }
 
@@ -170,6 +172,15 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
     return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
+// The first active lane's 64-bit value in every lane (scalar registers).  The
+// halves go through readfirstlane, whose int result is zero-extended back:
+// sign-extending it would corrupt values with bit 31 or bit 63 set.
+__device__ __forceinline__ unsigned long long wave_first_u64(unsigned long long v) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return ((unsigned long long)hi << 32) | (unsigned long long)lo;
+}
+
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -199,14 +210,14 @@ __device__ __forceinline__ uint32_t bin_instance(const BinCore &c, const Shared 
         int32_t pix;
         // the range test costs two compares and keeps any logic slip from writing out of bounds
         if (fast_ring_pixel_region<kBelt>((int32_t)sh.nside, Nd, sh.eps, dx, dy, dz, pix, E.ttc + opaque_zero()) &&
-            pix >= 0 && pix < sh.npix) {
+            (uint32_t)pix < (uint32_t)sh.npix) {  // npix < 2^31 for nside <= 8192
             if (kMode == kRescue) return kNoKey;
             ++st.inst;
-            if (kMode == kAtomic) {
+            if (kMode == kAtomic && !c.key32) {
                 atomicAdd(c.counts + (int64_t)j * sh.npix + pix, 1u);
                 return kNoKey;
             }
-            return (uint32_t)j * (uint32_t)sh.npix + (uint32_t)pix;  // < 2^32: the host checks B * npix
+            return (uint32_t)j * (uint32_t)sh.npix + (uint32_t)pix;  // < 2^32: key32, or the host checks B * npix
         }
     }
     if (kMode == kRescue) {
@@ -247,7 +258,8 @@ __device__ __forceinline__ void emit_keys(Emitter &em, const BinCore &c, uint32_
     const int rank = lanes_below(m);
     const int room = kKeyChunk - em.fill;
     if (has && rank < room) {
-        em.keys[em.base + em.fill + rank] = key;
+        uint32_t *dst = em.keys + (em.base + (unsigned long long)em.fill);  // uniform: one scalar base per wave
+        dst[rank] = key;
         if (em.hist) atomicAdd(&em.hist[key >> em.shift], 1u);
     }
     if (n <= room) {
@@ -257,7 +269,7 @@ __device__ __forceinline__ void emit_keys(Emitter &em, const BinCore &c, uint32_
     // the current chunk is full: reserve the next one
     unsigned long long b = 0;
     if (lane == 0) b = atomicAdd(em.reserved, (unsigned long long)kKeyChunk);
-    b = __shfl(b, 0, 64);
+    b = wave_first_u64(b);  // lane 0's reservation (every lane is active here)
     if (b + kKeyChunk > em.cap) {
         // chunk-aligned capacity: this reservation lies wholly outside the buffer
         em.full = true;
@@ -276,6 +288,35 @@ __device__ __forceinline__ void emit_keys(Emitter &em, const BinCore &c, uint32_
     em.fill = n - room;
 }
 
+// Atomic accumulation with equal keys aggregated over the wave: the 64 keys
+// (kNoKey for lanes without an instance) are sorted across the lanes (bitonic
+// network over lane-index bits), and the first lane of every run of equal keys
+// adds the run's length with one atomic.  Must be reached by all 64 lanes.
+__device__ __forceinline__ void aggregate_add(uint32_t *counts, uint32_t key) {
+    const int lane = threadIdx.x & 63;
+    if (wave_ballot(key != kNoKey) == 0ull) return;  // uniform
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t other = __shfl_xor(key, j, 64);
+            const bool ascending = (lane & k) == 0;
+            const bool lower = (lane & j) == 0;
+            key = (lower == ascending) ? min(key, other) : max(key, other);
+        }
+    }
+    const uint32_t prev = __shfl_up(key, 1, 64);
+    const bool valid = key != kNoKey;
+    const bool head = valid && (lane == 0 || prev != key);
+    // a run ends at the next head or at the first lane without a key (kNoKey sorts last)
+    const unsigned long long stops = wave_ballot(head) | ~wave_ballot(valid);
+    if (head) {
+        const unsigned long long above = lane == 63 ? 0ull : (stops >> (lane + 1)) << (lane + 1);
+        const int next = above ? __builtin_ctzll(above) : 64;
+        atomicAdd(counts + key, (uint32_t)(next - lane));
+    }
+}
+
 // Pad the unused tail of the wave's current chunk with sentinels.
 __device__ __forceinline__ void close_emitter(Emitter &em) {
     if (em.full || em.fill >= kKeyChunk) return;
@@ -290,45 +331,39 @@ struct WaveQueue {
     int nc;     // cap entries in slots [kQueue - nc, kQueue)
 };
 
-// Take the 64 entries at one end of the queue, shift the rest of that end into
-// place, and decide the taken images (one per lane).  All 64 lanes call it.
+// Take the 64 most recently queued entries at one end of the queue (the top 64 of
+// the belt end, the bottom 64 of the cap end; no entry moves) and decide them,
+// one per lane.  All 64 lanes call it.
 template <int kMode, bool kBelt>
 __device__ __forceinline__ void take_batch(const BinCore &c, const Shared &sh, const EdgeLds &E, double Nd,
                                            WaveQueue &q, LaneStats &st, Emitter &em) {
     const int lane = threadIdx.x & 63;
-    const int rest = (kBelt ? q.nb : q.nc) - 64;
-    const int take = kBelt ? lane : kQueue - 64 + lane;
-    const int from = kBelt ? 64 + lane : kQueue - 64 - rest + lane;
-    const int to = kBelt ? lane : kQueue - rest + lane;
+    const int take = kBelt ? q.nb - 64 + lane : kQueue - q.nc + lane;
     wave_lds_sync();
     const double ax = q.q[take], ay = q.q[kQueue + take], az = q.q[2 * kQueue + take];
-    double rx = 0.0, ry = 0.0, rz = 0.0;
-    if (lane < rest) {
-        rx = q.q[from];
-        ry = q.q[kQueue + from];
-        rz = q.q[2 * kQueue + from];
-    }
-    wave_lds_sync();
-    if (lane < rest) {
-        q.q[to] = rx;
-        q.q[kQueue + to] = ry;
-        q.q[2 * kQueue + to] = rz;
-    }
     if (kBelt)
-        q.nb = rest;
+        q.nb -= 64;
     else
-        q.nc = rest;
+        q.nc -= 64;
     const uint32_t key = bin_instance<kMode, kBelt>(c, sh, E, Nd, ax, ay, az, st);
     if (kMode == kEmit) emit_keys(em, c, key, st);
+    if (kMode == kAtomic) aggregate_add(c.counts, key);
 }
+
+// Never stop early (the plain passes).
+struct NoStop {
+    __device__ bool operator()() const { return false; }
+};
 
 // Per-wave core: this wave handles particles base, base + stride, ... (64 at a
 // time) below `end`; queued images persist in `q` across calls and are drained
-// by drain_queue().
-template <typename T, int kMode>
-__device__ __forceinline__ void bin_wave_range(const BinCore &c, const Shared &sh, const EdgeLds &E,
-                                               int64_t base, int64_t end, int64_t stride, WaveQueue &q,
-                                               LaneStats &st, Emitter &em) {
+// by drain_queue().  `stop` is asked before every batch of 64 particles after
+// the first; the return value is the base of the first batch not processed
+// (>= end when the range is done).
+template <typename T, int kMode, typename Stop = NoStop>
+__device__ __forceinline__ int64_t bin_wave_range(const BinCore &c, const Shared &sh, const EdgeLds &E,
+                                                  int64_t base, int64_t end, int64_t stride, WaveQueue &q,
+                                                  LaneStats &st, Emitter &em, Stop stop = Stop{}) {
     const int lane = threadIdx.x & 63;
     const T *X = static_cast<const T *>(c.x);
     const T *Y = static_cast<const T *>(c.y);
@@ -342,7 +377,8 @@ __device__ __forceinline__ void bin_wave_range(const BinCore &c, const Shared &s
         py = Y[base + lane];
         pz = Z[base + lane];
     }
-    for (; base < end; base += stride) {
+    for (bool first = true; base < end; base += stride, first = false) {
+        if (!first && stop()) break;  // uniform
         const int64_t i = base + lane;
         const double x = (double)px, y = (double)py, z = (double)pz;
         const int64_t inext = base + stride + lane;
@@ -396,6 +432,7 @@ __device__ __forceinline__ void bin_wave_range(const BinCore &c, const Shared &s
         // past 2^30 keeps the 32-bit counts exact
         if (__ballot(st.inst >= (1u << 30)) != 0ull) flush_stats(sh.status, st);
     }
+    return base;
 }
 
 // Decide what is left in the queue (fewer than 64 at each end).
@@ -409,10 +446,12 @@ __device__ __forceinline__ void drain_queue(const BinCore &c, const Shared &sh, 
     if (lane < q.nb)
         key = bin_instance<kMode, true>(c, sh, E, Nd, q.q[lane], q.q[kQueue + lane], q.q[2 * kQueue + lane], st);
     if (kMode == kEmit) emit_keys(em, c, key, st);
+    if (kMode == kAtomic) aggregate_add(c.counts, key);
     key = kNoKey;
     const int t = kQueue - 1 - lane;
     if (lane < q.nc) key = bin_instance<kMode, false>(c, sh, E, Nd, q.q[t], q.q[kQueue + t], q.q[2 * kQueue + t], st);
     if (kMode == kEmit) emit_keys(em, c, key, st);
+    if (kMode == kAtomic) aggregate_add(c.counts, key);
     wave_lds_sync();
     q.nb = 0;
     q.nc = 0;

@@ -4,10 +4,11 @@
 // Random 32-bit atomics into a GB-sized map run at a fixed ceiling on this GPU
 // (about 2e10 per second), far below what the FP64 pixelisation delivers, so
 // this path never updates the map once per instance.  Instead:
-//   0. plan: when every image of the set fits the key buffer, one chunk;
-//      otherwise count, per group of particles, an upper bound on its in-range
-//      images (squared radius only) and split the particles into chunks whose
-//      keys fit the workspace (on the device, no host synchronisation);
+//   0. chunks: every wave of the key pass walks its own grid-stride sequence of
+//      64-particle batches and stops before a batch once the key buffer could
+//      not take the keys of one batch of every wave; it saves its position, and
+//      the next chunk resumes there; the last chunk finishes every sequence
+//      (no host synchronisation, no counting pass, no shared claim counter);
 //   per chunk:
 //   1. keys: the binning core emits key = b * npix + pix per instance into a
 //      buffer (waves reserve 4096-slot chunks with one global atomic each);
@@ -33,14 +34,14 @@ constexpr int kBlockCells = 1 << kBlockShift;
 constexpr int kSuper = 32768;                    // keys per partition super-tile
 constexpr int kPartThreads = 256;
 constexpr int kMaxBins = 512;                    // buckets per partition level
-constexpr int kGroup = 8192;                     // particles per counting group
+constexpr int kKeyWavesMax = 16 * kBinWaves;      // key-pass waves per compute unit, at most (per-wave state)
 constexpr int kAccThreads = 512;
 constexpr int kAccUnroll = 16;
 
 struct PartHeader {
     unsigned long long reserved;  // key slots reserved by the key pass of the current chunk
-    unsigned int n_chunks;        // chunks the plan produced
-    unsigned int pad0;
+    unsigned int active;          // some wave has batches left: the current chunk runs
+    unsigned int unfinished;      // waves that stopped on the margin in the current chunk
     unsigned long long pad[30];
 };
 static_assert(sizeof(PartHeader) == 256, "partition header is 256 bytes");
@@ -49,20 +50,36 @@ struct PartLayout {
     int s1;                 // level-1 shift
     int nb1, nb2;           // buckets per level
     int64_t nblk;           // cell blocks (nb1 * nb2 slots allocated)
-    int64_t ngroups;        // particle groups
     int kmax;               // chunk iterations launched
     unsigned long long cap; // key slots per buffer (multiple of kKeyChunk)
-    unsigned long long budget;  // planned keys per chunk
+    unsigned long long margin;  // room a wave needs before it claims: every wave's worst-case claim
+    unsigned long long budget;  // keys every chunk but the last processes, at least
     int64_t hist_rows;      // super-tile rows of the per-tile histogram
-    size_t off_guard, off_hdr, off_off1, off_tiles1, off_offb, off_tot, off_thist, off_grp, off_chunk, off_keysa,
-        off_keysb, total;
+    size_t off_guard, off_hdr, off_wave, off_off1, off_tiles1, off_offb, off_tot, off_thist, off_keysa, off_keysb,
+        total;
 };
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 constexpr int64_t kPartGuardEntries = 65536;
 
-// Layout for a call; cap_slots = 0 means "as many as the bytes allow".
+// Key slots a chunk keeps free: before each batch a wave checks that the slots
+// reserved (as of its latest reservation) leave room for one batch of every
+// wave (64 particles times the image bound, plus the up to kQueue queued images
+// carried between batches, rounded up to whole reservations) and one more
+// reservation; slack: one partly filled 4096-slot reservation per wave.  The
+// key pass launches one resident round, so its waves are bounded by the
+// workgroups per compute unit that the key kernels' occupancy allows.
+static int key_wgs_per_cu();
+
+static void claim_reserve(int64_t n, int img_bound, unsigned long long &margin, unsigned long long &slack) {
+    const int64_t wgs = std::min<int64_t>((n + kBinBlock - 1) / kBinBlock, (int64_t)device_cus() * key_wgs_per_cu());
+    const unsigned long long waves = (unsigned long long)std::max<int64_t>(wgs, 1) * kBinWaves;
+    margin = waves * (64ull * (unsigned long long)img_bound + kQueue + kKeyChunk) + kKeyChunk;
+    slack = waves * (unsigned long long)kKeyChunk;
+}
+
+// Layout for a call; want_keys = 0 means "as many as the bytes allow".
 static bool plan_layout(PartLayout &L, int64_t n, int64_t ncells, int img_bound, size_t bytes, int64_t want_keys) {
     if (ncells <= 0 || ncells >= (int64_t)kNoKey) return false;
     int bits = 0;
@@ -75,24 +92,23 @@ static bool plan_layout(PartLayout &L, int64_t n, int64_t ncells, int img_bound,
     L.nb2 = 1 << b2;
     L.nb1 = (int)((ncells + ((int64_t)1 << L.s1) - 1) >> L.s1);
     L.nblk = (int64_t)L.nb1 * L.nb2;
-    L.ngroups = (n + kGroup - 1) / kGroup;
     size_t o = 0;
     L.off_guard = o; o = align256(o + kGuardHeader + kPartGuardEntries * sizeof(GuardEntry));
     L.off_hdr = o; o = align256(o + sizeof(PartHeader));
+    L.off_wave = o; o = align256(o + sizeof(int64_t) * (size_t)device_cus() * kKeyWavesMax);
     L.off_off1 = o; o = align256(o + sizeof(uint32_t) * (L.nb1 + 1));
     L.off_tiles1 = o; o = align256(o + sizeof(uint32_t) * (L.nb1 + 1));
     L.off_offb = o; o = align256(o + sizeof(uint32_t) * (L.nblk + 1));
     L.off_tot = o; o = align256(o + sizeof(uint32_t) * std::max<int64_t>(L.nb1, L.nblk));
-    L.off_grp = o; o = align256(o + sizeof(uint32_t) * L.ngroups);
-    const int kmax_cap = 4096;
-    L.off_chunk = o; o = align256(o + sizeof(uint32_t) * (kmax_cap + 1));
     const size_t fixed_head = o;
-    // slack: every wave of the key pass may leave up to one partly filled chunk
-    const unsigned long long slack = (unsigned long long)kKeyChunk * (unsigned long long)device_cus() * 16ull * kBinWaves;
+    unsigned long long margin, slack;
+    claim_reserve(n, img_bound, margin, slack);
     const int wide = std::max(L.nb1, L.nb2);
     unsigned long long cap;
     if (want_keys > 0) {
-        cap = (unsigned long long)want_keys + slack + kKeyChunk;
+        // two reservations of headroom: a layout re-derived from this one's byte count
+        // (a plan's shared workspace) rounds its capacity down by up to one
+        cap = std::max((unsigned long long)want_keys + margin + slack, 2 * (margin + slack)) + 3 * kKeyChunk;
     } else {
         // bytes = head + per-tile histogram (~ cap/kSuper rows) + two key buffers
         const double per_key = 2.0 * sizeof(uint32_t) + (double)wide * sizeof(uint32_t) / kSuper;
@@ -100,25 +116,30 @@ static bool plan_layout(PartLayout &L, int64_t n, int64_t ncells, int img_bound,
         if (bytes < fixed_head + extra) return false;
         cap = (unsigned long long)((double)(bytes - fixed_head - extra) / per_key);
     }
+    if (want_keys > 0) cap = (cap + kKeyChunk - 1) / kKeyChunk * kKeyChunk;  // whole reservations
     if (cap > 0xFFF00000ull) cap = 0xFFF00000ull;  // offsets are 32-bit
     cap = cap / kKeyChunk * kKeyChunk;
-    const unsigned long long gmax = (unsigned long long)kGroup * (unsigned long long)img_bound;
-    if (cap < slack + 4 * gmax) return false;
+    // every chunk but the last must keep at least half of the buffer
+    if (cap < 2 * (margin + slack) + kKeyChunk) return false;
     L.hist_rows = (int64_t)(cap / kSuper) + L.nb1 + 2;
     L.off_thist = o; o = align256(o + sizeof(uint32_t) * (size_t)wide * L.hist_rows);
     const size_t fixed = o;
     L.cap = cap;
-    // a chunk's planned bound can pass the budget by up to one group's bound
-    // (the plan cuts at group boundaries), and every wave may leave one partly
-    // filled reservation: both fit below cap
-    L.budget = cap - slack - gmax;
+    L.margin = margin;
+    L.budget = cap - margin - slack;
     L.off_keysa = fixed;
     L.off_keysb = align256(fixed + sizeof(uint32_t) * cap);
     L.total = align256(L.off_keysb + sizeof(uint32_t) * cap);
+    // keys the set can produce at most; a chunk that stops on the margin has
+    // processed at least `budget` of them, and the last chunk takes the rest
     const double est = (double)n * (double)img_bound;
-    double k = std::ceil(est / (double)L.budget);
-    if (k < 1.0) k = 1.0;
-    L.kmax = (int)std::min<double>(k, (double)kmax_cap);
+    const int kmax_cap = 4096;
+    if (est + (double)slack <= (double)cap) {
+        L.kmax = 1;
+    } else {
+        const double k = std::ceil(est / (double)L.budget) + 1.0;
+        L.kmax = (int)std::min<double>(k, (double)kmax_cap);
+    }
     return true;
 }
 
@@ -147,114 +168,31 @@ static int image_bound(const BinCore &c, const double *e, int nb) {
 
 // ------------------------------------------------------------------ kernels
 
-// 0a. upper bound of in-range images per group of kGroup particles.  Per
-// particle and image column (sx, sy), the images sz in [-R, R] with
-// lo2 <= rho^2 + dz^2 < hi2 are counted in closed form: dz = bz + sz L must
-// satisfy |dz| < h = sqrt(hi2 - rho^2) and, when rho^2 < lo2, not |dz| < g =
-// sqrt(lo2 - rho^2).  h is widened and g narrowed by a relative 1e-6 (plus
-// 1e-9 L), so rounding can only add images to the count: it bounds the keys
-// the key pass emits, which is all the chunk plan needs.
-__device__ __forceinline__ int count_in_slab(double bz, double half, double invL, int R) {
-    // integers s in [-R, R] with -half <= bz + s L <= half
-    if (R == 0) return fabs(bz) <= half ? 1 : 0;
-    const double lo = ceil((-half - bz) * invL), hi = floor((half - bz) * invL);
-    const double a = fmax(lo, (double)-R), b = fmin(hi, (double)R);
-    return b >= a ? (int)(b - a) + 1 : 0;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void count_groups_kernel(BinCore c, uint32_t *grp) {
-    __shared__ unsigned int red[4];
-    const T *X = static_cast<const T *>(c.x);
-    const T *Y = static_cast<const T *>(c.y);
-    const T *Z = static_cast<const T *>(c.z);
-    const int64_t g = blockIdx.x;
-    const int64_t beg = g * kGroup;
-    const int64_t end = beg + kGroup < c.n ? beg + kGroup : c.n;
-    const double invL = c.R > 0 ? 1.0 / c.L : 0.0;
-    const double pad = 1e-9 * c.L;
-    unsigned int cnt = 0;
-    for (int64_t i = beg + threadIdx.x; i < end; i += 256) {
-        const double x = (double)X[i], y = (double)Y[i], z = (double)Z[i];
-        if (!(isfinite(x) && isfinite(y) && isfinite(z))) continue;
-        const double bx = x - c.ox, by = y - c.oy, bz = z - c.oz;
-        for (int sx = -c.R; sx <= c.R; ++sx) {
-            const double dx = bx + (double)sx * c.L;
-            for (int sy = -c.R; sy <= c.R; ++sy) {
-                const double dy = by + (double)sy * c.L;
-                const double rho2 = dx * dx + dy * dy;
-                if (rho2 >= c.hi2 * (1.0 + 1e-6)) continue;
-                const double h = sqrt(fmax(c.hi2 - rho2, 0.0)) * (1.0 + 1e-6) + pad;
-                int k = count_in_slab(bz, h, invL, c.R);
-                if (rho2 < c.lo2) {
-                    const double gg = sqrt(c.lo2 - rho2) * (1.0 - 1e-6) - pad;
-                    // strictly inside the inner sphere: |dz| < gg, counted as the closed slab
-                    // of half-width gg shrunk once more by pad
-                    if (gg > pad) k -= count_in_slab(bz, gg - pad, invL, c.R);
-                }
-                cnt += (unsigned)k;
-            }
-        }
-    }
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) grp[g] = red[0] + red[1] + red[2] + red[3];
-}
-
-// 0b. chunk plan: chunk k covers groups [chunk[k], chunk[k+1]), the groups whose
-// exclusive prefix of bounds lies in [k budget, (k+1) budget); a chunk's bound
-// therefore stays below budget + one group's bound, which the layout keeps
-// below the key buffer's capacity.
-__global__ __launch_bounds__(1024) void plan_chunks_kernel(const uint32_t *grp, int64_t ngroups,
-                                                           unsigned long long budget, int kmax, uint32_t *chunk,
-                                                           PartHeader *hdr) {
-    __shared__ unsigned long long part[1024];
-    __shared__ unsigned long long carry;
-    for (int k = threadIdx.x; k <= kmax; k += 1024) chunk[k] = k == 0 ? 0u : (uint32_t)ngroups;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    unsigned long long last_c = 0;
-    for (int64_t base = 0; base < ngroups; base += 1024) {
-        const int64_t g = base + threadIdx.x;
-        const unsigned long long v = g < ngroups ? grp[g] : 0ull;
-        part[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan (Hillis-Steele)
-            const unsigned long long t = threadIdx.x >= off ? part[threadIdx.x - off] : 0ull;
-            __syncthreads();
-            part[threadIdx.x] += t;
-            __syncthreads();
-        }
-        const unsigned long long excl = carry + part[threadIdx.x] - v;
-        if (g < ngroups && g > 0) {
-            const unsigned long long c = excl / budget;
-            const unsigned long long prev = (excl - grp[g - 1]) / budget;
-            if (c > prev && c < (unsigned long long)kmax) chunk[c] = (uint32_t)g;
-        }
-        __syncthreads();
-        if (threadIdx.x == 1023) carry += part[1023];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        last_c = carry == 0 ? 0ull : (carry - 1) / budget + 1;
-        hdr->n_chunks = (unsigned int)(last_c < (unsigned long long)kmax ? last_c : kmax);
+// per-chunk reset of the key counter; chunk 0 runs when there are particles,
+// a later chunk when some wave stopped on the margin in the previous one
+__global__ void reset_chunk_kernel(PartHeader *hdr, int64_t n, int first) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        hdr->reserved = 0ull;
+        hdr->active = first ? (n > 0 ? 1u : 0u) : (hdr->unfinished > 0 ? 1u : 0u);
+        hdr->unfinished = 0u;
     }
 }
 
-// per-chunk reset of the key counter
-__global__ void reset_chunk_kernel(PartHeader *hdr) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) hdr->reserved = 0ull;
-}
-
-// 1. emit keys for the particles of chunk k
+// 1. emit keys for the particles of the current chunk.  Wave v (of the same
+// resident grid in every chunk) walks batches base_v, base_v + stride, ...;
+// wave_pos[v] holds where it resumes.  Before a batch it checks that the slots
+// reserved when it last reserved leave `margin` free (room for one batch of
+// every wave), so a chunk never overflows its key buffer; the last chunk does not check and
+// finishes every sequence (should its keys exceed the buffer, the rest are
+// added by atomics and counted in n_fallback).
 struct KeyParams {
     BinParams p;
     uint32_t *keys;
     unsigned long long cap;
+    unsigned long long margin;
     PartHeader *hdr;
-    const uint32_t *chunk;
-    int k, kmax;
+    int64_t *wave_pos;  // per wave: base of its next batch (-1: not started)
+    int last;
 };
 
 template <typename T>
@@ -262,13 +200,11 @@ __global__ __launch_bounds__(kBinBlock, 6) void keys_kernel(KeyParams kp) {
     const BinParams &p = kp.p;
     __shared__ EdgeLds E;
     __shared__ double qbuf[kBinWaves][3 * kQueue];
-    if (kp.k >= (int)kp.hdr->n_chunks) return;  // uniform: a chunk the plan left empty
-    const int64_t p0 = (int64_t)kp.chunk[kp.k] * kGroup;
-    int64_t p1 = (int64_t)kp.chunk[kp.k + 1] * kGroup;
-    if (p1 > p.c.n) p1 = p.c.n;
-    if (p0 >= p1) return;
+    if (!kp.hdr->active) return;  // uniform: every wave finished in an earlier chunk
     load_edges(E, p.c, p.e);
     const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * kBinWaves + w;
     const Shared sh = shared_of(p);
     LaneStats st;
     Emitter em{};
@@ -281,12 +217,37 @@ __global__ __launch_bounds__(kBinBlock, 6) void keys_kernel(KeyParams kp) {
     em.fill = kKeyChunk;
     em.full = false;
     WaveQueue q{qbuf[w], 0, 0};
-    const int64_t base = p0 + (int64_t)blockIdx.x * kBinBlock + w * 64;
     const int64_t stride = (int64_t)gridDim.x * kBinBlock;
-    bin_wave_range<T, kEmit>(p.c, sh, E, base, p1, stride, q, st, em);
+    const int64_t saved = kp.wave_pos[wid];
+    const int64_t base = saved >= 0 ? saved : (int64_t)blockIdx.x * kBinBlock + w * 64;
+    // The room check reads no memory: em.base, the reserved count the wave's
+    // latest reservation returned, is a lower bound of the count at that moment.
+    // Of the waves' last views before their last checks, the latest one covers
+    // every reservation made before any of those checks, and each wave adds at
+    // most one batch after its last check: the margin bounds the total.
+    const unsigned long long limit = kp.cap - kp.margin;
+    const bool last = kp.last != 0;
+    auto full = [&]() { return !last && em.base > limit; };
+    int64_t next = base;
+    if (base < p.c.n && !full()) next = bin_wave_range<T, kEmit>(p.c, sh, E, base, p.c.n, stride, q, st, em, full);
     drain_queue<kEmit>(p.c, sh, E, q, st, em);
     close_emitter(em);
+    if (lane == 0) {
+        kp.wave_pos[wid] = next;
+        if (next < p.c.n) atomicAdd(&kp.hdr->unfinished, 1u);
+    }
     flush_stats(p.status, st);
+}
+
+static int key_wgs_per_cu() {
+    static int v = 0;
+    if (!v) {
+        int a = 0, b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, keys_kernel<float>, kBinBlock, 0) != hipSuccess) a = 16;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, keys_kernel<double>, kBinBlock, 0) != hipSuccess) b = 16;
+        v = std::min(std::max(std::max(a, b), 1), kKeyWavesMax / kBinWaves);
+    }
+    return v;
 }
 
 // Partition steps.  Level 1: one segment keys[0, reserved) (with sentinels),
@@ -357,10 +318,10 @@ __device__ __forceinline__ void lds_barrier() {
 // per-super-tile bucket counts (wave-private LDS histograms, summed); 16 loads
 // in flight per thread
 constexpr int kHistUnroll = 16;
-__global__ __launch_bounds__(kPartThreads) void tile_hist_kernel(PartStep ps, int chunk_k, int kmax) {
+__global__ __launch_bounds__(kPartThreads) void tile_hist_kernel(PartStep ps) {
     constexpr int kW = kPartThreads / 64;
     __shared__ uint32_t wh[kW][kMaxBins];
-    if (chunk_k >= (int)ps.hdr->n_chunks) return;
+    if (!ps.hdr->active) return;
     const int tid = threadIdx.x, w = tid >> 6;
     const int64_t ntiles = step_tiles(ps);
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -395,9 +356,9 @@ __global__ __launch_bounds__(kPartThreads) void tile_hist_kernel(PartStep ps, in
 
 // one workgroup per global bucket g = seg * nbins + b: exclusive offsets of the
 // bucket's keys over the super-tiles of its segment, and the bucket total
-__global__ __launch_bounds__(256) void bucket_scan_kernel(PartStep ps, int chunk_k, int kmax) {
+__global__ __launch_bounds__(256) void bucket_scan_kernel(PartStep ps) {
     __shared__ uint32_t wsum[4];
-    if (chunk_k >= (int)ps.hdr->n_chunks) return;
+    if (!ps.hdr->active) return;
     const int64_t g = blockIdx.x;
     const int seg = (int)(g / ps.nbins), b = (int)(g % ps.nbins);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -435,12 +396,11 @@ __global__ __launch_bounds__(256) void bucket_scan_kernel(PartStep ps, int chunk
 // with shuffles and across the 16 waves through LDS: two barriers per
 // 1024 * kPer totals.
 __global__ __launch_bounds__(1024) void bucket_base_kernel(const uint32_t *tot, int64_t nbkt, uint32_t *base,
-                                                           uint32_t *tiles, const PartHeader *hdr, int chunk_k,
-                                                           int kmax) {
+                                                           uint32_t *tiles, const PartHeader *hdr) {
     constexpr int kPer = 8;
     constexpr int kW = 1024 / 64;
     __shared__ unsigned long long wh[kW], wt[kW];
-    if (chunk_k >= (int)hdr->n_chunks) return;
+    if (!hdr->active) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     unsigned long long carry = 0, carry_t = 0;  // uniform over the workgroup
     for (int64_t s = 0; s < nbkt; s += 1024 * kPer) {
@@ -503,7 +463,7 @@ __global__ __launch_bounds__(1024) void bucket_base_kernel(const uint32_t *tot, 
 constexpr int kScatThreads = 512;
 constexpr int kSub = 8192;
 template <typename OutT>
-__global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, int chunk_k, int kmax) {
+__global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps) {
     static_assert(sizeof(OutT) == 4 || sizeof(OutT) == 2, "full keys or 16-bit cell indices");
     static_assert(kBlockShift <= 16, "a cell index inside a block fits 16 bits");
     constexpr int kW = kScatThreads / 64;
@@ -517,7 +477,7 @@ __global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, i
     __shared__ uint32_t dst[kMaxBins];       // global position of sorted slot 0 of the bucket (mod 2^32)
     __shared__ uint32_t skeys[kSub];
     __shared__ uint32_t wsum[kW];
-    if (chunk_k >= (int)ps.hdr->n_chunks) return;
+    if (!ps.hdr->active) return;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int64_t ntiles = step_tiles(ps);
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -599,9 +559,9 @@ __global__ __launch_bounds__(kScatThreads, 4) void scatter_kernel(PartStep ps, i
 // 5. one workgroup per cell block: LDS histogram, then counts += histogram
 __global__ __launch_bounds__(kAccThreads) void accumulate_kernel(const uint16_t *cells, const uint32_t *offb,
                                                                  int64_t nblk, int64_t ncells, uint32_t *counts,
-                                                                 const PartHeader *hdr, int chunk_k, int kmax) {
+                                                                 const PartHeader *hdr) {
     __shared__ uint32_t h[kBlockCells];
-    if (chunk_k >= (int)hdr->n_chunks) return;
+    if (!hdr->active) return;
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         const uint32_t lo = offb[blk], hi = offb[blk + 1];
         if (lo == hi) continue;  // uniform over the block
@@ -682,20 +642,14 @@ __global__ __launch_bounds__(kBinBlock) void part_rescue_kernel(BinParams p) {
     flush_stats(p.status, st);
 }
 
-__global__ void part_guard_reset_kernel(GuardList *g) {
-    if (threadIdx.x == 0) {
+__global__ void part_guard_reset_kernel(GuardList *g, PartHeader *hdr, int64_t *wave_pos, int64_t nwaves) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
         g->count = 0u;
         g->overflow = 0u;
+        hdr->unfinished = 0u;
     }
-}
-
-// The whole set fits one chunk: no counting pass, chunk 0 = all groups.
-__global__ void single_chunk_kernel(uint32_t *chunk, int64_t ngroups, PartHeader *hdr) {
-    if (threadIdx.x == 0) {
-        chunk[0] = 0u;
-        chunk[1] = (uint32_t)ngroups;
-        hdr->n_chunks = 1u;
-    }
+    if (i < nwaves) wave_pos[i] = -1;
 }
 
 template <typename T>
@@ -708,8 +662,6 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
     uint32_t *offb = reinterpret_cast<uint32_t *>(ws + L.off_offb);
     uint32_t *tot = reinterpret_cast<uint32_t *>(ws + L.off_tot);
     uint32_t *thist = reinterpret_cast<uint32_t *>(ws + L.off_thist);
-    uint32_t *grp = reinterpret_cast<uint32_t *>(ws + L.off_grp);
-    uint32_t *chunk = reinterpret_cast<uint32_t *>(ws + L.off_chunk);
     uint32_t *keysa = reinterpret_cast<uint32_t *>(ws + L.off_keysa);
     uint32_t *keysb = reinterpret_cast<uint32_t *>(ws + L.off_keysb);
     p.guard = guard;
@@ -717,17 +669,15 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
     const int64_t ncells = (int64_t)p.c.nb * p.npix;
     const unsigned cus = (unsigned)device_cus();
 
-    timer_start(timer, s);
-    hipLaunchKernelGGL(part_guard_reset_kernel, dim3(1), dim3(64), 0, s, guard);
-    if (L.kmax == 1 && (double)p.c.n * (double)img_bound <= (double)L.budget) {
-        // every instance of the set fits the key buffer (positions in the box)
-        hipLaunchKernelGGL(single_chunk_kernel, dim3(1), dim3(64), 0, s, chunk, L.ngroups, hdr);
-    } else {
-        hipLaunchKernelGGL((count_groups_kernel<T>), dim3((unsigned)L.ngroups), dim3(256), 0, s, p.c, grp);
-        hipLaunchKernelGGL(plan_chunks_kernel, dim3(1), dim3(1024), 0, s, grp, L.ngroups, L.budget, L.kmax, chunk,
-                           hdr);
-    }
+    int64_t *wave_pos = reinterpret_cast<int64_t *>(ws + L.off_wave);
+    // one resident round of waves, the same in every chunk (wave v resumes its own sequence)
+    const unsigned key_grid = blocks_for(p.c.n, kBinBlock, resident_grid(keys_kernel<T>, kBinBlock, cus));
+    const int64_t nwaves = (int64_t)key_grid * kBinWaves;
+    if (nwaves > (int64_t)cus * kKeyWavesMax) return UFALCON_EWORKSPACE;  // never: the grid is one resident round
 
+    timer_start(timer, s);
+    hipLaunchKernelGGL(part_guard_reset_kernel, dim3(blocks_for(nwaves, 256)), dim3(256), 0, s, guard, hdr, wave_pos,
+                       nwaves);
     timer_mark(timer, UFALCON_PHASE_SETUP, s);
 
     KeyParams kp;
@@ -735,10 +685,7 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
     kp.keys = keysa;
     kp.cap = L.cap;
     kp.hdr = hdr;
-    kp.chunk = chunk;
-    kp.kmax = L.kmax;
-    // one resident round: the particle loop is grid-strided and evenly loaded
-    const unsigned key_grid = blocks_for(p.c.n, kBinBlock, resident_grid(keys_kernel<T>, kBinBlock, cus));
+    kp.wave_pos = wave_pos;
 
     PartStep l1{};
     l1.in = keysa;
@@ -770,28 +717,26 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
     const unsigned scat_grid = resident_grid(scatter_kernel<uint32_t>, kScatThreads, cus);
     const unsigned acc_grid = resident_grid(accumulate_kernel, kAccThreads, cus);
     for (int k = 0; k < L.kmax; ++k) {
-        hipLaunchKernelGGL(reset_chunk_kernel, dim3(1), dim3(64), 0, s, hdr);
-        kp.k = k;
+        hipLaunchKernelGGL(reset_chunk_kernel, dim3(1), dim3(64), 0, s, hdr, p.c.n, k == 0 ? 1 : 0);
+        kp.margin = L.margin;
+        kp.last = k + 1 == L.kmax ? 1 : 0;  // the last chunk takes every particle left
         if (k == 0 && hooks && hooks->wait_keys) UFX_HIP_CHECK(hipStreamWaitEvent(s, hooks->wait_keys, 0));
         hipLaunchKernelGGL((keys_kernel<T>), dim3(key_grid), dim3(kBinBlock), 0, s, kp);
         if (k == 0 && hooks && hooks->done_keys) UFX_HIP_CHECK(hipEventRecord(hooks->done_keys, s));
         timer_mark(timer, UFALCON_PHASE_DECIDE, s);
         // level 1: by key >> s1
-        hipLaunchKernelGGL(tile_hist_kernel, dim3(hist_grid), dim3(kPartThreads), 0, s, l1, k, L.kmax);
-        hipLaunchKernelGGL(bucket_scan_kernel, dim3((unsigned)L.nb1), dim3(256), 0, s, l1, k, L.kmax);
-        hipLaunchKernelGGL(bucket_base_kernel, dim3(1), dim3(1024), 0, s, tot, (int64_t)L.nb1, off1, tiles1, hdr, k,
-                           L.kmax);
-        hipLaunchKernelGGL(scatter_kernel<uint32_t>, dim3(scat_grid), dim3(kScatThreads), 0, s, l1, k, L.kmax);
+        hipLaunchKernelGGL(tile_hist_kernel, dim3(hist_grid), dim3(kPartThreads), 0, s, l1);
+        hipLaunchKernelGGL(bucket_scan_kernel, dim3((unsigned)L.nb1), dim3(256), 0, s, l1);
+        hipLaunchKernelGGL(bucket_base_kernel, dim3(1), dim3(1024), 0, s, tot, (int64_t)L.nb1, off1, tiles1, hdr);
+        hipLaunchKernelGGL(scatter_kernel<uint32_t>, dim3(scat_grid), dim3(kScatThreads), 0, s, l1);
         // level 2: by cell block inside each level-1 bucket
-        hipLaunchKernelGGL(tile_hist_kernel, dim3(hist_grid), dim3(kPartThreads), 0, s, l2, k, L.kmax);
-        hipLaunchKernelGGL(bucket_scan_kernel, dim3((unsigned)L.nblk), dim3(256), 0, s, l2, k, L.kmax);
-        hipLaunchKernelGGL(bucket_base_kernel, dim3(1), dim3(1024), 0, s, tot, L.nblk, offb, (uint32_t *)nullptr, hdr,
-                           k, L.kmax);
-        hipLaunchKernelGGL(scatter_kernel<uint16_t>, dim3(scat_grid), dim3(kScatThreads), 0, s, l2, k, L.kmax);
+        hipLaunchKernelGGL(tile_hist_kernel, dim3(hist_grid), dim3(kPartThreads), 0, s, l2);
+        hipLaunchKernelGGL(bucket_scan_kernel, dim3((unsigned)L.nblk), dim3(256), 0, s, l2);
+        hipLaunchKernelGGL(bucket_base_kernel, dim3(1), dim3(1024), 0, s, tot, L.nblk, offb, (uint32_t *)nullptr, hdr);
+        hipLaunchKernelGGL(scatter_kernel<uint16_t>, dim3(scat_grid), dim3(kScatThreads), 0, s, l2);
         timer_mark(timer, UFALCON_PHASE_PARTITION, s);
         hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)std::min<int64_t>(L.nblk, acc_grid)), dim3(kAccThreads), 0,
-                           s, reinterpret_cast<const uint16_t *>(keysa), offb, L.nblk, ncells, p.c.counts, hdr, k,
-                           L.kmax);
+                           s, reinterpret_cast<const uint16_t *>(keysa), offb, L.nblk, ncells, p.c.counts, hdr);
         timer_mark(timer, UFALCON_PHASE_ACCUMULATE, s);
     }
     hipLaunchKernelGGL(part_guarded_kernel, dim3(64), dim3(256), 0, s, p);
@@ -820,10 +765,8 @@ int try_partitioned(BinParams &p, int dtype, void *workspace, size_t bytes, hipS
 size_t partitioned_size_for(const BinParams &p) {
     const int img = image_bound(p.c, p.e, p.c.nb);
     const double want = std::min<double>((double)p.c.n * img, 4.0e9);
-    const int64_t floor_keys = 4ll * kGroup * img;
     PartLayout L;
-    if (!plan_layout(L, p.c.n, (int64_t)p.c.nb * p.npix, img, 0, std::max<int64_t>((int64_t)want, floor_keys)))
-        return 0;
+    if (!plan_layout(L, p.c.n, (int64_t)p.c.nb * p.npix, img, 0, std::max<int64_t>((int64_t)want, 1))) return 0;
     return L.total;
 }
 
@@ -844,7 +787,6 @@ extern "C" size_t ufalcon_bin_shells_workspace_size_partitioned(int64_t n, int32
         return 0;
     const int side = 2 * n_rep + 1;
     const int img = side * side * side;
-    const int64_t floor_keys = 4ll * kGroup * img;  // the smallest budget the chunk plan accepts
-    return partitioned_workspace_size(n, (int64_t)shells_in_range * npix_of(nside), img,
-                                      max_keys > floor_keys ? max_keys : floor_keys);
+    // the layout keeps room for the claim protocol on top of max_keys
+    return partitioned_workspace_size(n, (int64_t)shells_in_range * npix_of(nside), img, max_keys > 0 ? max_keys : 1);
 }

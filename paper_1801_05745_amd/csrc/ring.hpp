@@ -188,30 +188,43 @@ UFX_HD int shell_table_cells(const double *e2, int nb, double lo2, double hi2) {
     return 0;
 }
 
+// Entry of the shell lookup table for the cell [a, b) of r^2: the shell holding
+// r^2 = a (plus one, so that -1 is stored as 0) in the low 12 bits, and in bits
+// 12-13 which edge lies within delta of the cell, if any: 1 for e2[base + 1]
+// (inside the cell or just past its end), 2 for e2[base] (just below its
+// start), 0 for none.  delta = 2^-24 cells + 2^-30 |b| covers the rounding of
+// the cell index of r^2 and every guard band (2^-38 relative); consecutive
+// edges being two cells apart, at most one edge is within delta of a cell.
+UFX_HD int16_t shell_table_entry(const double *e2, int nb, int steps, double a, double b) {
+    const int base = shell_of_r2(e2, nb, steps, a);
+    const double delta = 0x1p-24 * (b - a) + 0x1p-30 * fabs(b);
+    int which = 0;
+    if (base + 1 <= nb && e2[base + 1] <= b + delta) which = 1;
+    else if (base >= 0 && e2[base] >= a - delta) which = 2;
+    return (int16_t)((base + 1) | (which << 12));
+}
+
 // Largest j in [-1, nb] with e2[j] <= r2 (e2 ascending, indexable from -2 to
 // nb + 2 with the sentinels above); *clear is false when r2 is within the
-// relative guard of e2[j] or e2[j+1].  With a table (tab_n > 0), tab[c] is the
-// shell at the start of cell c of tab_n equal cells of r^2 from tab_lo (cell
-// width 1/tab_scale); consecutive edges being two cells apart, the hint of the
-// computed cell is within one of the answer (also when rounding moves r^2 into a
-// neighbouring cell), and one step up or down corrects it.
+// relative guard of e2[j] or e2[j+1].  With a table (tab_n > 0) of tab_n equal
+// cells of r^2 from tab_lo (cell width 1/tab_scale; entries from
+// shell_table_entry), the cell's entry gives the shell of its start and the one
+// edge that can be near r^2: one comparison with that edge decides the shell and
+// the guard (every other edge is farther than any guard band from the cell).
 UFX_FN int fast_shell(const double *e2, int nb, int steps, const int16_t *tab, int tab_n, double tab_lo,
                       double tab_scale, double r2, bool &clear) {
-    int j;
-    double elo, ehi;
     if (tab_n > 0) {
         const double cf = fmin(fmax((r2 - tab_lo) * tab_scale, 0.0), (double)(tab_n - 1));
-        const int h = tab[(int)cf];
-        const double em = e2[h - 1], e0 = e2[h], e1 = e2[h + 1], ep = e2[h + 2];
-        const bool up = e1 <= r2, down = e0 > r2;
-        j = up ? h + 1 : (down ? h - 1 : h);
-        elo = up ? e1 : (down ? em : e0);
-        ehi = up ? ep : (down ? e0 : e1);
-    } else {
-        j = shell_of_r2(e2, nb, steps, r2);
-        elo = e2[j];
-        ehi = e2[j + 1];
+        const int t = tab[(int)cf];
+        const int base1 = t & 0xFFF, which = t >> 12;
+        const int k = which == 2 ? base1 - 1 : base1;  // the near edge (any valid index when none)
+        const double ek = e2[k];
+        const bool up = r2 >= ek;
+        clear = which == 0 || fabs(r2 - ek) > kRelGuard * ek;
+        return which == 0 ? base1 - 1 : (up ? k : k - 1);
     }
+    const int j = shell_of_r2(e2, nb, steps, r2);
+    const double elo = e2[j], ehi = e2[j + 1];
     const bool clear_lo = fabs(r2 - elo) > kRelGuard * elo;
     const bool clear_hi = fabs(r2 - ehi) > kRelGuard * ehi;
     clear = clear_lo && clear_hi;

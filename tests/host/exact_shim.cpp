@@ -41,7 +41,9 @@ int shim_fast_shell(const double *e2, int nb, double r2, int *clear, int use_tab
         h = (hi2 - lo2) / tab_n;
         scale = tab_n / (hi2 - lo2);
         tab.resize(tab_n);
-        for (int t = 0; t < tab_n; ++t) tab[t] = (int16_t)ufx::shell_of_r2(E, nb, steps, lo2 + (double)t * h);
+        for (int t = 0; t < tab_n; ++t)
+            tab[t] = ufx::shell_table_entry(E, nb, steps, lo2 + (double)t * h,
+                                            t + 1 < tab_n ? lo2 + (double)(t + 1) * h : hi2);
     }
     bool c = false;
     int j = ufx::fast_shell(E, nb, steps, tab.data(), tab_n, lo2, scale, r2, c);

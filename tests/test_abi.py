@@ -195,3 +195,13 @@ def test_binding_rejects_malformed_born_inputs():
         uf.born_kappa_adjoint(c32, inb, torch.ones((1, 192), dtype=torch.float16))
     with pytest.raises(ValueError, match="uint32"):
         uf.BornKappa.apply(W, c32.to(torch.int64), inb)
+
+
+def test_partitioned_workspace_sizes_exist():
+    # the partitioned layout keeps room for the key pass's claims on top of the keys;
+    # every combination of set size, replication and resolution gets a workspace
+    lib = uf.load()
+    for n in (0, 1, 100, 1000, 100000, 1 << 20, 1 << 27, 1 << 28):
+        for R in (0, 1, 2, 3):
+            for nside in (1, 4, 1024, 2048):
+                assert lib.ufalcon_bin_shells_workspace_size_partitioned(n, R, 30, nside, n * (2 * R + 1) ** 3) > 0
