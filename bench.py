@@ -105,7 +105,7 @@ def measured_traffic():
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
-ALL_PARTS = ("config1", "config2", "config4", "config5", "spectra")
+ALL_PARTS = ("batched_cell", "config1", "config2", "config4", "config5", "spectra")
 
 
 def parse():
@@ -126,18 +126,34 @@ def parse():
 
 def sht_flops(nside, lmax):
     """Algorithmic FP64 flops of one spherical-harmonic analysis or synthesis at
-    Nside, lmax, fixed by the transform (not by a kernel variant): the ring
-    transforms as direct DFTs of each ring's n real samples at the lmax + 1
-    azimuthal orders m (2 flops per real-by-complex product, 2 per complex add
-    -> 4 per sample and m), and the Legendre step, 7 flops per (l, m, ring
-    pair): the three-term recurrence (3) and the complex multiply-add with the
-    folded ring sums (4)."""
+    Nside, lmax, fixed by the transform (not by a kernel variant): every ring of
+    n = 4 n4 pixels as four direct length-n4 DFTs (4 flops per real-by-complex
+    multiply-add: 16 n4^2 per ring), and the Legendre step, 7 flops per (l, m,
+    ring pair): the three-term recurrence (3) and the complex multiply-add with
+    the folded ring sums (4)."""
     N = nside
     n_alm = (lmax + 1) * (lmax + 2) // 2
     legendre = 7 * n_alm * 2 * N
-    ring_pixels = 12 * N * N
-    dft = 4 * ring_pixels * (lmax + 1)
+    dft = (2 * N + 1) * 16 * N * N + 2 * sum(16 * i * i for i in range(1, N))
     return float(legendre + dft)
+
+
+def sht_flops_executed(nside, lmax, inverse=False):
+    """The flops the kernels execute: the ring DFTs divided by their number K of
+    output classes (equatorial rings: K = 4 when 4 | Nside, 2 when Nside is even,
+    and for the inverse 8 when 8 | Nside, with complex sums from K = 4 on; polar
+    rings: K = 2 on even rings), plus the same Legendre step."""
+    N = nside
+    n_alm = (lmax + 1) * (lmax + 2) // 2
+    legendre = 7 * n_alm * 2 * N
+    if inverse:
+        k_eq = 8 if N % 8 == 0 else (4 if N % 4 == 0 else (2 if N % 2 == 0 else 1))
+        dft_eq = (2 * N + 1) * 16 * N * N // k_eq * (2 if k_eq >= 4 else 1)
+    else:
+        k_eq = 4 if N % 4 == 0 else (2 if N % 2 == 0 else 1)
+        dft_eq = (2 * N + 1) * 16 * N * N // k_eq
+    dft_polar = sum(2 * 16 * i * i // (2 if i % 2 == 0 else 1) for i in range(1, N))
+    return float(legendre + dft_eq + dft_polar)
 
 
 def cpu_info():
@@ -201,7 +217,7 @@ def log(msg):
 
 # ---------------------------------------------------------------- headline (batched, 16 realisations)
 
-def batched16(dev, args):
+def batched16(dev, args, order=None, steps=None, warmup=None, plain_reps=2, roofline=True):
     import torch
 
     import paper_1801_05745_amd as uf
@@ -215,7 +231,7 @@ def batched16(dev, args):
     items = []
     for r in range(16):
         x, y, z = synth.lognormal_box(sizes[r], L, seed=r, ngrid=256, dtype=torch.float32, device=dev,
-                                      order=args.order)
+                                      order=order or args.order)
         zg = torch.linspace(0.1, 1.0, shells[r] + 1, dtype=torch.float64, device=dev)
         edges = uf.comoving_distance(zg, om).cpu().tolist()
         R = radius_reps(edges, L)
@@ -257,20 +273,22 @@ def batched16(dev, args):
         plan.run_graph(status)
         backward([it["kappa"] for it in items])
 
-    for _ in range(args.warmup):
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     status.zero_()
     t1 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t1
-    ms_per_step = 1e3 * wall / args.steps
+    ms_per_step = 1e3 * wall / steps
     st = uf.status_dict(status)
-    log(f"headline: {ms_per_step:.1f} ms per step")
+    log(f"batched16 ({order or args.order}): {ms_per_step:.1f} ms per step")
     n_total = sum(sizes)
-    inst = st["n_instances"] / args.steps
+    inst = st["n_instances"] / steps
     kap = torch.cat([it["kappa"].double() for it in items], 0)
     rms = kap.pow(2).mean(dim=1).sqrt()
     max_over_rms = float((kap.abs().max(dim=1).values / rms).max())
@@ -278,8 +296,10 @@ def batched16(dev, args):
 
     # plain: the same step as 16 sequences of single-map calls (one shared workspace)
     plain = None
-    if not args.no_plain:
+    ws = None
+    if not args.no_plain and (plain_reps > 0 or roofline):
         ws = uf.partition_workspace(max(sizes), max(it["n_rep"] for it in items), max(shells), nside, device=dev)
+    if ws is not None and plain_reps > 0:
 
         def plain_step():
             kappas = []
@@ -295,7 +315,7 @@ def batched16(dev, args):
 
         plain_step()
         torch.cuda.synchronize()
-        reps = 2
+        reps = plain_reps
         t1 = time.perf_counter()
         for _ in range(reps):
             plain_step()
@@ -304,6 +324,7 @@ def batched16(dev, args):
         log(f"headline: plain {plain_ms:.1f} ms per batch")
         plain = {"ms_per_batch": plain_ms, "maps_per_s": 16e3 / plain_ms, "reps": reps}
 
+    if roofline and ws is not None:
         # the dominant kernel, timed on its own stream by the library's phase events:
         # one phase-timed plain binning pass over the 16 realisations
         phases = {name: 0.0 for name in uf.PHASES}
@@ -315,27 +336,28 @@ def batched16(dev, args):
             for k, v in timer.read().items():
                 phases[k] += v
         timer.close()
-        del ws
+    del ws
     plan.close()
     images = sum(it["n"] * (2 * it["n_rep"] + 1) ** 3 for it in items)
     flops = FLOPS_PER_IMAGE * images + FLOPS_PER_INSTANCE * inst
     bin_bytes = sum(12 * it["n"] + 4 * it["counts"].numel() for it in items)
     res = {
         "ms_per_step": ms_per_step, "particles": n_total, "instances_per_step": inst, "images": images,
-        "guarded_per_step": st["n_guarded"] / args.steps, "unresolved": st["n_unresolved"],
+        "order": order or args.order, "steps": steps,
+        "guarded_per_step": st["n_guarded"] / steps, "unresolved": st["n_unresolved"],
         "fallback": st["n_fallback"], "kappa_max_over_rms": max_over_rms, "shells": shells,
         "maps_per_s_batched": 16e3 / ms_per_step, "plain": plain,
         "tuning": {"method": tuning["method"], "tile": tuning["tile"], "persistent_wgs": tuning["persistent_wgs"],
                    "candidates": tuning["candidates"], "tune_s": tune_s, "sample_items": 2},
         "input_generation_s": gen_s,
     }
-    if plain is not None:
+    if roofline and not args.no_plain:
         res["phases_ms"] = phases
         res["decide_ms"] = phases["decide"]
         res["algorithmic_flops"] = flops
         res["bin_bytes"] = bin_bytes
     cpu_sample = None
-    if not args.no_cpu_baseline:
+    if roofline and not args.no_cpu_baseline:
         it = items[0]
         m = min(args.cpu_sample, it["n"])
         cpu_sample = dict(x=it["x"][:m].cpu().numpy(), y=it["y"][:m].cpu().numpy(), z=it["z"][:m].cpu().numpy(),
@@ -622,7 +644,9 @@ def config5(dev, reps=2):
     torch.cuda.synchronize()
     gen_s = time.time() - t0
     log(f"config5: 150 realisations generated in {gen_s:.1f} s")
-    plan = uf.BatchPlan(items, nside, T=1, method="partition")
+    W.copy_(uf.lensing_weights(om, [base], edges, device=dev))
+    tuning = uf.autotune_batch(items, nside, T=1, sample_items=4)
+    plan = uf.BatchPlan(items, nside, T=1, method="auto")
     status = uf.new_status(dev)
     out = {}
 
@@ -648,6 +672,28 @@ def config5(dev, reps=2):
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t1) / reps
     st = uf.status_dict(status)
+    t1 = time.perf_counter()
+    plan.run_graph(status)
+    torch.cuda.synchronize()
+    fwd_ms = 1e3 * (time.perf_counter() - t1)
+    plan.close()
+    # the same forward pass as 150 plain calls (one shared workspace)
+    ws = uf.partition_workspace(n, R, B, nside, device=dev)
+
+    def plain_forward():
+        for it in items:
+            uf.fill_u32(it["counts"], 0)
+            uf.bin_shells(it["x"], it["y"], it["z"], edges, nside, box_L=L, n_rep=R, counts=it["counts"],
+                          workspace=ws)
+            it["kappa"].copy_(uf.born_kappa(it["counts"], W, inb))
+
+    plain_forward()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plain_forward()
+    torch.cuda.synchronize()
+    plain_fwd_ms = 1e3 * (time.perf_counter() - t1)
+    del ws
     res = {"workload": "150 realisations x 256^3 lognormal FP32 particles, 1 Gpc/h box, 40 shells z=0.1-1.5, "
                        "Nside 512, images {-3..3}^3, Smail n(z); forward (batch-plan graph: bin + Born) + backward "
                        "(adjoint of L = sum kappa^2 to W, Omega_m, z0)",
@@ -656,8 +702,11 @@ def config5(dev, reps=2):
            "instances_per_s": st["n_instances"] / reps / (ms / 1e3),
            "unresolved": st["n_unresolved"], "fallback": st["n_fallback"],
            "dL_dOmega_m": float(out["g_om"]), "dL_dz0": float(out["g_z0"]),
+           "tuning": {"method": tuning["method"], "candidates_ms": [round(c["ms"], 2) for c in tuning["candidates"]],
+                      "sample_items": 4},
+           "forward_batched_ms": fwd_ms, "forward_batched_maps_per_s": R_real * 1e3 / fwd_ms,
+           "forward_plain_ms": plain_fwd_ms, "forward_plain_maps_per_s": R_real * 1e3 / plain_fwd_ms,
            "input_generation_s": gen_s, "reps": reps}
-    plan.close()
     del items, plan, out
     free_device()
     return res
@@ -716,6 +765,8 @@ def spectra(dev, kmap):
     mom = mom.cpu().tolist()
     res = {
         "nside": nside, "lmax": lmax, "algorithmic_flops_per_transform": fl,
+        "executed_flops": {"map2alm": sht_flops_executed(nside, lmax),
+                           "alm2map": sht_flops_executed(nside, lmax, inverse=True)},
         "map2alm": {"ms": sht_ms, "TFLOPs": fl / (sht_ms / 1e3) / 1e12,
                     "frac_fp64": fl / (sht_ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS},
         "alm2cl_ms": cl_ms, "power_spectra_per_s": 1e3 / (sht_ms + cl_ms),
@@ -812,6 +863,10 @@ def main():
     if not args.no_cpu_baseline and cpu_sample is not None:
         line["cpu_baseline"] = cpu_baseline(cpu_sample)
         log(f"cpu baseline: {line['cpu_baseline']['value']:.3g} particles/s")
+    if "batched_cell" in parts:
+        cell, _ = batched16(dev, args, order="cell", steps=3, warmup=1, plain_reps=1, roofline=False)
+        line["batched_cell_order"] = {k: cell[k] for k in ("ms_per_step", "maps_per_s_batched", "plain", "tuning",
+                                                           "instances_per_step", "fallback", "unresolved")}
     kmap = None
     if "config2" in parts:
         line["config2"], kmap = config2(dev, "shuffled")

@@ -290,9 +290,12 @@ typedef struct ufalcon_batch_item {
 typedef struct ufalcon_batch_plan ufalcon_batch_plan;
 
 typedef enum ufalcon_accumulation {
-    UFALCON_ACCUMULATE_PARTITIONED = 0, /* keys + radix partition + LDS block histograms, item after item */
-    UFALCON_ACCUMULATE_ATOMIC = 1,      /* one persistent launch over (realisation, tile), global atomics */
-    UFALCON_ACCUMULATE_AUTO = 2         /* the autotuner's choice for this batch shape (else PARTITIONED) */
+    UFALCON_ACCUMULATE_PARTITIONED = 0, /* keys + radix partition + LDS block histograms, realisations on two
+                                           streams with their key passes staggered */
+    UFALCON_ACCUMULATE_ATOMIC = 1,      /* one persistent launch over (realisation, tile), global atomics with
+                                           equal keys aggregated across each wavefront */
+    UFALCON_ACCUMULATE_AUTO = 2,        /* the autotuner's choice for this batch shape (else PARTITIONED) */
+    UFALCON_ACCUMULATE_PARTITIONED_ONE_STREAM = 3 /* partitioned, realisations one after another */
 } ufalcon_accumulation;
 
 /*
@@ -322,15 +325,17 @@ int ufalcon_batch_run_graph(ufalcon_batch_plan *plan, ufalcon_status *status, uf
 /*
  * Autotuner of the batched form.  Times clear + bin + Born of the first
  * min(n_items, sample_items) realisations (sample_items <= 0: all) under each
- * candidate configuration: partitioned accumulation, and the persistent atomic
- * kernel with tile in {2^16, 2^18, 2^20} particles and {4, 8, 16} workgroups
- * per compute unit.  Each candidate runs once to warm up and once timed (HIP
- * events on `stream`; the call synchronises).  The fastest is written to
- * *tuning and recorded in a process-wide cache keyed by the batch shape
- * (device, dtype, nside, T, number of realisations, log2 of the particle
- * total, largest n_rep); ufalcon_batch_plan_create with
- * UFALCON_ACCUMULATE_AUTO, tile 0 and persistent_wgs 0 takes the cached
- * choice.  The cache is the library's only global state (mutex-guarded).
+ * candidate configuration: partitioned accumulation on two streams and on one,
+ * and the persistent atomic kernel (aggregated equal keys) with 2^18-particle
+ * tiles and 8 workgroups per compute unit, and 2^16-particle tiles and 16.
+ * Each candidate runs once to warm up and three times timed (HIP events on
+ * `stream`; the call synchronises); its median is its time.  The fastest is
+ * written to *tuning and recorded in a process-wide cache keyed by the batch
+ * shape (GPU architecture and compute units, dtype, nside, T, number of
+ * realisations, log2 of the particle total, largest n_rep);
+ * ufalcon_batch_plan_create with UFALCON_ACCUMULATE_AUTO, tile 0 and
+ * persistent_wgs 0 takes the cached choice.  The cache is the library's only
+ * global state (mutex-guarded); ufalcon_batch_tuning_save and _load persist it.
  * Side effects: the sampled realisations' counts and kappa are overwritten;
  * plans are created and freed (device allocations happen here, never in the
  * binning calls of a plan).
@@ -350,6 +355,17 @@ typedef struct ufalcon_batch_tuning {
 int ufalcon_batch_autotune(const ufalcon_batch_item *items, int32_t n_items, int dtype, int64_t nside, int32_t T,
                            int out_dtype, int32_t sample_items, ufalcon_batch_tuning *tuning,
                            ufalcon_stream_t stream);
+
+/*
+ * Persisted tuning choices: _save writes every cached choice to the file at
+ * `path` (one JSON object per line: arch, cus, dtype, nside, T, items, log2n,
+ * max_rep, accumulation, wgs, tile); _load adds the choices of such a file to
+ * the cache (entries already cached are replaced) and writes how many it read
+ * to *n_loaded (may be NULL).  Host only.  Errors: EINVAL (null path, or a line
+ * that is not such an object), EHIP (the file cannot be opened or written).
+ */
+int ufalcon_batch_tuning_save(const char *path);
+int ufalcon_batch_tuning_load(const char *path, int32_t *n_loaded);
 
 /*
  * Spherical-harmonic coefficients of HEALPix RING maps (section 3.1: the

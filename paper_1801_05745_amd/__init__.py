@@ -101,6 +101,8 @@ _SIGS = {
     "ufalcon_batch_run_graph": (ctypes.c_int, [_P, _P, _P]),
     "ufalcon_batch_autotune": (ctypes.c_int, [ctypes.POINTER(BatchItem), _I32, ctypes.c_int, _I64, _I32, ctypes.c_int,
                                               _I32, _P, _P]),
+    "ufalcon_batch_tuning_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "ufalcon_batch_tuning_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_I32)]),
     "ufalcon_map2alm_workspace_size": (_SZ, [_I64, _I32]),
     "ufalcon_map2alm": (ctypes.c_int, [_P, ctypes.c_int, _I32, _I64, _I32, _P, _P, _SZ, _P]),
     "ufalcon_alm2cl": (ctypes.c_int, [_P, _I32, _I32, _P, _P]),
@@ -417,6 +419,8 @@ class HostStream:
 
     def copy_ms(self):
         """Milliseconds the copy stream spent in the last run's copies (waits for them)."""
+        for _, b in self._events:
+            b.synchronize()
         return sum(a.elapsed_time(b) for a, b in self._events)
 
 
@@ -802,6 +806,22 @@ def _batch_items(items):
     return arr, dtype, keep
 
 
+ACCUMULATION_NAMES = {0: "partition", 1: "atomic", 3: "partition-one-stream"}
+_ACCUMULATION_CODES = {"partition": 0, "atomic": 1, "auto": 2, "partition-one-stream": 3}
+
+
+def save_tuning(path):
+    """Write the autotuner's cached choices to `path` (one JSON object per line)."""
+    _check(load().ufalcon_batch_tuning_save(os.fsencode(path)), "ufalcon_batch_tuning_save")
+
+
+def load_tuning(path):
+    """Add the choices saved in `path` to the autotuner's cache; returns how many were read."""
+    n = ctypes.c_int32(0)
+    _check(load().ufalcon_batch_tuning_load(os.fsencode(path), ctypes.byref(n)), "ufalcon_batch_tuning_load")
+    return n.value
+
+
 def autotune_batch(items, nside, T=1, out_dtype=torch.float32, sample_items=0):
     """Time the batched form's candidate configurations on (the first sample_items of)
     these realisations and record the fastest for BatchPlan(method="auto").  Overwrites
@@ -811,7 +831,7 @@ def autotune_batch(items, nside, T=1, out_dtype=torch.float32, sample_items=0):
     tun = Tuning()
     _check(lib.ufalcon_batch_autotune(arr, len(items), dtype, int(nside), int(T), _dtype_code(out_dtype),
                                       int(sample_items), ctypes.byref(tun), _stream()), "ufalcon_batch_autotune")
-    names = {0: "partition", 1: "atomic"}
+    names = ACCUMULATION_NAMES
     cands = [{"method": names[tun.cand_accumulation[i]], "tile": int(tun.cand_tile[i]),
               "persistent_wgs": int(tun.cand_wgs[i]), "ms": float(tun.ms[i])} for i in range(tun.n_tried)]
     return {"method": names[tun.accumulation], "tile": int(tun.tile), "persistent_wgs": int(tun.persistent_wgs),
@@ -831,7 +851,7 @@ class BatchPlan:
         arr, dtype, self._keep = _batch_items(items)
         self.items = items
         handle = ctypes.c_void_p()
-        acc = {"partition": 0, "atomic": 1, "auto": 2}[method]
+        acc = _ACCUMULATION_CODES[method]
         _check(lib.ufalcon_batch_plan_create(arr, len(items), dtype, int(nside), int(T), _dtype_code(out_dtype),
                                              int(tile), int(persistent_wgs), acc, ctypes.byref(handle)),
                "ufalcon_batch_plan_create")

@@ -30,8 +30,12 @@
 #include "binning_core.hpp"
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -503,12 +507,13 @@ static void free_plan(ufalcon_batch_plan *p) {
 // ------------------------------------------------------------------ autotune cache
 namespace {
 struct TuneKey {
-    int device, dtype;
+    std::string arch;
+    int cus, dtype;
     int64_t nside;
     int32_t T, n_items, log2n, max_rep;
     bool operator<(const TuneKey &o) const {
-        return std::tie(device, dtype, nside, T, n_items, log2n, max_rep) <
-               std::tie(o.device, o.dtype, o.nside, o.T, o.n_items, o.log2n, o.max_rep);
+        return std::tie(arch, cus, dtype, nside, T, n_items, log2n, max_rep) <
+               std::tie(o.arch, o.cus, o.dtype, o.nside, o.T, o.n_items, o.log2n, o.max_rep);
     }
 };
 struct TuneChoice {
@@ -518,9 +523,19 @@ struct TuneChoice {
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneChoice> g_tune;  // the library's only global state
 
+std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a(prop.gcnArchName);
+    const size_t colon = a.find(':');  // drop feature suffixes (":sramecc+:xnack-")
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
 TuneKey tune_key(const ufalcon_batch_item *items, int32_t n_items, int dtype, int64_t nside, int32_t T) {
     TuneKey k{};
-    if (hipGetDevice(&k.device) != hipSuccess) k.device = -1;
+    k.arch = device_arch();
+    k.cus = device_cus();
     k.dtype = dtype;
     k.nside = nside;
     k.T = T;
@@ -536,6 +551,32 @@ TuneKey tune_key(const ufalcon_batch_item *items, int32_t n_items, int dtype, in
     k.log2n = l;
     k.max_rep = max_rep;
     return k;
+}
+
+bool valid_accumulation(int32_t a) {
+    return a == UFALCON_ACCUMULATE_PARTITIONED || a == UFALCON_ACCUMULATE_ATOMIC ||
+           a == UFALCON_ACCUMULATE_PARTITIONED_ONE_STREAM;
+}
+
+// The number after "\"name\":" in a line of the tuning file.
+bool json_number(const std::string &line, const char *name, double &v) {
+    const std::string key = std::string("\"") + name + "\":";
+    const size_t at = line.find(key);
+    if (at == std::string::npos) return false;
+    const char *p = line.c_str() + at + key.size();
+    char *end = nullptr;
+    v = std::strtod(p, &end);
+    return end != p;
+}
+
+bool json_string(const std::string &line, const char *name, std::string &v) {
+    const std::string key = std::string("\"") + name + "\":\"";
+    const size_t at = line.find(key);
+    if (at == std::string::npos) return false;
+    const size_t b = at + key.size(), e = line.find('"', b);
+    if (e == std::string::npos) return false;
+    v = line.substr(b, e - b);
+    return true;
 }
 }  // namespace
 
@@ -554,8 +595,9 @@ extern "C" int ufalcon_batch_plan_create(const ufalcon_batch_item *items, int32_
             if (persistent_wgs == 0) persistent_wgs = it->second.wgs;
         }
     }
-    if (accumulation != UFALCON_ACCUMULATE_PARTITIONED && accumulation != UFALCON_ACCUMULATE_ATOMIC)
-        return UFALCON_EINVAL;
+    if (!valid_accumulation(accumulation)) return UFALCON_EINVAL;
+    const bool one_stream = accumulation == UFALCON_ACCUMULATE_PARTITIONED_ONE_STREAM;
+    if (one_stream) accumulation = UFALCON_ACCUMULATE_PARTITIONED;
     if (dtype != UFALCON_F32 && dtype != UFALCON_F64) return UFALCON_EINVAL;
     if (out_dtype != UFALCON_F32 && out_dtype != UFALCON_F64) return UFALCON_EINVAL;
     if (T < 0 || T > UFALCON_MAX_BINS) return UFALCON_EINVAL;
@@ -645,7 +687,7 @@ extern "C" int ufalcon_batch_plan_create(const ufalcon_batch_item *items, int32_
     if (part_need > 0) {
         p->part_bytes = part_need;
         bool ok = hipMalloc(&p->d_part, part_need) == hipSuccess;
-        if (ok && p->item_params.size() > 1 && !p->shared_rows) {  // the second lane
+        if (ok && p->item_params.size() > 1 && !p->shared_rows && !one_stream) {  // the second lane
             ok = hipMalloc(&p->d_part2, part_need) == hipSuccess &&
                  hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking) == hipSuccess &&
                  hipEventCreateWithFlags(&p->fork_event, hipEventDisableTiming) == hipSuccess &&
@@ -711,7 +753,7 @@ extern "C" int ufalcon_bin_shells_batched(ufalcon_batch_plan *plan, ufalcon_stat
     if (plan->accumulation == UFALCON_ACCUMULATE_PARTITIONED) {
         hipStream_t s0 = as_stream(stream);
         const size_t m = plan->item_params.size();
-        if (m == 1 || plan->shared_rows) {  // one lane, realisations in order
+        if (m == 1 || !plan->aux_stream) {  // one lane, realisations in order
             for (BinParams bp : plan->item_params) {
                 bp.status = status;
                 int rc = UFALCON_OK;
@@ -802,18 +844,19 @@ extern "C" int ufalcon_batch_autotune(const ufalcon_batch_item *items, int32_t n
         int32_t acc, wgs;
         int64_t tile;
     };
-    std::vector<Cand> cands;
-    cands.push_back({UFALCON_ACCUMULATE_PARTITIONED, 0, 0});
     const int cus = device_cus();
-    for (int64_t t : {(int64_t)1 << 16, (int64_t)1 << 18, (int64_t)1 << 20})
-        for (int w : {4, 8, 16}) cands.push_back({UFALCON_ACCUMULATE_ATOMIC, cus * w, t});
+    const std::vector<Cand> cands = {{UFALCON_ACCUMULATE_PARTITIONED, 0, 0},
+                                     {UFALCON_ACCUMULATE_PARTITIONED_ONE_STREAM, 0, 0},
+                                     {UFALCON_ACCUMULATE_ATOMIC, cus * 8, (int64_t)1 << 18},
+                                     {UFALCON_ACCUMULATE_ATOMIC, cus * 16, (int64_t)1 << 16}};
+    constexpr int kReps = 3;
     hipStream_t s = as_stream(stream);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess) return UFALCON_EHIP;
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return UFALCON_EHIP;
-    }
+    hipEvent_t ev[kReps + 1] = {};
+    for (int r = 0; r <= kReps; ++r)
+        if (hipEventCreate(&ev[r]) != hipSuccess) {
+            for (int q = 0; q < r; ++q) (void)hipEventDestroy(ev[q]);
+            return UFALCON_EHIP;
+        }
     int rc = UFALCON_OK;
     double best = 0.0;
     int bi = -1;
@@ -829,27 +872,34 @@ extern "C" int ufalcon_batch_autotune(const ufalcon_batch_item *items, int32_t n
             return r;
         };
         rc = run();  // warm-up
-        float ms = 0.0f;
-        if (!rc && hipEventRecord(e0, s) != hipSuccess) rc = UFALCON_EHIP;
-        if (!rc) rc = run();
-        if (!rc && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        for (int r = 0; r < kReps && !rc; ++r) {
+            if (hipEventRecord(ev[r], s) != hipSuccess) rc = UFALCON_EHIP;
+            if (!rc) rc = run();
+        }
+        if (!rc && (hipEventRecord(ev[kReps], s) != hipSuccess || hipEventSynchronize(ev[kReps]) != hipSuccess))
             rc = UFALCON_EHIP;
+        double t[kReps] = {};
+        for (int r = 0; r < kReps && !rc; ++r) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev[r], ev[r + 1]) != hipSuccess) rc = UFALCON_EHIP;
+            t[r] = ms;
+        }
         if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = UFALCON_EHIP;
         ufalcon_batch_plan_destroy(plan);
         if (rc) break;
-        tuning->ms[i] = ms;
+        std::sort(t, t + kReps);
+        const double med = t[kReps / 2];
+        tuning->ms[i] = med;
         tuning->cand_accumulation[i] = c.acc;
         tuning->cand_wgs[i] = c.wgs;
         tuning->cand_tile[i] = c.tile;
         tuning->n_tried = (int32_t)i + 1;
-        if (bi < 0 || ms < best) {
-            best = ms;
+        if (bi < 0 || med < best) {
+            best = med;
             bi = (int)i;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (int r = 0; r <= kReps; ++r) (void)hipEventDestroy(ev[r]);
     if (rc) return rc;
     tuning->best = bi;
     tuning->accumulation = cands[bi].acc;
@@ -858,5 +908,59 @@ extern "C" int ufalcon_batch_autotune(const ufalcon_batch_item *items, int32_t n
     const TuneKey key = tune_key(items, n_items, dtype, nside, T);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune[key] = TuneChoice{cands[bi].acc, cands[bi].wgs, cands[bi].tile};
+    return UFALCON_OK;
+}
+
+extern "C" int ufalcon_batch_tuning_save(const char *path) {
+    if (!path) return UFALCON_EINVAL;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    FILE *f = std::fopen(path, "w");
+    if (!f) return UFALCON_EHIP;
+    bool ok = true;
+    for (const auto &kv : g_tune) {
+        const TuneKey &k = kv.first;
+        const TuneChoice &c = kv.second;
+        ok = ok && std::fprintf(f,
+                                "{\"arch\":\"%s\",\"cus\":%d,\"dtype\":%d,\"nside\":%lld,\"T\":%d,\"items\":%d,"
+                                "\"log2n\":%d,\"max_rep\":%d,\"accumulation\":%d,\"wgs\":%d,\"tile\":%lld}\n",
+                                k.arch.c_str(), k.cus, k.dtype, (long long)k.nside, k.T, k.n_items, k.log2n, k.max_rep,
+                                c.accumulation, c.wgs, (long long)c.tile) > 0;
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? UFALCON_OK : UFALCON_EHIP;
+}
+
+extern "C" int ufalcon_batch_tuning_load(const char *path, int32_t *n_loaded) {
+    if (!path) return UFALCON_EINVAL;
+    std::ifstream in(path);
+    if (!in) return UFALCON_EHIP;
+    std::vector<std::pair<TuneKey, TuneChoice>> got;
+    std::string line;
+    while (std::getline(in, line)) {
+        if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+        TuneKey k{};
+        TuneChoice c{};
+        double v[10];
+        const char *names[10] = {"cus", "dtype", "nside", "T", "items", "log2n", "max_rep", "accumulation", "wgs",
+                                 "tile"};
+        if (!json_string(line, "arch", k.arch)) return UFALCON_EINVAL;
+        for (int i = 0; i < 10; ++i)
+            if (!json_number(line, names[i], v[i])) return UFALCON_EINVAL;
+        k.cus = (int)v[0];
+        k.dtype = (int)v[1];
+        k.nside = (int64_t)v[2];
+        k.T = (int32_t)v[3];
+        k.n_items = (int32_t)v[4];
+        k.log2n = (int32_t)v[5];
+        k.max_rep = (int32_t)v[6];
+        c.accumulation = (int32_t)v[7];
+        c.wgs = (int32_t)v[8];
+        c.tile = (int64_t)v[9];
+        if (!valid_accumulation(c.accumulation) || c.wgs < 0 || c.tile < 0) return UFALCON_EINVAL;
+        got.emplace_back(k, c);
+    }
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (const auto &kv : got) g_tune[kv.first] = kv.second;
+    if (n_loaded) *n_loaded = (int32_t)got.size();
     return UFALCON_OK;
 }

@@ -205,3 +205,24 @@ def test_partitioned_workspace_sizes_exist():
         for R in (0, 1, 2, 3):
             for nside in (1, 4, 1024, 2048):
                 assert lib.ufalcon_bin_shells_workspace_size_partitioned(n, R, 30, nside, n * (2 * R + 1) ** 3) > 0
+
+
+def test_tuning_file_round_trip(tmp_path):
+    # persisted autotuner choices: a file read into the cache is written back the same
+    lines = ['{"arch":"gfx950","cus":256,"dtype":0,"nside":1024,"T":1,"items":16,"log2n":31,"max_rep":2,'
+             '"accumulation":0,"wgs":0,"tile":0}',
+             '{"arch":"gfx950","cus":256,"dtype":0,"nside":1024,"T":1,"items":16,"log2n":31,"max_rep":3,'
+             '"accumulation":1,"wgs":2048,"tile":262144}']
+    src = tmp_path / "tune.json"
+    src.write_text("\n".join(lines) + "\n")
+    assert uf.load_tuning(str(src)) == 2
+    out = tmp_path / "out.json"
+    uf.save_tuning(str(out))
+    saved = set(out.read_text().splitlines())
+    assert set(lines) <= saved
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"arch":"gfx950","cus":256}\n')
+    with pytest.raises(uf.UfalconError):
+        uf.load_tuning(str(bad))
+    with pytest.raises(uf.UfalconError):
+        uf.load_tuning(str(tmp_path / "missing.json"))

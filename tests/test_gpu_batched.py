@@ -85,11 +85,24 @@ def test_graph_replays_match_eager(ufalcon, method):
     plan.close()
 
 
+def test_one_stream_partitioned_plan(ufalcon):
+    nside = 16
+    items = _realisations([50000, 70000, 0, 30000], [5, 3, 4, 7], nside=nside, seed0=40)
+    plan = uf.BatchPlan(items, nside, T=1, method="partition-one-stream")
+    plan.run_graph()
+    torch.cuda.synchronize()
+    for it in items:
+        ref, _ = obin.bin_shells(it["xh"], it["yh"], it["zh"], (it["box_L"] / 2,) * 3, it["box_L"], it["n_rep"],
+                                 it["chi_edges"], nside, threads=8)
+        assert np.array_equal(it["counts"].cpu().numpy().astype(np.int64), ref)
+    plan.close()
+
+
 def test_autotuned_plan_matches_plain(ufalcon):
     nside = 16
     items = _realisations([60001, 20000, 90000], [4, 6, 3], nside=nside, seed0=20)
     tun = uf.autotune_batch(items, nside, T=1, sample_items=2)
-    assert len(tun["candidates"]) == 10
+    assert [c["method"] for c in tun["candidates"]] == ["partition", "partition-one-stream", "atomic", "atomic"]
     times = [c["ms"] for c in tun["candidates"]]
     assert all(t > 0.0 for t in times)
     assert tun["best"] == int(np.argmin(times))
