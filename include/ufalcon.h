@@ -41,8 +41,22 @@ typedef enum ufalcon_err {
     UFALCON_EOVERFLOW = -4,       /* a uint32 count cell could exceed 2^32 - 1 */
     UFALCON_EWORKSPACE = -5,      /* workspace missing or too small */
     UFALCON_EHIP = -6,            /* a HIP runtime call failed */
-    UFALCON_ETOO_MANY_SHELLS = -7 /* more than UFALCON_MAX_SHELLS shells or UFALCON_MAX_BINS source bins */
+    UFALCON_ETOO_MANY_SHELLS = -7, /* more than UFALCON_MAX_SHELLS shells or UFALCON_MAX_BINS source bins */
+    UFALCON_EINJECTED = -8         /* failure injected by UFALCON_FAULT_INJECT (tests of error handling) */
 } ufalcon_err;
+
+/* Instrumentation of every entry point that returns a status:
+ *   - a roctx range named after the entry point (rocprofv3 --marker-trace shows
+ *     the library calls around their kernels);
+ *   - fault injection for tests of error propagation: when the environment
+ *     variable UFALCON_FAULT_INJECT holds the entry point's name (a
+ *     comma-separated list; "*" names every entry point), the call returns
+ *     UFALCON_EINJECTED at once, before it validates or touches any argument.
+ *     The name "partition_chunk" makes the partitioned binning path fail after
+ *     the kernels of its first chunk are enqueued: the call returns
+ *     UFALCON_EINJECTED although work was queued and the count map was
+ *     partly updated, which is what a caller must never treat as a result.
+ *     The destroy calls are never failed.  The variable is read on every call. */
 
 #define UFALCON_MAX_SHELLS 256
 #define UFALCON_MAX_NSIDE 8192

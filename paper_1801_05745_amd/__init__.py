@@ -11,6 +11,7 @@ is no CPU fallback: without the built library every call raises.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 from dataclasses import dataclass
 
@@ -363,6 +364,55 @@ def bin_shells_noalloc(x, y, z, chi_edges, nside, observer=None, box_L=0.0, n_re
     return counts
 
 
+def save_stream_checkpoint(prefix, cursor, counts, status=None):
+    """Write a resumable state of a chunked binning run: the count map (host copy
+    of `counts`), the status counters and `cursor` (a dict: the next chunk and the
+    run's shape).  The map goes to a file named after the chunks done and the
+    JSON file <prefix>.json, replaced atomically, commits the state; the previous
+    map file is removed afterwards, so a crash at any point leaves one whole state."""
+    import numpy as np
+
+    prefix = os.fspath(prefix)
+    state = dict(cursor)
+    old = load_stream_checkpoint(prefix, counts_too=False)
+    name = f"{os.path.basename(prefix)}.{int(state['chunks_done'])}.npy"
+    path = os.path.join(os.path.dirname(prefix) or ".", name)
+    host = counts.detach().view(torch.int32).cpu().numpy().view(np.uint32)
+    with open(path + ".tmp", "wb") as f:
+        np.save(f, host, allow_pickle=False)
+        f.flush()
+        os.fsync(f.fileno())
+    os.replace(path + ".tmp", path)
+    state["counts_file"] = name
+    state["status"] = None if status is None else [int(v) for v in status.cpu().tolist()]
+    with open(prefix + ".json.tmp", "w") as f:
+        json.dump(state, f)
+        f.flush()
+        os.fsync(f.fileno())
+    os.replace(prefix + ".json.tmp", prefix + ".json")
+    if old is not None and old["counts_file"] != name:
+        try:
+            os.remove(os.path.join(os.path.dirname(prefix) or ".", old["counts_file"]))
+        except FileNotFoundError:
+            pass
+
+
+def load_stream_checkpoint(prefix, counts_too=True):
+    """The state written by save_stream_checkpoint (with the map as a numpy uint32
+    array under "counts" when counts_too), or None if there is none."""
+    import numpy as np
+
+    prefix = os.fspath(prefix)
+    if not os.path.exists(prefix + ".json"):
+        return None
+    with open(prefix + ".json") as f:
+        state = json.load(f)
+    if counts_too:
+        state["counts"] = np.load(os.path.join(os.path.dirname(prefix) or ".", state["counts_file"]),
+                                  allow_pickle=False)
+    return state
+
+
 class HostStream:
     """Bins particles held in pinned host memory: chunks of `chunk` particles are
     copied to two device staging slots on a copy stream, and each chunk is binned
@@ -370,7 +420,15 @@ class HostStream:
     overlaps the binning of chunk k (the subvolume decomposition of section 2.4:
     chunk maps add up in the count map).  The slots and the binning workspace are
     allocated once, at construction.  copy_ms() reads the copy engine's busy time
-    (HIP events on the copy stream) of the last run."""
+    (HIP events on the copy stream) of the last run.
+
+    A run can be made resumable: with `checkpoint` (a path prefix) and
+    checkpoint_every = k > 0 the count map, the status and the cursor of the next
+    chunk are saved every k chunks and when the run stops; run(..., resume=True)
+    loads them and continues at the cursor.  Integer counts add associatively, so
+    a resumed run gives the same map, bit for bit, as an uninterrupted one.
+    max_chunks stops a run after that many chunks (self.cursor then names the
+    next one; None when every chunk is done)."""
 
     def __init__(self, chunk, n_rep_max, shells_max, nside, device="cuda", dtype=torch.float32):
         self.chunk = int(chunk)
@@ -380,21 +438,56 @@ class HostStream:
         self.ws = partition_workspace(self.chunk, n_rep_max, shells_max, nside, device=self.device, cached=False)
         self.copy = torch.cuda.Stream(self.device)
         self._events = []
+        self.cursor = None
 
-    def run(self, boxes, chi_edges, nside, counts, status=None):
+    def run(self, boxes, chi_edges, nside, counts, status=None, checkpoint=None, checkpoint_every=0, resume=False,
+            max_chunks=None):
         """boxes: dicts with host (pinned) x, y, z, box_L, n_rep, shell_begin, shell_end
         (and optionally observer); every chunk is added to `counts`."""
         compute = torch.cuda.current_stream(self.device)
         free = [None, None]
         self._events = []
+        shape = {"chunk": self.chunk, "nside": int(nside), "cells": int(counts.numel()),
+                 "boxes": [int(b["x"].numel()) for b in boxes]}
+        start_box, start_off, done = 0, 0, 0
+        if resume:
+            if checkpoint is None:
+                raise ValueError("resume needs the checkpoint prefix")
+            st = load_stream_checkpoint(checkpoint)
+            if st is None:
+                raise FileNotFoundError(f"no checkpoint at {checkpoint}.json")
+            if st["shape"] != shape:
+                raise ValueError(f"checkpoint of another run: {st['shape']} != {shape}")
+            if st["counts"].size != counts.numel():
+                raise ValueError("checkpoint map size differs")
+            counts.view(torch.int32).view(-1).copy_(torch.from_numpy(st["counts"].view("int32")).view(-1))
+            if status is not None and st["status"] is not None:
+                status.copy_(torch.tensor(st["status"], dtype=status.dtype))
+            if st["next"] is None:
+                self.cursor = None
+                return counts
+            start_box, start_off = st["next"]
+            done = int(st["chunks_done"])
+
+        def save(nxt):
+            save_stream_checkpoint(checkpoint, {"shape": shape, "next": nxt, "chunks_done": done}, counts, status)
+
         j = 0
-        for b in boxes:
+        self.cursor = None
+        for bi, b in enumerate(boxes):
+            if bi < start_box:
+                continue
             hx, hy, hz = b["x"], b["y"], b["z"]
             for t in (hx, hy, hz):
                 if t.is_cuda or not t.is_pinned():
                     raise ValueError("HostStream needs pinned host tensors")
             n = hx.numel()
-            for k in range(0, n, self.chunk):
+            for k in range(start_off if bi == start_box else 0, n, self.chunk):
+                if max_chunks is not None and j >= max_chunks:
+                    self.cursor = (bi, k)
+                    if checkpoint is not None:
+                        save(list(self.cursor))
+                    return counts
                 m = min(self.chunk, n - k)
                 s = j & 1
                 ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -410,11 +503,17 @@ class HostStream:
                            observer=b.get("observer"), box_L=b["box_L"], n_rep=b["n_rep"],
                            shell_begin=b.get("shell_begin", 0), shell_end=b.get("shell_end"), counts=counts,
                            status=status, workspace=self.ws)
-                done = torch.cuda.Event()
-                done.record(compute)
-                free[s] = done
+                done_ev = torch.cuda.Event()
+                done_ev.record(compute)
+                free[s] = done_ev
                 self._events.append(ev)
                 j += 1
+                done += 1
+                if checkpoint is not None and checkpoint_every > 0 and done % checkpoint_every == 0:
+                    nxt = [bi, k + self.chunk] if k + self.chunk < n else [bi + 1, 0]
+                    save(nxt if nxt[0] < len(boxes) else None)
+        if checkpoint is not None:
+            save(None)
         return counts
 
     def copy_ms(self):

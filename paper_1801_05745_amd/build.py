@@ -26,6 +26,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-I", os.path.join(ROOT, "include"),
+    # roctx ranges around the entry points
+    "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
 ]
 
 

@@ -32,6 +32,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <fstream>
 #include <map>
 #include <mutex>
@@ -307,9 +308,25 @@ extern "C" const char *ufalcon_strerror(int code) {
         case UFALCON_EWORKSPACE: return "workspace missing, misaligned or too small";
         case UFALCON_EHIP: return "HIP runtime error";
         case UFALCON_ETOO_MANY_SHELLS: return "too many shells or source bins";
+        case UFALCON_EINJECTED: return "failure injected by UFALCON_FAULT_INJECT";
         default: return "unknown error";
     }
 }
+
+namespace ufx {
+bool fault_injected(const char *point) {
+    const char *v = std::getenv("UFALCON_FAULT_INJECT");
+    if (!v || !*v) return false;
+    const size_t n = std::strlen(point);
+    for (const char *s = v;;) {
+        const char *e = std::strchr(s, ',');
+        const size_t len = e ? (size_t)(e - s) : std::strlen(s);
+        if ((len == 1 && *s == '*') || (len == n && std::strncmp(s, point, n) == 0)) return true;
+        if (!e) return false;
+        s = e + 1;
+    }
+}
+}  // namespace ufx
 
 extern "C" int ufalcon_version(void) { return 100; }
 
@@ -319,6 +336,7 @@ extern "C" size_t ufalcon_bin_shells_workspace_size(int64_t max_listed) {
 }
 
 extern "C" int ufalcon_fill_u32(uint32_t *p, int64_t n, uint32_t value, ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_fill_u32");
     if (n < 0 || (n > 0 && !p)) return UFALCON_EINVAL;
     if (n == 0) return UFALCON_OK;
     const unsigned blocks = blocks_for(n / 4 + 1, 256 * 4, 8192);
@@ -329,6 +347,7 @@ extern "C" int ufalcon_fill_u32(uint32_t *p, int64_t n, uint32_t value, ufalcon_
 
 extern "C" int ufalcon_counts_to_i64(const uint32_t *counts, int64_t n, int64_t *out, int accumulate,
                                      ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_counts_to_i64");
     if (n < 0 || (n > 0 && (!counts || !out)) || (accumulate != 0 && accumulate != 1)) return UFALCON_EINVAL;
     if (n == 0) return UFALCON_OK;
     hipLaunchKernelGGL(widen_counts_kernel, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, as_stream(stream), counts,
@@ -369,6 +388,7 @@ extern "C" int ufalcon_bin_shells(const void *x, const void *y, const void *z, i
                                   int32_t n_shells, int32_t shell_begin, int32_t shell_end, int64_t nside,
                                   uint32_t *counts, ufalcon_status *status, void *workspace, size_t workspace_bytes,
                                   ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_bin_shells");
     return bin_shells_entry(x, y, z, n, dtype, observer, box_L, n_rep, chi_edges, n_shells, shell_begin, shell_end,
                             nside, counts, status, workspace, workspace_bytes, stream, nullptr);
 }
@@ -378,6 +398,7 @@ extern "C" int ufalcon_bin_shells_timed(const void *x, const void *y, const void
                                         int32_t n_shells, int32_t shell_begin, int32_t shell_end, int64_t nside,
                                         uint32_t *counts, ufalcon_status *status, void *workspace,
                                         size_t workspace_bytes, ufalcon_stream_t stream, ufalcon_phase_timer *timer) {
+    UFX_API_ENTRY("ufalcon_bin_shells_timed");
     if (!timer) return UFALCON_EINVAL;
     return bin_shells_entry(x, y, z, n, dtype, observer, box_L, n_rep, chi_edges, n_shells, shell_begin, shell_end,
                             nside, counts, status, workspace, workspace_bytes, stream, timer);
@@ -419,6 +440,7 @@ extern "C" int ufalcon_bin_shells_noalloc(const void *x, const void *y, const vo
                                           const double *chi_edges, int32_t n_shells, int32_t shell_begin,
                                           int32_t shell_end, int64_t nside, uint32_t *counts,
                                           ufalcon_status *status, ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_bin_shells_noalloc");
     if (dtype != UFALCON_F32 && dtype != UFALCON_F64) return UFALCON_EINVAL;
     BinParams p;
     int rc = fill_core(p.c, p.e, x, y, z, n, observer, box_L, n_rep, chi_edges, n_shells, shell_begin, shell_end,
@@ -583,6 +605,7 @@ bool json_string(const std::string &line, const char *name, std::string &v) {
 extern "C" int ufalcon_batch_plan_create(const ufalcon_batch_item *items, int32_t n_items, int dtype, int64_t nside,
                                          int32_t T, int out_dtype, int64_t tile, int32_t persistent_wgs,
                                          int32_t accumulation, ufalcon_batch_plan **plan) {
+    UFX_API_ENTRY("ufalcon_batch_plan_create");
     if (!items || n_items < 1 || !plan) return UFALCON_EINVAL;
     if (accumulation == UFALCON_ACCUMULATE_AUTO) {
         accumulation = UFALCON_ACCUMULATE_PARTITIONED;
@@ -716,12 +739,14 @@ extern "C" int ufalcon_batch_plan_create(const ufalcon_batch_item *items, int32_
 }
 
 extern "C" int ufalcon_batch_plan_destroy(ufalcon_batch_plan *plan) {
+    UFX_API_RANGE("ufalcon_batch_plan_destroy");
     if (!plan) return UFALCON_EINVAL;
     free_plan(plan);
     return UFALCON_OK;
 }
 
 extern "C" int ufalcon_batch_clear(ufalcon_batch_plan *plan, ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_batch_clear");
     if (!plan) return UFALCON_EINVAL;
     for (int32_t k = 0; k < plan->n_items; ++k) {
         const int rc = ufalcon_fill_u32(plan->count_ptrs[k], plan->count_words[k], 0u, stream);
@@ -748,6 +773,7 @@ static BatchParams batch_params(ufalcon_batch_plan *plan, ufalcon_status *status
 }
 
 extern "C" int ufalcon_bin_shells_batched(ufalcon_batch_plan *plan, ufalcon_status *status, ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_bin_shells_batched");
     if (!plan) return UFALCON_EINVAL;
     if (plan->total_tiles == 0) return UFALCON_OK;
     if (plan->accumulation == UFALCON_ACCUMULATE_PARTITIONED) {
@@ -802,11 +828,13 @@ extern "C" int ufalcon_bin_shells_batched(ufalcon_batch_plan *plan, ufalcon_stat
 }
 
 extern "C" int ufalcon_born_kappa_batched(ufalcon_batch_plan *plan, ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_born_kappa_batched");
     if (!plan || plan->T < 1) return UFALCON_EINVAL;
     return launch_born_batched(plan->d_born, plan->n_items, plan->npix, plan->T, plan->out_dtype, as_stream(stream));
 }
 
 extern "C" int ufalcon_batch_run_graph(ufalcon_batch_plan *plan, ufalcon_status *status, ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_batch_run_graph");
     if (!plan) return UFALCON_EINVAL;
     if (!plan->graph_exec || plan->graph_status != status) {
         if (plan->graph_exec) {
@@ -837,6 +865,7 @@ extern "C" int ufalcon_batch_run_graph(ufalcon_batch_plan *plan, ufalcon_status 
 extern "C" int ufalcon_batch_autotune(const ufalcon_batch_item *items, int32_t n_items, int dtype, int64_t nside,
                                       int32_t T, int out_dtype, int32_t sample_items, ufalcon_batch_tuning *tuning,
                                       ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_batch_autotune");
     if (!items || n_items < 1 || !tuning) return UFALCON_EINVAL;
     const int32_t m = sample_items > 0 ? std::min(sample_items, n_items) : n_items;
     *tuning = ufalcon_batch_tuning{};
@@ -912,6 +941,7 @@ extern "C" int ufalcon_batch_autotune(const ufalcon_batch_item *items, int32_t n
 }
 
 extern "C" int ufalcon_batch_tuning_save(const char *path) {
+    UFX_API_ENTRY("ufalcon_batch_tuning_save");
     if (!path) return UFALCON_EINVAL;
     std::lock_guard<std::mutex> lock(g_tune_mu);
     FILE *f = std::fopen(path, "w");
@@ -931,6 +961,7 @@ extern "C" int ufalcon_batch_tuning_save(const char *path) {
 }
 
 extern "C" int ufalcon_batch_tuning_load(const char *path, int32_t *n_loaded) {
+    UFX_API_ENTRY("ufalcon_batch_tuning_load");
     if (!path) return UFALCON_EINVAL;
     std::ifstream in(path);
     if (!in) return UFALCON_EHIP;

@@ -5,9 +5,9 @@
 //
 // Both are streaming passes over the uint32 count maps: about 2 FLOP per
 // 4-byte count, far below the FP64 ridge, so they are bound by HBM and MFMA
-// has no role.  Each lane owns four consecutive pixels and reads 16 bytes per
-// shell row (a wavefront reads 1 KiB contiguous per row), accumulates in FP64
-// in shell order and rounds once.  The adjoint reduces over pixels in two
+// has no role.  Each lane owns one or two quads of consecutive pixels and reads
+// 16 bytes per quad and shell row (a wavefront reads 1 KiB contiguous per quad
+// and row), accumulates in FP64 in shell order and rounds once.  The adjoint reduces over pixels in two
 // stages with a fixed partition of the pixels, so its result is bitwise
 // reproducible run to run.
 #include "../../include/ufalcon.h"
@@ -24,7 +24,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ u32x4 ld_stream_u4(const uint32_t *p) {
     return __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
 }
-constexpr int kPixPerBlock = kBornBlock * 4;
 
 struct BornParams {
     const uint32_t *counts;
@@ -36,11 +35,20 @@ struct BornParams {
     double w_inline[UFALCON_MAX_SHELLS];
 };
 
-// One block: pixels [blk * 1024, blk * 1024 + 1024) of one map.
+// Quads of pixels per lane: two for one or two source bins (more 16-byte loads in
+// flight per shell row), one for more bins (their accumulators fill the registers).
+template <int TT>
+constexpr int born_quads() { return TT <= 2 ? 2 : 1; }
+template <int TT>
+constexpr int64_t born_pix_per_block() { return (int64_t)kBornBlock * 4 * born_quads<TT>(); }
+
+// One block: pixels [blk * P, blk * P + P) of one map, P = born_pix_per_block;
+// thread i owns the quads at blk * P + 4 i + 1024 h, h < born_quads.
 template <int TT, typename OutT>
 __device__ __forceinline__ void born_block(const uint32_t *counts, int64_t npix, int B, const double *W,
                                            const double *w_inline, const double *inv_nbar, void *out, int64_t blk,
                                            double *a_s, double *c_s) {
+    constexpr int Q = born_quads<TT>();
     for (int k = threadIdx.x; k < TT * B; k += kBornBlock) {
         const int b = k % B;
         const double w = W ? W[k] : w_inline[b];
@@ -53,54 +61,76 @@ __device__ __forceinline__ void born_block(const uint32_t *counts, int64_t npix,
     }
     __syncthreads();
 
-    const int64_t p0 = (blk * kBornBlock + threadIdx.x) * 4;
-    if (p0 < npix) {
-        double acc[TT][4];
+    // npix = 12 Nside^2 is a multiple of 4: quads are whole.  A quad past the end
+    // repeats the load of the first one and is not written.
+    const int64_t first = blk * born_pix_per_block<TT>() + (int64_t)threadIdx.x * 4;
+    if (first >= npix) return;
+    int64_t pq[Q];
+    bool in[Q];
 #pragma unroll
-        for (int t = 0; t < TT; ++t)
+    for (int h = 0; h < Q; ++h) {
+        const int64_t p = first + (int64_t)h * kBornBlock * 4;
+        in[h] = p < npix;
+        pq[h] = in[h] ? p : first;
+    }
+    double acc[TT][4 * Q];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[t][j] = 0.0;
+    for (int t = 0; t < TT; ++t)
+#pragma unroll
+        for (int j = 0; j < 4 * Q; ++j) acc[t][j] = 0.0;
 
-        const uint32_t *row = counts + p0;
-        int b = 0;
-        for (; b + 4 <= B; b += 4) {
-            u32x4 v[4];
+    int b = 0;
+    for (; b + 4 <= B; b += 4) {
+        u32x4 v[4][Q];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = ld_stream_u4(row + (int64_t)(b + u) * npix);
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int h = 0; h < Q; ++h) v[u][h] = ld_stream_u4(counts + (int64_t)(b + u) * npix + pq[h]);
 #pragma unroll
-                for (int t = 0; t < TT; ++t) {
-                    const double a = a_s[t * B + b + u];
-                    acc[t][0] += a * (double)v[u].x;
-                    acc[t][1] += a * (double)v[u].y;
-                    acc[t][2] += a * (double)v[u].z;
-                    acc[t][3] += a * (double)v[u].w;
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int t = 0; t < TT; ++t) {
+                const double a = a_s[t * B + b + u];
+#pragma unroll
+                for (int h = 0; h < Q; ++h) {
+                    acc[t][4 * h + 0] += a * (double)v[u][h].x;
+                    acc[t][4 * h + 1] += a * (double)v[u][h].y;
+                    acc[t][4 * h + 2] += a * (double)v[u][h].z;
+                    acc[t][4 * h + 3] += a * (double)v[u][h].w;
                 }
             }
         }
-        for (; b < B; ++b) {
-            const u32x4 v = ld_stream_u4(row + (int64_t)b * npix);
+    }
+    for (; b < B; ++b) {
+        u32x4 v[Q];
 #pragma unroll
-            for (int t = 0; t < TT; ++t) {
-                const double a = a_s[t * B + b];
-                acc[t][0] += a * (double)v.x;
-                acc[t][1] += a * (double)v.y;
-                acc[t][2] += a * (double)v.z;
-                acc[t][3] += a * (double)v.w;
-            }
-        }
+        for (int h = 0; h < Q; ++h) v[h] = ld_stream_u4(counts + (int64_t)b * npix + pq[h]);
 #pragma unroll
         for (int t = 0; t < TT; ++t) {
-            OutT *o = static_cast<OutT *>(out) + (int64_t)t * npix + p0;
-            const double c = c_s[t];
+            const double a = a_s[t * B + b];
+#pragma unroll
+            for (int h = 0; h < Q; ++h) {
+                acc[t][4 * h + 0] += a * (double)v[h].x;
+                acc[t][4 * h + 1] += a * (double)v[h].y;
+                acc[t][4 * h + 2] += a * (double)v[h].z;
+                acc[t][4 * h + 3] += a * (double)v[h].w;
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+        const double c = c_s[t];
+#pragma unroll
+        for (int h = 0; h < Q; ++h) {
+            if (!in[h]) continue;
+            OutT *o = static_cast<OutT *>(out) + (int64_t)t * npix + pq[h];
+            const double *r = acc[t] + 4 * h;
             if constexpr (sizeof(OutT) == 4) {
-                float4 r = {(float)(acc[t][0] - c), (float)(acc[t][1] - c), (float)(acc[t][2] - c),
-                            (float)(acc[t][3] - c)};
-                *reinterpret_cast<float4 *>(o) = r;
+                float4 f = {(float)(r[0] - c), (float)(r[1] - c), (float)(r[2] - c), (float)(r[3] - c)};
+                *reinterpret_cast<float4 *>(o) = f;
             } else {
-                double2 r0 = {acc[t][0] - c, acc[t][1] - c};
-                double2 r1 = {acc[t][2] - c, acc[t][3] - c};
+                double2 r0 = {r[0] - c, r[1] - c};
+                double2 r1 = {r[2] - c, r[3] - c};
                 reinterpret_cast<double2 *>(o)[0] = r0;
                 reinterpret_cast<double2 *>(o)[1] = r1;
             }
@@ -138,10 +168,12 @@ __global__ __launch_bounds__(kBornBlock) void born_batched_kernel(const BornItem
 
 template <typename OutT>
 int launch_born_t(const BornParams &p, hipStream_t s) {
-    const unsigned grid = blocks_for(p.npix, kPixPerBlock, 1u << 30);
     switch (p.T) {
-#define UFX_BORN_CASE(k) \
-        case k: hipLaunchKernelGGL((born_kernel<k, OutT>), dim3(grid), dim3(kBornBlock), 0, s, p); break;
+#define UFX_BORN_CASE(k)                                                                            \
+        case k:                                                                                     \
+            hipLaunchKernelGGL((born_kernel<k, OutT>), dim3(blocks_for(p.npix, born_pix_per_block<k>(), 1u << 30)), \
+                               dim3(kBornBlock), 0, s, p);                                          \
+            break;
         UFX_BORN_CASE(1) UFX_BORN_CASE(2) UFX_BORN_CASE(3) UFX_BORN_CASE(4)
         UFX_BORN_CASE(5) UFX_BORN_CASE(6) UFX_BORN_CASE(7) UFX_BORN_CASE(8)
 #undef UFX_BORN_CASE
@@ -157,11 +189,14 @@ int launch_born(const BornParams &p, int out_dtype, hipStream_t s) {
 
 template <typename OutT>
 int launch_born_batched_t(const BornItemDev *items, int32_t n_items, int64_t npix, int32_t T, hipStream_t s) {
-    const int64_t bpm = (npix + kPixPerBlock - 1) / kPixPerBlock;
-    const dim3 grid((unsigned)(bpm * n_items));
     switch (T) {
-#define UFX_BORNB_CASE(k) \
-        case k: hipLaunchKernelGGL((born_batched_kernel<k, OutT>), grid, dim3(kBornBlock), 0, s, items, npix, bpm); break;
+#define UFX_BORNB_CASE(k)                                                                               \
+        case k: {                                                                                      \
+            const int64_t bpm = (npix + born_pix_per_block<k>() - 1) / born_pix_per_block<k>();       \
+            hipLaunchKernelGGL((born_batched_kernel<k, OutT>), dim3((unsigned)(bpm * n_items)), dim3(kBornBlock), 0, \
+                               s, items, npix, bpm);                                                   \
+            break;                                                                                     \
+        }
         UFX_BORNB_CASE(1) UFX_BORNB_CASE(2) UFX_BORNB_CASE(3) UFX_BORNB_CASE(4)
         UFX_BORNB_CASE(5) UFX_BORNB_CASE(6) UFX_BORNB_CASE(7) UFX_BORNB_CASE(8)
 #undef UFX_BORNB_CASE
@@ -179,7 +214,7 @@ int launch_born_batched(const BornItemDev *items, int32_t n_items, int64_t npix,
 
 // ------------------------------------------------------------------ adjoint
 constexpr int kAdjBlock = 256;
-constexpr int64_t kAdjPixPerBlock = 4096;  // fixed pixel partition of stage 1 (16384: 10 % slower)
+constexpr int64_t kAdjPixPerBlock = 2048;  // fixed pixel partition of stage 1 (4096: 5 % slower, 16384: 15 %)
 
 struct AdjParams {
     const uint32_t *counts;
@@ -206,6 +241,35 @@ __device__ __forceinline__ void load4(const GT *g, double out[4]) {
 __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+constexpr int pow2_at_least(int v) { return v <= 1 ? 1 : 2 * pow2_at_least((v + 1) / 2); }
+
+// Sum of each of P (a power of two <= 64) per-lane values over the wave, spread
+// over the lanes: every step exchanges half of the remaining values with the
+// lane `off` away and keeps the half its lane bit selects (P/2 + P/4 + ... + 1
+// shuffles instead of 6 per value), then xor steps over the lane bits left
+// complete the sums.  Lane L returns the sum of value L >> (6 - log2 P).  The
+// tree is fixed, so the result is the same on every run.
+template <int P, int kOff = 32>
+__device__ __forceinline__ double wave_reduce_scatter(double *v) {
+    if constexpr (P > 1) {
+        constexpr int n = P / 2;
+        const bool upper = (threadIdx.x & kOff) != 0;
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+            const double send = upper ? v[k] : v[k + n];
+            const double keep = upper ? v[k + n] : v[k];
+            v[k] = keep + __shfl_xor(send, kOff, 64);
+        }
+        return wave_reduce_scatter<n, kOff / 2>(v);
+    } else {
+        double r = v[0];
+#pragma unroll
+        for (int off = kOff; off >= 1; off >>= 1) r += __shfl_xor(r, off, 64);
+        return r;
+    }
 }
 
 // Stage 1: block (chunk c, pixel range gblk) accumulates S1[t][b] for the shells of
@@ -246,18 +310,19 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_stage1(AdjParams p) {
             }
         }
     }
-    // Every sum over the wave first (the same xor tree for all), then over the
-    // waves in order, all behind one barrier.
+    // Every sum over the wave first (one fixed reduce-scatter tree), then over
+    // the waves in order, all behind one barrier.
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int P = pow2_at_least(TT * SB);
+    constexpr int kSh = 6 - ilog2(P);
+    static_assert(P <= 64, "one value per lane at most");
+    double vals[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) vals[i] = i < TT * SB ? acc[i / SB][i % SB] : 0.0;
+    const double r = wave_reduce_scatter<P>(vals);
+    if ((lane & ((1 << kSh) - 1)) == 0 && (lane >> kSh) < TT * SB) red[w][lane >> kSh] = r;
 #pragma unroll
     for (int t = 0; t < TT; ++t) {
-#pragma unroll
-        for (int k = 0; k < SB; ++k) {
-            if (k < nb) {
-                const double v = wave_sum(acc[t][k]);
-                if (lane == 0) red[w][t * SB + k] = v;
-            }
-        }
         const double v0 = wave_sum(acc0[t]);
         if (lane == 0) red[w][TT * SB + t] = v0;
     }
@@ -345,6 +410,7 @@ static int check_born_common(const uint32_t *counts, int32_t n_shells, int64_t n
 extern "C" int ufalcon_born_kappa(const uint32_t *counts, int32_t n_shells, int64_t nside, const double *W,
                                   const double *inv_nbar, int32_t T, void *kappa, int out_dtype,
                                   ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_born_kappa");
     int rc = check_born_common(counts, n_shells, nside, T);
     if (rc) return rc;
     if (!W || !inv_nbar || !kappa || (out_dtype != UFALCON_F32 && out_dtype != UFALCON_F64)) return UFALCON_EINVAL;
@@ -362,6 +428,7 @@ extern "C" int ufalcon_born_kappa(const uint32_t *counts, int32_t n_shells, int6
 
 extern "C" int ufalcon_overdensity(const uint32_t *counts, int32_t n_shells, int64_t nside, const double *chi_edges,
                                    const double *inv_nbar, void *delta, int out_dtype, ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_overdensity");
     int rc = check_born_common(counts, n_shells, nside, 1);
     if (rc) return rc;
     if ((rc = check_edges(chi_edges, n_shells))) return rc;
@@ -390,6 +457,7 @@ extern "C" int ufalcon_born_kappa_adjoint(const uint32_t *counts, int32_t n_shel
                                           const double *inv_nbar, const void *grad_kappa, int grad_dtype, int32_t T,
                                           double *grad_W, void *workspace, size_t workspace_bytes,
                                           ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_born_kappa_adjoint");
     int rc = check_born_common(counts, n_shells, nside, T);
     if (rc) return rc;
     if (!inv_nbar || !grad_kappa || !grad_W || (grad_dtype != UFALCON_F32 && grad_dtype != UFALCON_F64))

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cmath>
 #include <cstdint>
@@ -17,6 +18,24 @@ namespace ufx {
     } while (0)
 
 inline hipStream_t as_stream(ufalcon_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+// roctx range around one entry point call.
+struct ApiRange {
+    explicit ApiRange(const char *name) { roctxRangePushA(name); }
+    ~ApiRange() { roctxRangePop(); }
+    ApiRange(const ApiRange &) = delete;
+    ApiRange &operator=(const ApiRange &) = delete;
+};
+
+// True when UFALCON_FAULT_INJECT names `point` (defined in bin_shells.hip).
+bool fault_injected(const char *point);
+
+// First statement of an entry point that returns a status.
+#define UFX_API_ENTRY(name)                 \
+    ::ufx::ApiRange ufx_api_range_(name);  \
+    if (::ufx::fault_injected(name)) return UFALCON_EINJECTED
+// First statement of a destroy call: traced, never failed.
+#define UFX_API_RANGE(name) ::ufx::ApiRange ufx_api_range_(name)
 
 inline int check_edges(const double *e, int32_t n_shells) {
     if (!e) return UFALCON_EINVAL;

@@ -1322,6 +1322,7 @@ extern "C" size_t ufalcon_map2alm_workspace_size(int64_t nside, int32_t lmax) {
 
 extern "C" int ufalcon_map2alm(const void *maps, int dtype, int32_t n_maps, int64_t nside, int32_t lmax, double *alm,
                                void *workspace, size_t workspace_bytes, ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_map2alm");
     int rc = check_nside(nside);
     if (rc) return rc;
     if (n_maps < 0 || lmax < 0 || lmax > kMaxLmax) return UFALCON_EINVAL;
@@ -1364,6 +1365,7 @@ extern "C" int ufalcon_map2alm(const void *maps, int dtype, int32_t n_maps, int6
 }
 
 extern "C" int ufalcon_alm2cl(const double *alm, int32_t n_maps, int32_t lmax, double *cl, ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_alm2cl");
     if (n_maps < 0 || lmax < 0 || lmax > kMaxLmax) return UFALCON_EINVAL;
     if (n_maps == 0) return UFALCON_OK;
     if (!alm || !cl) return UFALCON_EINVAL;
@@ -1382,6 +1384,7 @@ extern "C" size_t ufalcon_cl_covariance_workspace_size(int32_t n_real, int32_t n
 extern "C" int ufalcon_cl_covariance(const double *cl, int32_t n_real, int32_t n_ell, int32_t ell_min,
                                      int32_t delta_ell, int32_t n_bands, int32_t ddof, double *band_mean, double *cov,
                                      double *corr, void *workspace, size_t workspace_bytes, ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_cl_covariance");
     if (!cl || !band_mean || !cov || !workspace) return UFALCON_EINVAL;
     if (n_real < 1 || n_ell < 1 || ell_min < 0 || delta_ell < 1 || n_bands < 1) return UFALCON_EINVAL;
     if (ddof != 0 && ddof != 1) return UFALCON_EINVAL;
@@ -1410,6 +1413,7 @@ extern "C" int ufalcon_cl_covariance(const double *cl, int32_t n_real, int32_t n
 }
 
 extern "C" int ufalcon_gaussian_beam(double sigma, int32_t lmax, double *beam, ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_gaussian_beam");
     if (!beam || lmax < 0 || lmax > kMaxLmax || !std::isfinite(sigma) || sigma < 0.0) return UFALCON_EINVAL;
     hipLaunchKernelGGL(gaussian_beam_kernel, dim3(blocks_for((int64_t)lmax + 1, 256)), dim3(256), 0,
                        as_stream(stream), sigma, lmax, beam);
@@ -1425,6 +1429,7 @@ extern "C" size_t ufalcon_alm2map_workspace_size(int64_t nside, int32_t lmax) {
 extern "C" int ufalcon_alm2map(const double *alm, int32_t n_maps, int64_t nside, int32_t lmax, const double *beam,
                                void *maps, int dtype, void *workspace, size_t workspace_bytes,
                                ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_alm2map");
     int rc = check_nside(nside);
     if (rc) return rc;
     if (n_maps < 0 || lmax < 0 || lmax > kMaxLmax) return UFALCON_EINVAL;
@@ -1466,6 +1471,7 @@ extern "C" size_t ufalcon_map_moments_workspace_size(int32_t n_maps) {
 
 extern "C" int ufalcon_map_moments(const void *maps, int dtype, int32_t n_maps, int64_t npix, double *moments,
                                    void *workspace, size_t workspace_bytes, ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_map_moments");
     if (n_maps < 0 || npix < 1) return UFALCON_EINVAL;
     if (dtype != UFALCON_F32 && dtype != UFALCON_F64) return UFALCON_EINVAL;
     if (n_maps == 0) return UFALCON_OK;

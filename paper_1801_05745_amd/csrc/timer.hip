@@ -39,6 +39,7 @@ void timer_mark(ufalcon_phase_timer *t, int phase, hipStream_t s) {
 }  // namespace ufx
 
 extern "C" int ufalcon_phase_timer_create(ufalcon_phase_timer **timer) {
+    UFX_API_ENTRY("ufalcon_phase_timer_create");
     if (!timer) return UFALCON_EINVAL;
     *timer = nullptr;
     auto *t = new (std::nothrow) ufalcon_phase_timer();
@@ -57,6 +58,7 @@ extern "C" int ufalcon_phase_timer_create(ufalcon_phase_timer **timer) {
 }
 
 extern "C" int ufalcon_phase_timer_destroy(ufalcon_phase_timer *timer) {
+    UFX_API_RANGE("ufalcon_phase_timer_destroy");
     if (!timer) return UFALCON_OK;
     int rc = UFALCON_OK;
     for (int i = 0; i < UFALCON_TIMER_EVENTS; ++i)
@@ -66,6 +68,7 @@ extern "C" int ufalcon_phase_timer_destroy(ufalcon_phase_timer *timer) {
 }
 
 extern "C" int ufalcon_phase_timer_read(ufalcon_phase_timer *timer, double *ms) {
+    UFX_API_ENTRY("ufalcon_phase_timer_read");
     if (!timer || !ms || timer->used < 1) return UFALCON_EINVAL;
     for (int k = 0; k < UFALCON_NPHASES; ++k) ms[k] = 0.0;
     if (hipEventSynchronize(timer->ev[timer->used - 1]) != hipSuccess) return UFALCON_EHIP;

@@ -313,6 +313,7 @@ using namespace ufx;
 
 extern "C" int ufalcon_comoving_distance(const double *z, int64_t n, double omega_m, double *chi,
                                          ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_comoving_distance");
     if (n < 0 || (n > 0 && (!z || !chi)) || !std::isfinite(omega_m) || omega_m < 0.0 || omega_m > 1.0)
         return UFALCON_EINVAL;
     if (n == 0) return UFALCON_OK;
@@ -325,6 +326,7 @@ extern "C" int ufalcon_comoving_distance(const double *z, int64_t n, double omeg
 extern "C" int ufalcon_lensing_weights(double omega_m, const ufalcon_source *sources, int32_t T,
                                        const double *chi_edges, int32_t n_shells, double *W, double *dW,
                                        ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_lensing_weights");
     if (!sources || !W || T < 1) return UFALCON_EINVAL;
     if (T > UFALCON_MAX_BINS) return UFALCON_ETOO_MANY_SHELLS;
     if (!std::isfinite(omega_m) || !(omega_m > 0.0) || omega_m > 1.0) return UFALCON_EINVAL;
@@ -365,6 +367,7 @@ extern "C" int ufalcon_lensing_weights(double omega_m, const ufalcon_source *sou
 
 extern "C" int ufalcon_lensing_weights_vjp(const double *dW, const double *grad_W, int32_t T, int32_t n_shells,
                                            double *grad_theta, ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_lensing_weights_vjp");
     if (!dW || !grad_W || !grad_theta || T < 1 || n_shells < 1) return UFALCON_EINVAL;
     if (T > UFALCON_MAX_BINS || n_shells > UFALCON_MAX_SHELLS) return UFALCON_ETOO_MANY_SHELLS;
     hipLaunchKernelGGL(weights_vjp_kernel, dim3(1), dim3(64), 0, as_stream(stream), dW, grad_W, T, n_shells,
@@ -376,6 +379,7 @@ extern "C" int ufalcon_lensing_weights_vjp(const double *dW, const double *grad_
 extern "C" int ufalcon_inv_nbar(int64_t n_src, double box_L, const double *chi_edges, int32_t n_shells,
                                 int32_t shell_begin, int32_t shell_end, int64_t nside, int32_t mode,
                                 double *inv_nbar, ufalcon_stream_t stream) {
+    UFX_API_ENTRY("ufalcon_inv_nbar");
     if (n_src <= 0 || !std::isfinite(box_L) || !(box_L > 0.0) || !inv_nbar) return UFALCON_EINVAL;
     if (mode != UFALCON_NBAR_EXACT_VOLUME && mode != UFALCON_NBAR_LOWER_EDGE) return UFALCON_EINVAL;
     int rc = check_edges(chi_edges, n_shells);

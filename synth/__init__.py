@@ -110,8 +110,11 @@ def lognormal_box(n: int, L: float, seed: int, ngrid: int = 256, sigma_ln: float
     order="shuffled" keeps the random draw order; order="cell" sorts by cell.
     """
     rho = lognormal_field(ngrid, seed, sigma_ln, device=device).reshape(-1)
-    cdf = torch.cumsum(rho, 0)
-    cdf = cdf / cdf[-1]
+    # the CDF is summed on the host: a device scan may combine its partial sums
+    # in a timing-dependent order, and a last-bit change of the CDF moves a
+    # particle to another cell now and then
+    cdf = torch.cumsum(rho.cpu(), 0)
+    cdf = (cdf / cdf[-1]).to(device)
     xs = torch.empty(n, dtype=dtype, device=device)
     ys = torch.empty(n, dtype=dtype, device=device)
     zs = torch.empty(n, dtype=dtype, device=device)

@@ -226,3 +226,47 @@ def test_tuning_file_round_trip(tmp_path):
         uf.load_tuning(str(bad))
     with pytest.raises(uf.UfalconError):
         uf.load_tuning(str(tmp_path / "missing.json"))
+
+
+def test_fault_injection_switch(monkeypatch):
+    """UFALCON_FAULT_INJECT fails the named entry points before any validation."""
+    lib = uf.load()
+    assert lib.ufalcon_strerror(-8).decode().startswith("failure injected")
+    monkeypatch.delenv("UFALCON_FAULT_INJECT", raising=False)
+    assert lib.ufalcon_fill_u32(None, 1, 0, None) == -1           # plain validation
+    assert _bin(edges=(1.0, 1.0)) == -2
+    monkeypatch.setenv("UFALCON_FAULT_INJECT", "ufalcon_bin_shells,ufalcon_fill_u32")
+    assert lib.ufalcon_fill_u32(None, 1, 0, None) == -8
+    assert _bin(edges=(1.0, 1.0)) == -8                          # injected before the edges are read
+    assert lib.ufalcon_alm2cl(None, -1, 0, None, None) == -1      # not named: validated as usual
+    monkeypatch.setenv("UFALCON_FAULT_INJECT", "ufalcon_bin")     # a prefix names nothing
+    assert _bin(edges=(1.0, 1.0)) == -2
+    monkeypatch.setenv("UFALCON_FAULT_INJECT", "*")
+    assert lib.ufalcon_alm2cl(None, -1, 0, None, None) == -8
+    assert lib.ufalcon_phase_timer_destroy(None) == 0             # destroy calls are never failed
+    with pytest.raises(uf.UfalconError) as err:
+        uf._check(lib.ufalcon_fill_u32(None, 1, 0, None), "ufalcon_fill_u32")
+    assert err.value.code == -8 and "injected" in str(err.value)
+    monkeypatch.setenv("UFALCON_FAULT_INJECT", "")
+    assert lib.ufalcon_fill_u32(None, 1, 0, None) == -1
+
+
+def test_stream_checkpoint_files(tmp_path):
+    """The resumable state of a chunked run: one whole state on disk at any time."""
+    import numpy as np
+    import torch
+
+    prefix = tmp_path / "run"
+    assert uf.load_stream_checkpoint(prefix) is None
+    counts = torch.arange(24, dtype=torch.int64).to(torch.int32).view(torch.uint32).reshape(2, 12)
+    status = torch.tensor([5, 0, 1, 0, 0], dtype=torch.int64)
+    uf.save_stream_checkpoint(prefix, {"shape": {"chunk": 8}, "next": [0, 8], "chunks_done": 1}, counts, status)
+    st = uf.load_stream_checkpoint(prefix)
+    assert st["next"] == [0, 8] and st["chunks_done"] == 1 and st["status"] == [5, 0, 1, 0, 0]
+    assert st["counts"].dtype == np.uint32 and np.array_equal(st["counts"], np.arange(24).reshape(2, 12))
+    counts2 = (torch.arange(24, dtype=torch.int64) * 3).to(torch.int32).view(torch.uint32).reshape(2, 12)
+    uf.save_stream_checkpoint(prefix, {"shape": {"chunk": 8}, "next": None, "chunks_done": 2}, counts2, None)
+    st = uf.load_stream_checkpoint(prefix)
+    assert st["next"] is None and st["status"] is None
+    assert np.array_equal(st["counts"], 3 * np.arange(24).reshape(2, 12))
+    assert sorted(p.name for p in tmp_path.iterdir()) == ["run.2.npy", "run.json"]   # the older map is gone

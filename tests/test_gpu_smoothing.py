@@ -62,6 +62,13 @@ def test_gaussian_beam(ufalcon):
     (1024, 1023, [0, 1, 500, 1023, 1024, 2047, 2048, 3000, 4094]),
     (2048, 300, [0, 7, 2047, 4095, 8190]),        # several ring-pair blocks
     (513, 400, [0, 1, 2, 255, 256, 511, 512, 1025, 1536, 2049, 2050]),  # odd Nside, both polar parities
+    # 4 | Nside, 8 does not: the 4-class equatorial inverse, 4400-pixel rings in many chunks
+    (1100, 500, [0, 1, 600, 1098, 1099, 1100, 2199, 3298, 3299, 3300, 4398]),
+    # Nside = 2 x odd: the 2-class equatorial inverse
+    (1026, 500, [0, 1, 1024, 1025, 1026, 2050, 3074, 3075, 3076, 4102]),
+    # odd polar rings i = 601 and 1023 (ring index i from 1), which span several
+    # workgroups along the ring, and their southern mirrors 4 Nside - i
+    (1024, 1023, [600, 1022, 3072, 3494]),
 ])
 def test_alm2map_sampled_rings(ufalcon, nside, lmax, rings):
     full = _alm(lmax, seed=nside + lmax)

@@ -169,3 +169,28 @@ def test_shell_totals_edge_particles_and_range():
     assert st["flagged"] == 5
     tot12, _ = bn.shell_totals(xs, ys, zs, obs, 100.0, 0, edges, shell_begin=1, shell_end=3)
     assert tot12.tolist() == [1, 2]
+
+
+def test_chunked_run_resumed_from_checkpoint(tmp_path):
+    # an interrupted chunked run, saved and resumed through the library's checkpoint
+    # files, gives the map of the uninterrupted run: integer counts add associatively
+    import torch
+
+    import paper_1801_05745_amd as uf
+
+    L = 50.0
+    x, y, z = synth.lognormal_box(20000, L, seed=6, ngrid=16)
+    edges = [5.0, 15.0, 25.0, 40.0]
+    obs = (25.0, 25.0, 25.0)
+    whole, _ = bn.bin_shells(x, y, z, obs, L, 1, edges, 4)
+    chunk, prefix = 6000, tmp_path / "run"
+    acc = np.zeros_like(whole)
+    for k in range(0, 12000, chunk):
+        acc += bn.bin_shells(x[k:k + chunk], y[k:k + chunk], z[k:k + chunk], obs, L, 1, edges, 4)[0]
+    uf.save_stream_checkpoint(prefix, {"shape": {}, "next": [0, 12000], "chunks_done": 2},
+                              torch.from_numpy(acc.astype(np.int32)).view(torch.uint32))
+    st = uf.load_stream_checkpoint(prefix)
+    acc = st["counts"].astype(np.int64)
+    for k in range(st["next"][1], len(x), chunk):
+        acc += bn.bin_shells(x[k:k + chunk], y[k:k + chunk], z[k:k + chunk], obs, L, 1, edges, 4)[0]
+    assert np.array_equal(acc, whole)
