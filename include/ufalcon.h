@@ -175,10 +175,13 @@ int ufalcon_bin_shells_noalloc(const void *x, const void *y, const void *z, int6
  *   EXACT       exact decisions of guarded instances (and the rescue pass)
  * ufalcon_phase_timer_read waits for the last recorded event and writes the
  * milliseconds of each phase, summed over chunks, to ms[UFALCON_NPHASES].
+ * ufalcon_phase_timer_intervals writes how many intervals each phase's sum
+ * covers to counts[UFALCON_NPHASES] (DECIDE: one per key-pass launch, i.e. per
+ * chunk of a partitioned call), without waiting.
  * A timer serves one call at a time; each timed call replaces the previous
- * record.  Errors: EINVAL (null timer / ms, or read before any timed call),
- * EOVERFLOW (more than UFALCON_TIMER_EVENTS events were needed: the record is
- * incomplete), EHIP.
+ * record.  Errors: EINVAL (null timer / ms / counts, or read before any timed
+ * call), EOVERFLOW (more than UFALCON_TIMER_EVENTS events were needed: the
+ * record is incomplete), EHIP.
  */
 #define UFALCON_TIMER_EVENTS 256
 enum {
@@ -199,6 +202,7 @@ int ufalcon_bin_shells_timed(const void *x, const void *y, const void *z, int64_
                              void *workspace, size_t workspace_bytes, ufalcon_stream_t stream,
                              ufalcon_phase_timer *timer);
 int ufalcon_phase_timer_read(ufalcon_phase_timer *timer, double *ms);
+int ufalcon_phase_timer_intervals(const ufalcon_phase_timer *timer, int32_t *counts);
 
 /* Source redshift distributions for the lensing weights. */
 typedef enum ufalcon_source_kind { UFALCON_SOURCE_DELTA = 0, UFALCON_SOURCE_SMAIL = 1 } ufalcon_source_kind;

@@ -84,6 +84,7 @@ _SIGS = {
     "ufalcon_phase_timer_create": (ctypes.c_int, [ctypes.POINTER(_P)]),
     "ufalcon_phase_timer_destroy": (ctypes.c_int, [_P]),
     "ufalcon_phase_timer_read": (ctypes.c_int, [_P, ctypes.POINTER(_D)]),
+    "ufalcon_phase_timer_intervals": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "ufalcon_comoving_distance": (ctypes.c_int, [_P, _I64, _D, _P, _P]),
     "ufalcon_lensing_weights": (ctypes.c_int, [_D, ctypes.POINTER(Source), _I32, ctypes.POINTER(_D), _I32,
                                                _P, _P, _P]),
@@ -278,6 +279,12 @@ class PhaseTimer:
         ms = (ctypes.c_double * len(PHASES))()
         _check(load().ufalcon_phase_timer_read(self._h, ms), "ufalcon_phase_timer_read")
         return dict(zip(PHASES, list(ms)))
+
+    def intervals(self):
+        """How many intervals each phase's sum covers (decide: key-pass launches)."""
+        c = (ctypes.c_int32 * len(PHASES))()
+        _check(load().ufalcon_phase_timer_intervals(self._h, c), "ufalcon_phase_timer_intervals")
+        return dict(zip(PHASES, list(c)))
 
     def close(self):
         if self._h is not None and self._h.value:

@@ -341,22 +341,40 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_stage1(AdjParams p) {
 }
 
 // Stage 2: grad_W[t][b] = inv_nbar[b] * sum_blocks S1 - sum_blocks S0.  One workgroup
-// per (t, b); thread j sums blocks j, j + 256, ... in order, then a fixed-shape tree
-// over the 256 partial sums: the same order on every run.
-__global__ __launch_bounds__(256) void adjoint_stage2(const double *partial, const double *partial0, int64_t G,
-                                                      int32_t T, int32_t B, const double *inv_nbar, double *grad_W) {
-    __shared__ double r1[256], r0[256];
+// per (t, b); thread j sums blocks j, j + 1024, ... in that order (four loads in
+// flight), then a fixed-shape tree over the 1024 partial sums: the same order on
+// every run.
+constexpr int kS2Threads = 1024;
+__global__ __launch_bounds__(kS2Threads) void adjoint_stage2(const double *partial, const double *partial0, int64_t G,
+                                                             int32_t T, int32_t B, const double *inv_nbar,
+                                                             double *grad_W) {
+    __shared__ double r1[kS2Threads], r0[kS2Threads];
     const int k = blockIdx.x;
     const int t = k / B, b = k % B;
+    const int64_t TB = (int64_t)T * B;
     double s1 = 0.0, s0 = 0.0;
-    for (int64_t i = threadIdx.x; i < G; i += 256) {
-        s1 += partial[i * (int64_t)T * B + k];
+    int64_t i = threadIdx.x;
+    for (; i + 3 * kS2Threads < G; i += 4 * kS2Threads) {
+        double a[4], c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = partial[(i + u * kS2Threads) * TB + k];
+            c[u] = partial0[(i + u * kS2Threads) * T + t];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            s1 += a[u];
+            s0 += c[u];
+        }
+    }
+    for (; i < G; i += kS2Threads) {
+        s1 += partial[i * TB + k];
         s0 += partial0[i * T + t];
     }
     r1[threadIdx.x] = s1;
     r0[threadIdx.x] = s0;
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
+    for (int off = kS2Threads / 2; off > 0; off >>= 1) {
         if (threadIdx.x < off) {
             r1[threadIdx.x] += r1[threadIdx.x + off];
             r0[threadIdx.x] += r0[threadIdx.x + off];
@@ -478,8 +496,8 @@ extern "C" int ufalcon_born_kappa_adjoint(const uint32_t *counts, int32_t n_shel
     hipStream_t s = as_stream(stream);
     rc = grad_dtype == UFALCON_F32 ? launch_adj<float>(p, s) : launch_adj<double>(p, s);
     if (rc) return rc;
-    hipLaunchKernelGGL(adjoint_stage2, dim3(T * n_shells), dim3(256), 0, s, p.partial, p.partial0, p.G, T, n_shells,
-                       inv_nbar, grad_W);
+    hipLaunchKernelGGL(adjoint_stage2, dim3(T * n_shells), dim3(kS2Threads), 0, s, p.partial, p.partial0, p.G, T,
+                       n_shells, inv_nbar, grad_W);
     UFX_HIP_CHECK(hipGetLastError());
     return UFALCON_OK;
 }

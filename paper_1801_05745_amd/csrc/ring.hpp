@@ -31,26 +31,45 @@ UFX_HD double floor_margin(double Nd) { return Nd * 0x1p-38; }
 // Newton step, which squares its relative error.  The estimates are good to
 // 2^-23.2 (rsq) and 2^-24.4 (rcp), measured over 2^24 seeded inputs spanning
 // 121 binades on gfx950, so the refined values are good to ~2^-46; even an
-// estimate of only 2^-20 would leave 2^-40, inside the floor margin.  The host
-// build uses IEEE operations.
-UFX_FN double rsqrt_nr(double x) {
+// estimate of only 2^-20 would leave ~2^-40, inside the floor margin.  A host
+// build uses the IEEE values as the estimates, or, in a test build that defines
+// UFX_HOST_ESTIMATE_MODEL, estimates with a relative error the test sets, so
+// that the refinement and the margin are checked on the CPU too.
+#if !defined(__HIP_DEVICE_COMPILE__) && defined(UFX_HOST_ESTIMATE_MODEL)
+double host_rsq_estimate(double x);
+double host_rcp_estimate(double x);
+#endif
+
+UFX_FN double rsq_estimate(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    const double y = __builtin_amdgcn_rsq(x);
-    const double e = fma(-(x * y), y, 1.0);  // 1 - x y^2
-    return fma(0.5 * e, y, y);
+    return __builtin_amdgcn_rsq(x);
+#elif defined(UFX_HOST_ESTIMATE_MODEL)
+    return host_rsq_estimate(x);
 #else
     return 1.0 / sqrt(x);
 #endif
 }
 
-UFX_FN double rcp_nr(double d) {
+UFX_FN double rcp_estimate(double d) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    const double r = __builtin_amdgcn_rcp(d);
-    const double e = fma(-d, r, 1.0);  // 1 - d r
-    return fma(r, e, r);
+    return __builtin_amdgcn_rcp(d);
+#elif defined(UFX_HOST_ESTIMATE_MODEL)
+    return host_rcp_estimate(d);
 #else
     return 1.0 / d;
 #endif
+}
+
+UFX_FN double rsqrt_nr(double x) {
+    const double y = rsq_estimate(x);
+    const double e = fma(-(x * y), y, 1.0);  // 1 - x y^2
+    return fma(0.5 * e, y, y);
+}
+
+UFX_FN double rcp_nr(double d) {
+    const double r = rcp_estimate(d);
+    const double e = fma(-d, r, 1.0);  // 1 - d r
+    return fma(r, e, r);
 }
 
 UFX_FN bool clear_of_integer(double v, double eps, double &fl) {

@@ -80,3 +80,14 @@ extern "C" int ufalcon_phase_timer_read(ufalcon_phase_timer *timer, double *ms) 
     }
     return timer->overflow ? UFALCON_EOVERFLOW : UFALCON_OK;
 }
+
+extern "C" int ufalcon_phase_timer_intervals(const ufalcon_phase_timer *timer, int32_t *counts) {
+    UFX_API_ENTRY("ufalcon_phase_timer_intervals");
+    if (!timer || !counts || timer->used < 1) return UFALCON_EINVAL;
+    for (int k = 0; k < UFALCON_NPHASES; ++k) counts[k] = 0;
+    for (int i = 1; i < timer->used; ++i) {
+        const int ph = timer->phase[i];
+        if (ph >= 0 && ph < UFALCON_NPHASES) ++counts[ph];
+    }
+    return timer->overflow ? UFALCON_EOVERFLOW : UFALCON_OK;
+}

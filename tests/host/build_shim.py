@@ -12,6 +12,8 @@ def build():
     deps = [src] + [os.path.join(HERE, "..", "..", "paper_1801_05745_amd", "csrc", f) for f in ("exact.hpp", "ring.hpp", "common.hpp")]
     if os.path.exists(OUT) and all(os.path.getmtime(OUT) >= os.path.getmtime(d) for d in deps):
         return OUT
+    tmp = f"{OUT}.{os.getpid()}.tmp"
     subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC",
-                    src, "-o", OUT], check=True)
+                    src, "-o", tmp], check=True)
+    os.replace(tmp, OUT)
     return OUT

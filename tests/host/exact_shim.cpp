@@ -1,12 +1,37 @@
 // Host build of the library's device-side decision code (exact.hpp, ring.hpp)
 // so that its logic can be checked against the oracle on a machine without a GPU.
 #define UFX_HOST_BUILD 1
+#define UFX_HOST_ESTIMATE_MODEL 1
+#include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "../../paper_1801_05745_amd/csrc/exact.hpp"
 #include "../../paper_1801_05745_amd/csrc/ring.hpp"
 
+// Model of the device's reciprocal estimates: the IEEE value times (1 + s e),
+// with e and the sign s set by the test (s = 0: a sign from the input's bits).
+static double g_est_err = 0.0;
+static int g_est_sign = 1;
+static double perturb(double exact, double x) {
+    int s = g_est_sign;
+    if (s == 0) {
+        uint64_t b;
+        std::memcpy(&b, &x, sizeof b);
+        b ^= b >> 29;
+        b *= 0xBF58476D1CE4E5B9ull;
+        s = ((b >> 61) & 1) ? 1 : -1;
+    }
+    return exact * (1.0 + s * g_est_err);
+}
+double ufx::host_rsq_estimate(double x) { return perturb(1.0 / std::sqrt(x), x); }
+double ufx::host_rcp_estimate(double x) { return perturb(1.0 / x, x); }
+
 extern "C" {
+void shim_set_estimate_error(double err, int sign) {
+    g_est_err = err;
+    g_est_sign = sign;
+}
 int64_t shim_exact_ring_pixel(int64_t nside, double dx, double dy, double dz, int *unresolved) {
     *unresolved = 0;
     return ufx::exact_ring_pixel(nside, dx, dy, dz, unresolved);

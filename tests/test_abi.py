@@ -93,6 +93,7 @@ def test_phase_timer_validation():
     lib = uf.load()
     ms = (ctypes.c_double * 5)()
     assert lib.ufalcon_phase_timer_read(None, ms) == -1
+    assert lib.ufalcon_phase_timer_intervals(None, (ctypes.c_int32 * 5)()) == -1
     assert lib.ufalcon_phase_timer_create(None) == -1
     assert lib.ufalcon_phase_timer_destroy(None) == 0
     e = (ctypes.c_double * 2)(0.0, 1.0)

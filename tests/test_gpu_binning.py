@@ -175,8 +175,13 @@ def test_phase_timer_records_phases_without_changing_counts(ufalcon, method):
     assert set(ms) == set(uf.PHASES)
     assert all(v >= 0.0 for v in ms.values())
     assert ms["decide"] > 0.0
+    iv = timer.intervals()
+    assert set(iv) == set(uf.PHASES) and iv["setup"] == 1 and iv["exact"] == 1
     if method == "atomic":
         assert ms["partition"] == 0.0 and ms["accumulate"] == 0.0
+        assert iv["decide"] == 1 and iv["partition"] == 0
     else:
         assert ms["partition"] > 0.0 and ms["accumulate"] > 0.0
+        # one key pass, partition and accumulation per chunk
+        assert iv["decide"] >= 1 and iv["partition"] == iv["decide"] == iv["accumulate"]
     timer.close()

@@ -43,6 +43,8 @@ def lib():
         _lib.shim_tt.argtypes = [ctypes.c_double, ctypes.c_double]
         _lib.shim_fast_tt.restype = ctypes.c_double
         _lib.shim_fast_tt.argtypes = [ctypes.c_double, ctypes.c_double]
+        _lib.shim_set_estimate_error.restype = None
+        _lib.shim_set_estimate_error.argtypes = [ctypes.c_double, ctypes.c_int]
     return _lib
 
 
@@ -227,3 +229,64 @@ def test_workload_edges_use_the_shell_table():
         lo2, hi2 = _prefilter_range(edges)
         c = ctypes.c_int(0)
         assert lib().shim_fast_shell(e2, nb, 0.5 * (lo2 + hi2), ctypes.byref(c), 1, lo2, hi2) != -100, nb
+
+
+def _boundary_points(nside, delta, seed, n=400):
+    """Directions whose floor arguments lie `delta` (argument units) from an integer:
+    the belt's lines N(1/2 + tt) -/+ (3/4) N z = j and the caps' lines u sigma = j and
+    (1 - u) sigma = j (sigma = N sqrt(3 (1 - |z|)), u = tt - floor(tt))."""
+    rng = random.Random(seed)
+    N = nside
+    pts = []
+    for _ in range(n):
+        d = rng.choice((delta, -delta))
+        z = rng.uniform(-0.6, 0.6)
+        s = rng.choice((-1.0, 1.0))
+        tt = (rng.randrange(0, 4 * N) + d + s * 0.75 * N * z) / N - 0.5
+        if 0.0 <= tt < 4.0:
+            pts.append(_unit(z, tt * math.pi / 2))
+        z = rng.uniform(0.7, 0.999)
+        sigma = N * math.sqrt(3.0 * (1.0 - z))
+        if sigma > 1.5:
+            j = rng.randrange(1, int(sigma))
+            u = (j + d) / sigma if rng.random() < 0.5 else 1.0 - (j + d) / sigma
+            if 0.0 < u < 1.0:
+                pts.append(_unit(z if rng.random() < 0.5 else -z, (rng.randrange(4) + u) * math.pi / 2))
+    return pts
+
+
+def _fast_against_exact(nside, pts):
+    wrong = accepted = 0
+    for v in pts:
+        f = fast_pix(nside, v)
+        if f is None:
+            continue
+        accepted += 1
+        p, unres = exact_pix(nside, v)
+        assert unres == 0
+        wrong += f != p
+    return wrong, accepted
+
+
+@pytest.mark.parametrize("nside", [64, 1024, 8192])
+def test_reciprocal_estimates_refined_inside_the_margin(nside):
+    # The device takes 1/sqrt and 1/x from hardware estimates (measured good to
+    # 2^-23.2 and 2^-24.4) plus one Newton step.  Modelled here with estimates off
+    # by 2^-20 of either sign, the fast path still agrees with the exact pixel or
+    # defers on directions 8 margins (N 2^-35) from a floor boundary; estimates
+    # off by 2^-14 (no useful refinement) give wrong pixels there, so these points
+    # do probe the margin.
+    pts = _boundary_points(nside, nside * 2.0 ** -35, seed=nside)
+    try:
+        for sign in (1, -1, 0):
+            lib().shim_set_estimate_error(2.0 ** -20, sign)
+            wrong, accepted = _fast_against_exact(nside, pts)
+            assert wrong == 0, (sign, wrong)
+            assert accepted > 0.9 * len(pts)
+        worst = 0
+        for sign in (1, -1):
+            lib().shim_set_estimate_error(2.0 ** -14, sign)
+            worst = max(worst, _fast_against_exact(nside, pts)[0])
+        assert worst > 0
+    finally:
+        lib().shim_set_estimate_error(0.0, 1)
