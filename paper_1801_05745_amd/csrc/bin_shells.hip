@@ -48,7 +48,8 @@ __global__ __launch_bounds__(kBinBlock) void bin_shells_kernel(BinParams p) {
     if (kMode == kRescue && p.guard->overflow == 0u) return;  // uniform: nothing to rescue
     __shared__ EdgeLds E;
     __shared__ double qbuf[kBinWaves][3 * kQueue];
-    load_edges(E, p.c, p.e);
+    __shared__ double radii[kMode == kRescue ? UFALCON_MAX_SHELLS + 1 : 1];
+    load_edges(E, p.c, p.e, kMode == kRescue ? radii : nullptr);
     const int w = threadIdx.x >> 6;
     const Shared sh = shared_of(p);
     LaneStats st;
@@ -143,6 +144,7 @@ __global__ __launch_bounds__(kBinBlock) void bin_batched_kernel(BatchParams p) {
     if (kMode == kRescue && p.sh.guard->overflow == 0u) return;
     __shared__ EdgeLds E;
     __shared__ double qbuf[kBinWaves][3 * kQueue];
+    __shared__ double radii[kMode == kRescue ? UFALCON_MAX_SHELLS + 1 : 1];
     __shared__ int64_t work;
     __shared__ int cur_item;
     const int w = threadIdx.x >> 6;
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(kBinBlock) void bin_batched_kernel(BatchParams p) {
         const BinCore c = p.items[k].c;
         if (k != cur_item) {  // uniform: `work` is shared
             __syncthreads();
-            load_edges(E, c, p.edges + p.items[k].edge_off);
+            load_edges(E, c, p.edges + p.items[k].edge_off, kMode == kRescue ? radii : nullptr);
             if (threadIdx.x == 0) cur_item = k;
         }
         const int64_t first = (t - p.items[k].tile_begin) * p.tile;

@@ -69,11 +69,12 @@ struct BinCore {
     double tab_lo, tab_h, tab_scale;  // table over r^2 from tab_lo, cell width tab_h = 1 / tab_scale
 };
 
-// Edges of one shell range in LDS: the radii (exact path), the squared radii
-// with two sentinels on each side (e2() is indexable from -2 to nb + 2) and the
-// shell lookup table.
+// Edges of one shell range in LDS: the squared radii with two sentinels on each
+// side (e2() is indexable from -2 to nb + 2), the shell lookup table, and a
+// pointer to the radii, which only the exact path reads (kRescue kernels keep
+// them in an LDS array of their own; elsewhere the pointer is null).
 struct EdgeLds {
-    double e[UFALCON_MAX_SHELLS + 1];
+    const double *e;
     double e2p[UFALCON_MAX_SHELLS + 5];
     double sL[2 * kMaxRep + 1];  // fl(s L) for s = -R .. R (index s + R)
     double ttc[kTtTerms];         // azimuth polynomial
@@ -81,13 +82,15 @@ struct EdgeLds {
     __device__ const double *e2() const { return e2p + 2; }
 };
 
-// Fill `E` for the range of `c` with radii `e`.  Every thread of the block calls
-// it (it synchronises twice).
-__device__ inline void load_edges(EdgeLds &E, const BinCore &c, const double *e) {
+// Fill `E` for the range of `c` with radii `e`, copying the radii to `radii`
+// (UFALCON_MAX_SHELLS + 1 LDS doubles) when the kernel decides exactly.  Every
+// thread of the block calls it (it synchronises twice).
+__device__ inline void load_edges(EdgeLds &E, const BinCore &c, const double *e, double *radii = nullptr) {
     for (int j = threadIdx.x; j <= c.nb; j += blockDim.x) {
-        E.e[j] = e[j];
+        if (radii) radii[j] = e[j];
         E.e2p[j + 2] = e[j] * e[j];
     }
+    if (threadIdx.x == 0) E.e = radii;
     if (threadIdx.x < 2) {
         E.e2p[threadIdx.x] = -kEdgeSentinel;
         E.e2p[c.nb + 3 + threadIdx.x] = kEdgeSentinel;
@@ -125,17 +128,28 @@ struct Shared {
     ufalcon_status *status;  // event counts (may be null)
 };
 
+// Level-1 buckets (key >> shift) that the key pass can count per reservation.
+constexpr int kHistBins = 256;
+
 // Key emission state of one wave (kEmit).  All lanes hold the same values.
+// With `hist`, the wave also counts its keys per level-1 bucket in LDS (two
+// 16-bit counters per word: a reservation holds at most 4096 keys) and, when a
+// reservation is closed, writes the counts to that reservation's row of
+// `hist_rows` (kHistBins 16-bit counts), so that the partition needs no pass
+// over the keys to histogram them.
 struct Emitter {
     uint32_t *keys;                    // key buffer (slots)
     unsigned long long *reserved;      // global count of reserved slots
     unsigned long long cap;            // usable slots (a multiple of kKeyChunk)
-    uint32_t *hist;                    // LDS histogram of key >> shift (per workgroup)
+    uint32_t *hist;                    // the wave's kHistBins / 2 LDS words, or null
+    uint16_t *hist_rows;               // [cap / kKeyChunk][kHistBins] counts per reservation
     int shift;
     unsigned long long base;           // current chunk [base, base + kKeyChunk)
     int fill;                          // slots used in the current chunk
     bool full;                         // the key buffer is exhausted: fall back to atomics
+    bool open;                         // a reservation is held (its counts are in `hist`)
 };
+
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -240,6 +254,23 @@ __device__ __forceinline__ uint32_t bin_instance(const BinCore &c, const Shared 
     return kNoKey;
 }
 
+__device__ __forceinline__ void hist_add(const Emitter &em, uint32_t key) {
+    const uint32_t b = key >> em.shift;
+    atomicAdd(&em.hist[b >> 1], 1u << ((b & 1u) * 16u));
+}
+
+// Write the counts of the wave's current reservation to its row and clear them.
+// All 64 lanes call it.  Lane l holds bins 4l .. 4l+3 in words 2l and 2l + 1,
+// which are the row's 16-bit entries 4l .. 4l+3 in order.
+__device__ __forceinline__ void flush_hist(Emitter &em) {
+    const int lane = threadIdx.x & 63;
+    wave_lds_sync();
+    const uint2 v = reinterpret_cast<const uint2 *>(em.hist)[lane];
+    reinterpret_cast<uint2 *>(em.hist_rows + (em.base / kKeyChunk) * (unsigned long long)kHistBins)[lane] = v;
+    reinterpret_cast<uint2 *>(em.hist)[lane] = make_uint2(0u, 0u);
+    wave_lds_sync();
+}
+
 // Wave-cooperative append of the lanes' keys (kNoKey lanes skip).  Must be
 // reached by all 64 lanes of the wave.
 __device__ __forceinline__ void emit_keys(Emitter &em, const BinCore &c, uint32_t key, LaneStats &st) {
@@ -260,13 +291,15 @@ __device__ __forceinline__ void emit_keys(Emitter &em, const BinCore &c, uint32_
     if (has && rank < room) {
         uint32_t *dst = em.keys + (em.base + (unsigned long long)em.fill);  // uniform: one scalar base per wave
         dst[rank] = key;
-        if (em.hist) atomicAdd(&em.hist[key >> em.shift], 1u);
+        if (em.hist) hist_add(em, key);
     }
     if (n <= room) {
         em.fill += n;
         return;
     }
-    // the current chunk is full: reserve the next one
+    // the current chunk is full: close it and reserve the next one
+    if (em.hist && em.open) flush_hist(em);
+    em.open = false;
     unsigned long long b = 0;
     if (lane == 0) b = atomicAdd(em.reserved, (unsigned long long)kKeyChunk);
     b = wave_first_u64(b);  // lane 0's reservation (every lane is active here)
@@ -281,9 +314,10 @@ __device__ __forceinline__ void emit_keys(Emitter &em, const BinCore &c, uint32_
         return;
     }
     em.base = b;
+    em.open = true;
     if (has && rank >= room) {
         em.keys[b + (rank - room)] = key;
-        if (em.hist) atomicAdd(&em.hist[key >> em.shift], 1u);
+        if (em.hist) hist_add(em, key);
     }
     em.fill = n - room;
 }
@@ -317,11 +351,14 @@ __device__ __forceinline__ void aggregate_add(uint32_t *counts, uint32_t key) {
     }
 }
 
-// Pad the unused tail of the wave's current chunk with sentinels.
+// Pad the unused tail of the wave's current chunk with sentinels and write its
+// counts.  All 64 lanes call it.
 __device__ __forceinline__ void close_emitter(Emitter &em) {
-    if (em.full || em.fill >= kKeyChunk) return;
+    if (!em.open) return;
     const int lane = threadIdx.x & 63;
     for (int k = em.fill + lane; k < kKeyChunk; k += 64) em.keys[em.base + k] = kNoKey;
+    if (em.hist) flush_hist(em);
+    em.open = false;
 }
 
 // The wave's queue (LDS arrays of kQueue slots) and its fill at each end.

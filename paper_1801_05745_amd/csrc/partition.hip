@@ -11,8 +11,12 @@
 //      (no host synchronisation, no counting pass, no shared claim counter);
 //   per chunk:
 //   1. keys: the binning core emits key = b * npix + pix per instance into a
-//      buffer (waves reserve 4096-slot chunks with one global atomic each);
-//   2. level-1 partition by key >> s1 (MSD radix step, <= 512 buckets);
+//      buffer (waves reserve 4096-slot chunks with one global atomic each) and,
+//      with at most 256 level-1 buckets, counts each reservation's keys per
+//      level-1 bucket in LDS, writing the counts when the reservation closes;
+//   2. level-1 partition by key >> s1 (MSD radix step, <= 512 buckets; its
+//      per-tile counts are sums of the reservations' counts when the key pass
+//      took them, else a pass over the keys);
 //   3. level-2 partition by cell block (key >> 14) inside each level-1 bucket;
 //   4. accumulate: one workgroup per 16384-cell block counts its keys with LDS
 //      atomics and adds the block into the map with coalesced 16-byte
@@ -55,8 +59,9 @@ struct PartLayout {
     unsigned long long margin;  // room a wave needs before it claims: every wave's worst-case claim
     unsigned long long budget;  // keys every chunk but the last processes, at least
     int64_t hist_rows;      // super-tile rows of the per-tile histogram
-    size_t off_guard, off_hdr, off_wave, off_off1, off_tiles1, off_offb, off_tot, off_thist, off_keysa, off_keysb,
-        total;
+    bool counted;           // the key pass counts the level-1 buckets (nb1 <= kHistBins)
+    size_t off_guard, off_hdr, off_wave, off_off1, off_tiles1, off_offb, off_tot, off_thist, off_hrows, off_keysa,
+        off_keysb, total;
 };
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -110,8 +115,10 @@ static bool plan_layout(PartLayout &L, int64_t n, int64_t ncells, int img_bound,
         // (a plan's shared workspace) rounds its capacity down by up to one
         cap = std::max((unsigned long long)want_keys + margin + slack, 2 * (margin + slack)) + 3 * kKeyChunk;
     } else {
-        // bytes = head + per-tile histogram (~ cap/kSuper rows) + two key buffers
-        const double per_key = 2.0 * sizeof(uint32_t) + (double)wide * sizeof(uint32_t) / kSuper;
+        // bytes = head + per-tile histogram (~ cap/kSuper rows) + per-reservation
+        // level-1 counts + two key buffers
+        const double per_key = 2.0 * sizeof(uint32_t) + (double)wide * sizeof(uint32_t) / kSuper +
+                               (L.nb1 <= kHistBins ? (double)kHistBins * sizeof(uint16_t) / kKeyChunk : 0.0);
         const size_t extra = sizeof(uint32_t) * (size_t)wide * (L.nb1 + 2) + 4096;
         if (bytes < fixed_head + extra) return false;
         cap = (unsigned long long)((double)(bytes - fixed_head - extra) / per_key);
@@ -123,6 +130,9 @@ static bool plan_layout(PartLayout &L, int64_t n, int64_t ncells, int img_bound,
     if (cap < 2 * (margin + slack) + kKeyChunk) return false;
     L.hist_rows = (int64_t)(cap / kSuper) + L.nb1 + 2;
     L.off_thist = o; o = align256(o + sizeof(uint32_t) * (size_t)wide * L.hist_rows);
+    L.counted = L.nb1 <= kHistBins;
+    L.off_hrows = o;
+    if (L.counted) o = align256(o + sizeof(uint16_t) * (size_t)kHistBins * (size_t)(cap / kKeyChunk));
     const size_t fixed = o;
     L.cap = cap;
     L.margin = margin;
@@ -192,6 +202,8 @@ struct KeyParams {
     unsigned long long margin;
     PartHeader *hdr;
     int64_t *wave_pos;  // per wave: base of its next batch (-1: not started)
+    uint16_t *hist_rows;  // per reservation: level-1 bucket counts (null: tile_hist counts them)
+    int hist_shift;
     int last;
 };
 
@@ -200,10 +212,15 @@ __global__ __launch_bounds__(kBinBlock, 6) void keys_kernel(KeyParams kp) {
     const BinParams &p = kp.p;
     __shared__ EdgeLds E;
     __shared__ double qbuf[kBinWaves][3 * kQueue];
+    __shared__ uint32_t hist_s[kBinWaves][kHistBins / 2];
     if (!kp.hdr->active) return;  // uniform: every wave finished in an earlier chunk
     load_edges(E, p.c, p.e);
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
+    if (kp.hist_rows) {
+        reinterpret_cast<uint2 *>(hist_s[w])[lane] = make_uint2(0u, 0u);
+        wave_lds_sync();
+    }
     const int64_t wid = (int64_t)blockIdx.x * kBinWaves + w;
     const Shared sh = shared_of(p);
     LaneStats st;
@@ -211,11 +228,13 @@ __global__ __launch_bounds__(kBinBlock, 6) void keys_kernel(KeyParams kp) {
     em.keys = kp.keys;
     em.reserved = &kp.hdr->reserved;
     em.cap = kp.cap;
-    em.hist = nullptr;
-    em.shift = 0;
+    em.hist = kp.hist_rows ? hist_s[w] : nullptr;
+    em.hist_rows = kp.hist_rows;
+    em.shift = kp.hist_shift;
     em.base = 0;
     em.fill = kKeyChunk;
     em.full = false;
+    em.open = false;
     WaveQueue q{qbuf[w], 0, 0};
     const int64_t stride = (int64_t)gridDim.x * kBinBlock;
     const int64_t saved = kp.wave_pos[wid];
@@ -367,6 +386,25 @@ __global__ __launch_bounds__(kPartThreads) void tile_hist_kernel(PartStep ps) {
             row[b] = c;
         }
         lds_barrier();
+    }
+}
+
+// Level-1 bucket counts per super-tile from the key pass's per-reservation
+// counts (super-tile t holds reservations t * kSuper / kKeyChunk onwards): the
+// tile_hist of level 1 without reading the keys.
+static_assert(kSuper % kKeyChunk == 0, "super-tiles are whole reservations");
+__global__ __launch_bounds__(kHistBins) void l1_rows_kernel(PartStep ps, const uint16_t *hrows) {
+    constexpr int kPerTile = kSuper / kKeyChunk;
+    if (!ps.hdr->active) return;
+    const int64_t nres = step_total(ps) / kKeyChunk;  // reserved slots come in whole reservations
+    const int64_t ntiles = step_tiles(ps);
+    const int b = threadIdx.x;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t r0 = t * kPerTile;
+        const int64_t r1 = r0 + kPerTile < nres ? r0 + kPerTile : nres;
+        uint32_t c = 0;
+        for (int64_t r = r0; r < r1; ++r) c += hrows[r * kHistBins + b];
+        if (b < ps.nbins) ps.tile_hist[t * ps.nbins + b] = c;
     }
 }
 
@@ -648,7 +686,8 @@ __global__ __launch_bounds__(kBinBlock) void part_rescue_kernel(BinParams p) {
     if (p.guard->overflow == 0u) return;
     __shared__ EdgeLds E;
     __shared__ double qbuf[kBinWaves][3 * kQueue];
-    load_edges(E, p.c, p.e);
+    __shared__ double radii[UFALCON_MAX_SHELLS + 1];
+    load_edges(E, p.c, p.e, radii);
     const int w = threadIdx.x >> 6;
     const Shared sh = shared_of(p);
     LaneStats st;
@@ -704,6 +743,8 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
     kp.cap = L.cap;
     kp.hdr = hdr;
     kp.wave_pos = wave_pos;
+    kp.hist_rows = L.counted ? reinterpret_cast<uint16_t *>(ws + L.off_hrows) : nullptr;
+    kp.hist_shift = L.s1;
 
     PartStep l1{};
     l1.in = keysa;
@@ -742,8 +783,12 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
         hipLaunchKernelGGL((keys_kernel<T>), dim3(key_grid), dim3(kBinBlock), 0, s, kp);
         if (k == 0 && hooks && hooks->done_keys) UFX_HIP_CHECK(hipEventRecord(hooks->done_keys, s));
         timer_mark(timer, UFALCON_PHASE_DECIDE, s);
-        // level 1: by key >> s1
-        hipLaunchKernelGGL(tile_hist_kernel, dim3(hist_grid), dim3(kPartThreads), 0, s, l1);
+        // level 1: by key >> s1 (the key pass counted the buckets when there are few enough)
+        if (kp.hist_rows)
+            hipLaunchKernelGGL(l1_rows_kernel, dim3(hist_grid), dim3(kHistBins), 0, s, l1,
+                               (const uint16_t *)kp.hist_rows);
+        else
+            hipLaunchKernelGGL(tile_hist_kernel, dim3(hist_grid), dim3(kPartThreads), 0, s, l1);
         hipLaunchKernelGGL(bucket_scan_kernel, dim3((unsigned)L.nb1), dim3(256), 0, s, l1);
         hipLaunchKernelGGL(bucket_base_kernel, dim3(1), dim3(1024), 0, s, tot, (int64_t)L.nb1, off1, tiles1, hdr);
         hipLaunchKernelGGL(scatter_kernel<uint32_t>, dim3(scat_grid), dim3(kScatThreads), 0, s, l1);
