@@ -145,9 +145,8 @@ struct Emitter {
     uint16_t *hist_rows;               // [cap / kKeyChunk][kHistBins] counts per reservation
     int shift;
     unsigned long long base;           // current chunk [base, base + kKeyChunk)
-    int fill;                          // slots used in the current chunk
+    int fill;                          // slots used in the current chunk; kKeyChunk + 1: no chunk held
     bool full;                         // the key buffer is exhausted: fall back to atomics
-    bool open;                         // a reservation is held (its counts are in `hist`)
 };
 
 
@@ -287,7 +286,7 @@ __device__ __forceinline__ void emit_keys(Emitter &em, const BinCore &c, uint32_
     }
     const int n = __popcll(m);
     const int rank = lanes_below(m);
-    const int room = kKeyChunk - em.fill;
+    const int room = em.fill < kKeyChunk ? kKeyChunk - em.fill : 0;  // fill is kKeyChunk + 1 when no chunk is held
     if (has && rank < room) {
         uint32_t *dst = em.keys + (em.base + (unsigned long long)em.fill);  // uniform: one scalar base per wave
         dst[rank] = key;
@@ -297,16 +296,15 @@ __device__ __forceinline__ void emit_keys(Emitter &em, const BinCore &c, uint32_
         em.fill += n;
         return;
     }
-    // the current chunk is full: close it and reserve the next one
-    if (em.hist && em.open) flush_hist(em);
-    em.open = false;
+    // the current chunk is full (or none is held): close it and reserve the next one
+    if (em.hist && em.fill <= kKeyChunk) flush_hist(em);
     unsigned long long b = 0;
     if (lane == 0) b = atomicAdd(em.reserved, (unsigned long long)kKeyChunk);
     b = wave_first_u64(b);  // lane 0's reservation (every lane is active here)
     if (b + kKeyChunk > em.cap) {
         // chunk-aligned capacity: this reservation lies wholly outside the buffer
         em.full = true;
-        em.fill = kKeyChunk;
+        em.fill = kKeyChunk + 1;
         if (has && rank >= room) {
             atomicAdd(c.counts + key, 1u);
             ++st.fallback;
@@ -314,7 +312,6 @@ __device__ __forceinline__ void emit_keys(Emitter &em, const BinCore &c, uint32_
         return;
     }
     em.base = b;
-    em.open = true;
     if (has && rank >= room) {
         em.keys[b + (rank - room)] = key;
         if (em.hist) hist_add(em, key);
@@ -354,11 +351,11 @@ __device__ __forceinline__ void aggregate_add(uint32_t *counts, uint32_t key) {
 // Pad the unused tail of the wave's current chunk with sentinels and write its
 // counts.  All 64 lanes call it.
 __device__ __forceinline__ void close_emitter(Emitter &em) {
-    if (!em.open) return;
+    if (em.fill > kKeyChunk) return;  // no chunk held
     const int lane = threadIdx.x & 63;
     for (int k = em.fill + lane; k < kKeyChunk; k += 64) em.keys[em.base + k] = kNoKey;
     if (em.hist) flush_hist(em);
-    em.open = false;
+    em.fill = kKeyChunk + 1;
 }
 
 // The wave's queue (LDS arrays of kQueue slots) and its fill at each end.

@@ -232,9 +232,8 @@ __global__ __launch_bounds__(kBinBlock, 6) void keys_kernel(KeyParams kp) {
     em.hist_rows = kp.hist_rows;
     em.shift = kp.hist_shift;
     em.base = 0;
-    em.fill = kKeyChunk;
+    em.fill = kKeyChunk + 1;  // no chunk held: the first key reserves one
     em.full = false;
-    em.open = false;
     WaveQueue q{qbuf[w], 0, 0};
     const int64_t stride = (int64_t)gridDim.x * kBinBlock;
     const int64_t saved = kp.wave_pos[wid];
