@@ -298,8 +298,13 @@ def batched16(dev, args, order=None, steps=None, warmup=None, plain_reps=2, roof
     max_over_rms = float((kap.abs().max(dim=1).values / rms).max())
     del kap
 
+    # the batched step's outputs, compared below with the plain calls' (same inputs, same kernels)
+    batched_kappa = [it["kappa"].clone() for it in items]
+    batched_grad = [g.clone() for g in outs["gth"]]
+
     # plain: the same step as 16 sequences of single-map calls (one shared workspace)
     plain = None
+    match = None
     ws = None
     if not args.no_plain and (plain_reps > 0 or roofline):
         ws = uf.partition_workspace(max(sizes), max(it["n_rep"] for it in items), max(shells), nside, device=dev)
@@ -316,6 +321,7 @@ def batched16(dev, args, order=None, steps=None, warmup=None, plain_reps=2, roof
                 inb = uf.inv_nbar(it["n"], L, it["chi_edges"], nside, device=dev)
                 kappas.append(uf.born_kappa(it["counts"], W, inb))
             backward(kappas)
+            outs["plain_kappa"] = kappas
 
         plain_step()
         torch.cuda.synchronize()
@@ -327,6 +333,12 @@ def batched16(dev, args, order=None, steps=None, warmup=None, plain_reps=2, roof
         plain_ms = 1e3 * (time.perf_counter() - t1) / reps
         log(f"headline: plain {plain_ms:.1f} ms per batch")
         plain = {"ms_per_batch": plain_ms, "maps_per_s": 16e3 / plain_ms, "reps": reps}
+        match = {"kappa": all(torch.equal(a, b) for a, b in zip(batched_kappa, outs["plain_kappa"])),
+                 "grad": all(torch.equal(a, b) for a, b in zip(batched_grad, outs["gth"]))}
+        if not (match["kappa"] and match["grad"]):
+            log(f"headline: batched and plain outputs differ: {match}")
+        del outs["plain_kappa"]
+    del batched_kappa, batched_grad
 
     if roofline and ws is not None:
         # the dominant kernel, timed on its own stream by the library's phase events:
@@ -353,6 +365,7 @@ def batched16(dev, args, order=None, steps=None, warmup=None, plain_reps=2, roof
         "guarded_per_step": st["n_guarded"] / steps, "unresolved": st["n_unresolved"],
         "fallback": st["n_fallback"], "kappa_max_over_rms": max_over_rms, "shells": shells,
         "maps_per_s_batched": 16e3 / ms_per_step, "plain": plain,
+        "batched_equals_plain": match,
         "tuning": {"method": tuning["method"], "tile": tuning["tile"], "persistent_wgs": tuning["persistent_wgs"],
                    "candidates": tuning["candidates"], "tune_s": tune_s, "sample_items": 2},
         "input_generation_s": gen_s,
@@ -697,6 +710,8 @@ def config5(dev, reps=2):
     torch.cuda.synchronize()
     fwd_ms = 1e3 * (time.perf_counter() - t1)
     plan.close()
+    check = [0, R_real // 2, R_real - 1]
+    batched_kappa = [items[r]["kappa"].clone() for r in check]
     # the same forward pass as 150 plain calls (one shared workspace)
     ws = uf.partition_workspace(n, R, B, nside, device=dev)
 
@@ -713,7 +728,8 @@ def config5(dev, reps=2):
     plain_forward()
     torch.cuda.synchronize()
     plain_fwd_ms = 1e3 * (time.perf_counter() - t1)
-    del ws
+    batched_equals_plain = all(torch.equal(a, items[r]["kappa"]) for a, r in zip(batched_kappa, check))
+    del ws, batched_kappa
     res = {"workload": "150 realisations x 256^3 lognormal FP32 particles, 1 Gpc/h box, 40 shells z=0.1-1.5, "
                        "Nside 512, images {-3..3}^3, Smail n(z); forward (batch-plan graph: bin + Born) + backward "
                        "(adjoint of L = sum kappa^2 to W, Omega_m, z0)",
@@ -724,7 +740,8 @@ def config5(dev, reps=2):
            "dL_dOmega_m": float(out["g_om"]), "dL_dz0": float(out["g_z0"]),
            "tuning": {"method": tuning["method"], "candidates_ms": [round(c["ms"], 2) for c in tuning["candidates"]],
                       "sample_items": 4},
-           "forward_batched_ms": fwd_ms, "forward_batched_maps_per_s": R_real * 1e3 / fwd_ms,
+           "forward_batched_ms": fwd_ms,
+           "batched_equals_plain": {"kappa_realisations": check, "equal": batched_equals_plain}, "forward_batched_maps_per_s": R_real * 1e3 / fwd_ms,
            "forward_plain_ms": plain_fwd_ms, "forward_plain_maps_per_s": R_real * 1e3 / plain_fwd_ms,
            "input_generation_s": gen_s, "reps": reps}
     del items, plan, out
@@ -900,7 +917,8 @@ def secondary(dev, args, parts, line):
     """The parts after the headline, added to `line`."""
     if "batched_cell" in parts:
         cell, _ = batched16(dev, args, order="cell", steps=3, warmup=1, plain_reps=1, roofline=False)
-        line["batched_cell_order"] = {k: cell[k] for k in ("ms_per_step", "maps_per_s_batched", "plain", "tuning",
+        line["batched_cell_order"] = {k: cell[k] for k in ("ms_per_step", "maps_per_s_batched", "plain",
+                                                           "batched_equals_plain", "tuning",
                                                            "instances_per_step", "fallback", "unresolved")}
     kmap = None
     if "config2" in parts:
