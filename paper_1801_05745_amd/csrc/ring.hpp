@@ -72,9 +72,13 @@ UFX_FN double rcp_nr(double d) {
     return fma(r, e, r);
 }
 
+// floor(v), and whether v lies more than eps from both integers around it.  The
+// callers' arguments are >= 0 (a negative rounding residue fails the test), so
+// v - floor(v) is exact.
 UFX_FN bool clear_of_integer(double v, double eps, double &fl) {
     fl = floor(v);
-    return (v - fl) > eps && (fl + 1.0 - v) > eps;
+    const double frac = v - fl;
+    return frac > eps && frac < 1.0 - eps;
 }
 
 // tt = 2 phi / pi in [0, 4] for phi = atan2(dy, dx) taken in [0, 2 pi).
@@ -106,10 +110,14 @@ UFX_FN double fast_tt_c(double dx, double dy, CoefPtr c) {
     const double s = u * u;
     double p = c[kTtTerms - 1];
     for (int k = kTtTerms - 2; k >= 0; --k) p = fma(p, s, c[k]);
-    double th = fma(u, p, upper ? 0.5 : 0.0);  // quarter turns of atan(mn/mx), in [0, 1/2]
-    th = ay > ax ? 1.0 - th : th;              // quarter turns of the angle of (|dx|, |dy|)
-    if (dx >= 0.0) return dy >= 0.0 ? th : 4.0 - th;
-    return dy >= 0.0 ? 2.0 - th : 2.0 + th;
+    const double th = fma(u, p, upper ? 0.5 : 0.0);  // quarter turns of atan(mn/mx), in [0, 1/2]
+    // The angle of (|dx|, |dy|) is th, or 1 - th when |dy| > |dx|; the quadrant
+    // maps it to a, 2 - a, 2 + a or 4 - a.  Together: tt = o + s th with an
+    // integer o in 0..4 and s = +-1, one rounding.
+    const bool nx = dx < 0.0, ny = dy < 0.0, swap = ay > ax;
+    const int o = (nx ? 2 : (ny ? 4 : 0)) + (swap ? (nx == ny ? 1 : -1) : 0);
+    const bool neg = (nx != ny) != swap;
+    return (double)o + (neg ? -th : th);
 }
 
 UFX_FN double fast_tt(double dx, double dy) { return fast_tt_c(dx, dy, kTtCoef); }
