@@ -130,7 +130,7 @@ UFX_FN double fast_tt(double dx, double dy) { return fast_tt_c(dx, dy, kTtCoef);
 // With y = 1/|d| (refined reciprocal square root): z = dz y in the belt, and in
 // the caps 1 - |z| = rho^2 / (r (r + |dz|)) = rho^2 y^2 / (1 + |z|), which has no
 // cancellation near the poles.  Vectors so short that a reciprocal would leave
-// the normal range (|d|^2 <= 2^-600 or max(|dx|,|dy|) <= 2^-500) are deferred.
+// the normal range (|d|^2 <= 2^-600 or dx^2 + dy^2 <= 2^-1000) are deferred.
 // No data-dependent branches: rejected lanes carry harmless values.
 template <bool kBelt, typename CoefPtr>
 UFX_FN bool fast_ring_pixel_region(int32_t N, double Nd, double eps, double dx, double dy, double dz, int32_t &pix,
@@ -139,10 +139,10 @@ UFX_FN bool fast_ring_pixel_region(int32_t N, double Nd, double eps, double dx, 
     const double dz2 = dz * dz;
     const double r2 = rho2 + dz2;
     const double a5 = 5.0 * dz2, a4 = 4.0 * rho2;
-    const double mx = fmax(fabs(dx), fabs(dy));
     const bool region = (a5 < a4) == kBelt;
     const bool away = fabs(a5 - a4) > kRelGuard * (a5 + a4);  // not near |z| = 2/3 (nor d = 0)
-    bool ok = region && away && r2 > 0x1p-600 && mx > 0x1p-500;
+    // rho^2 > 2^-1000 keeps max(|dx|, |dy|) > 2^-500.5, the azimuth's divisor in range
+    bool ok = region && away && r2 > 0x1p-600 && rho2 > 0x1p-1000;
     const double y = rsqrt_nr(ok ? r2 : 1.0);                   // 1 / |d|
     const double tt = fast_tt_c(dx, dy, tt_coef);
     const double z = dz * y;

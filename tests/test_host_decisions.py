@@ -290,3 +290,21 @@ def test_reciprocal_estimates_refined_inside_the_margin(nside):
         assert worst > 0
     finally:
         lib().shim_set_estimate_error(0.0, 1)
+
+
+def test_short_vectors_defer_or_agree():
+    # directions whose x-y part is far below the normal range of the azimuth's
+    # divisor: the fast path must defer (or agree); the exact path decides or
+    # reports the instance as unresolved (positions never come this close to the
+    # observer in practice)
+    vs = [(2.0 ** -520, 2.0 ** -530, 1.0), (2.0 ** -499, 0.0, -1.0), (1e-160, 1e-160, 1.0),
+          (-1e-200, 3e-200, -0.5), (1e-155, -1e-156, 2.0), (-2.0 ** -501, -2.0 ** -501, 3.0)]
+    for nside in (1, 64, 1024):
+        for v in vs:
+            want = hp.ang2pix_ring(nside, *v)
+            p, unres = exact_pix(nside, v)
+            assert unres == 1 or p == want, (nside, v)  # far outside its exponent range the exact path may report
+            f = fast_pix(nside, v)
+            assert f is None or f == want, (nside, v)
+            if 0.0 < v[0] ** 2 + v[1] ** 2 <= 2.0 ** -1000:
+                assert f is None, (nside, v)
