@@ -439,13 +439,16 @@ __device__ __forceinline__ int64_t bin_wave_range(const BinCore &c, const Shared
             for (int iy = 0; iy < side; ++iy) {
                 const double dy = by + E.sL[iy];
                 const double rho2 = dx * dx + dy * dy;
-                const double a4 = 4.0 * rho2;
+                // belt when 5 dz^2 < 4 rho^2, tested as dz^2 < 0.8 rho^2: a direction this
+                // puts in the other queue lies within rounding of |z| = 2/3, where the
+                // decision code defers it
+                const double a08 = 0.8 * rho2;
                 for (int iz = 0; iz < side; ++iz) {
                     const double dz = bz + E.sL[iz];
                     const double dz2 = dz * dz;
                     const double r2 = rho2 + dz2;  // the same roundings as the decision code
                     const bool in = valid && r2 >= c.lo2 && r2 < c.hi2;
-                    const bool belt = 5.0 * dz2 < a4;
+                    const bool belt = dz2 < a08;
                     const unsigned long long mi = wave_ballot(in), mbelt = wave_ballot(belt);
                     if (mi == 0ull) continue;
                     const unsigned long long mb = mi & mbelt, mc = mi & ~mbelt;

@@ -72,6 +72,16 @@ UFX_FN double rcp_nr(double d) {
     return fma(r, e, r);
 }
 
+// Product of two operands in [0, 2^24) whose product fits 32 bits (the pixel
+// index terms, N <= 8192): one full-rate 24-bit multiply on the device.
+UFX_FN int32_t mul24(int32_t a, int32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return (int32_t)__umul24((unsigned)a, (unsigned)b);
+#else
+    return a * b;
+#endif
+}
+
 // floor(v), and whether v lies more than eps from both integers around it.  The
 // callers' arguments are >= 0 (a negative rounding residue fails the test), so
 // v - floor(v) is exact.
@@ -156,7 +166,7 @@ UFX_FN bool fast_ring_pixel_region(int32_t N, double Nd, double eps, double dx, 
         const int32_t k = N + 1 + jp - jm;                              // ring below z = 2/3, 1 .. 2N+1
         int32_t q = (jp + jm - N + ((k & 1) ^ 1) + 1) >> 1;             // 0 .. 4N+1
         q = q >= 4 * N ? q - 4 * N : q;
-        pix = 2 * N * (N - 1) + 4 * N * (k - 1) + q;
+        pix = 2 * N * (N - 1) + mul24(4 * N, k - 1) + q;
     } else {
         const double om = rho2 * y * y * rcp_nr(1.0 + fabs(z));       // 1 - |z|
         double ftt;
@@ -172,7 +182,7 @@ UFX_FN bool fast_ring_pixel_region(int32_t N, double Nd, double eps, double dx, 
         ok = ok & clear_of_integer(tt * (double)k, eps, fq);
         int32_t q = (int32_t)(ok ? fq : 0.0);                          // 0 .. 4k-1 when clear
         q = q >= 4 * k ? q - 4 * k : q;
-        pix = dz > 0.0 ? 2 * k * (k - 1) + q : 12 * N * N - 2 * k * (k + 1) + q;
+        pix = dz > 0.0 ? 2 * mul24(k, k - 1) + q : 12 * N * N - 2 * mul24(k, k + 1) + q;
     }
     return ok;
 }
