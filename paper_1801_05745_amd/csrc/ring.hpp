@@ -116,7 +116,7 @@ UFX_FN double fast_tt_c(double dx, double dy, CoefPtr c) {
     const bool upper = mn > 0.4142 * mx;
     const double num = upper ? mn - mx : mn;
     const double den = upper ? mn + mx : mx;
-    const double u = den > 0.0 ? num * rcp_nr(den) : 0.0;  // den is normal whenever the caller accepts
+    const double u = num * rcp_nr(den);  // den is normal whenever the caller accepts (else NaN, rejected)
     const double s = u * u;
     double p = c[kTtTerms - 1];
     for (int k = kTtTerms - 2; k >= 0; --k) p = fma(p, s, c[k]);
@@ -141,7 +141,8 @@ UFX_FN double fast_tt(double dx, double dy) { return fast_tt_c(dx, dy, kTtCoef);
 // the caps 1 - |z| = rho^2 / (r (r + |dz|)) = rho^2 y^2 / (1 + |z|), which has no
 // cancellation near the poles.  Vectors so short that a reciprocal would leave
 // the normal range (|d|^2 <= 2^-600 or dx^2 + dy^2 <= 2^-1000) are deferred.
-// No data-dependent branches: rejected lanes carry harmless values.
+// No data-dependent branches: rejected lanes may carry NaN or infinities, which
+// every integer conversion masks with the acceptance flag.
 template <bool kBelt, typename CoefPtr>
 UFX_FN bool fast_ring_pixel_region(int32_t N, double Nd, double eps, double dx, double dy, double dz, int32_t &pix,
                                    CoefPtr tt_coef) {
@@ -153,7 +154,7 @@ UFX_FN bool fast_ring_pixel_region(int32_t N, double Nd, double eps, double dx, 
     const bool away = fabs(a5 - a4) > kRelGuard * (a5 + a4);  // not near |z| = 2/3 (nor d = 0)
     // rho^2 > 2^-1000 keeps max(|dx|, |dy|) > 2^-500.5, the azimuth's divisor in range
     bool ok = region && away && r2 > 0x1p-600 && rho2 > 0x1p-1000;
-    const double y = rsqrt_nr(ok ? r2 : 1.0);                   // 1 / |d|
+    const double y = rsqrt_nr(r2);                              // 1 / |d| (rejected lanes may carry NaN)
     const double tt = fast_tt_c(dx, dy, tt_coef);
     const double z = dz * y;
     if (kBelt) {
@@ -173,7 +174,7 @@ UFX_FN bool fast_ring_pixel_region(int32_t N, double Nd, double eps, double dx, 
         ok = ok & clear_of_integer(tt, eps, ftt);
         const double u = tt - ftt;
         const double om3 = 3.0 * om;                                  // sqrt(om3) = om3 / sqrt(om3)
-        const double sig = Nd * (om3 * rsqrt_nr(om3 > 0.0 ? om3 : 1.0));
+        const double sig = Nd * (om3 * rsqrt_nr(om3));              // om3 > 0 when rho^2 > 0
         double fa, fb;
         ok = ok & clear_of_integer(u * sig, eps, fa);
         ok = ok & clear_of_integer((1.0 - u) * sig, eps, fb);
