@@ -433,6 +433,7 @@ __device__ __forceinline__ int64_t bin_wave_range(const BinCore &c, const Shared
                 ++st.invalid;
             }
         }
+        const unsigned long long mvalid = wave_ballot(valid);
         const int side = 2 * c.R + 1;
         for (int ix = 0; ix < side; ++ix) {
             const double dx = bx + E.sL[ix];  // d = (x - o) + fl(s L), per axis
@@ -447,12 +448,14 @@ __device__ __forceinline__ int64_t bin_wave_range(const BinCore &c, const Shared
                     const double dz = bz + E.sL[iz];
                     const double dz2 = dz * dz;
                     const double r2 = rho2 + dz2;  // the same roundings as the decision code
-                    const bool in = valid && r2 >= c.lo2 && r2 < c.hi2;
-                    const bool belt = dz2 < a08;
-                    const unsigned long long mi = wave_ballot(in), mbelt = wave_ballot(belt);
+                    // lane masks straight from the compares; the per-lane flags read back
+                    // from them
+                    const unsigned long long mi = wave_ballot(r2 >= c.lo2) & wave_ballot(r2 < c.hi2) & mvalid;
                     if (mi == 0ull) continue;
+                    const unsigned long long mbelt = wave_ballot(dz2 < a08);
                     const unsigned long long mb = mi & mbelt, mc = mi & ~mbelt;
-                    if (in) {
+                    if (__builtin_amdgcn_inverse_ballot_w64(mi)) {
+                        const bool belt = __builtin_amdgcn_inverse_ballot_w64(mbelt);
                         const int pos = belt ? q.nb + lanes_below(mb) : kQueue - 1 - q.nc - lanes_below(mc);
                         q.q[pos] = dx;
                         q.q[kQueue + pos] = dy;
