@@ -178,6 +178,16 @@ __device__ __forceinline__ int opaque_zero() {
     return z;
 }
 
+// An LDS array's address, opaque to the compiler in the same way: every element
+// read through it is a fresh load, and all of them share the one address
+// register (constant offsets in the load instructions).
+typedef __attribute__((address_space(3))) const double LdsDouble;
+__device__ __forceinline__ LdsDouble *opaque_lds(const double *p) {
+    LdsDouble *q = (LdsDouble *)p;
+    asm volatile("" : "+v"(q));
+    return q;
+}
+
 // Ballot of a lane predicate (the compare's lane mask, without a round trip
 // through a VGPR) and the number of lanes below this one set in a mask.
 __device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
@@ -222,7 +232,7 @@ __device__ __forceinline__ uint32_t bin_instance(const BinCore &c, const Shared 
         if (j < 0 || j >= c.nb) return kNoKey;
         int32_t pix;
         // the range test costs two compares and keeps any logic slip from writing out of bounds
-        if (fast_ring_pixel_region<kBelt>((int32_t)sh.nside, Nd, sh.eps, dx, dy, dz, pix, E.ttc + opaque_zero()) &&
+        if (fast_ring_pixel_region<kBelt>((int32_t)sh.nside, Nd, sh.eps, dx, dy, dz, pix, opaque_lds(E.ttc)) &&
             (uint32_t)pix < (uint32_t)sh.npix) {  // npix < 2^31 for nside <= 8192
             if (kMode == kRescue) return kNoKey;
             ++st.inst;
@@ -255,7 +265,7 @@ __device__ __forceinline__ uint32_t bin_instance(const BinCore &c, const Shared 
 
 __device__ __forceinline__ void hist_add(const Emitter &em, uint32_t key) {
     const uint32_t b = key >> em.shift;
-    atomicAdd(&em.hist[b >> 1], 1u << ((b & 1u) * 16u));
+    atomicAdd(&em.hist[key >> (em.shift + 1)], (b & 1u) ? 0x10000u : 1u);  // word b / 2, half b % 2
 }
 
 // Write the counts of the wave's current reservation to its row and clear them.
@@ -285,9 +295,9 @@ __device__ __forceinline__ void emit_keys(Emitter &em, const BinCore &c, uint32_
         return;
     }
     const int n = __popcll(m);
-    const int rank = lanes_below(m);
+    const unsigned rank = (unsigned)lanes_below(m);  // unsigned: a 32-bit offset from a scalar base
     const int room = em.fill < kKeyChunk ? kKeyChunk - em.fill : 0;  // fill is kKeyChunk + 1 when no chunk is held
-    if (has && rank < room) {
+    if (has && rank < (unsigned)room) {
         uint32_t *dst = em.keys + (em.base + (unsigned long long)em.fill);  // uniform: one scalar base per wave
         dst[rank] = key;
         if (em.hist) hist_add(em, key);
@@ -305,14 +315,14 @@ __device__ __forceinline__ void emit_keys(Emitter &em, const BinCore &c, uint32_
         // chunk-aligned capacity: this reservation lies wholly outside the buffer
         em.full = true;
         em.fill = kKeyChunk + 1;
-        if (has && rank >= room) {
+        if (has && rank >= (unsigned)room) {
             atomicAdd(c.counts + key, 1u);
             ++st.fallback;
         }
         return;
     }
     em.base = b;
-    if (has && rank >= room) {
+    if (has && rank >= (unsigned)room) {
         em.keys[b + (rank - room)] = key;
         if (em.hist) hist_add(em, key);
     }
