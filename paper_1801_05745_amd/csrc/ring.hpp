@@ -183,7 +183,10 @@ UFX_FN bool fast_ring_pixel_region(int32_t N, double Nd, double eps, double dx, 
         ok = ok & clear_of_integer(tt * (double)k, eps, fq);
         int32_t q = (int32_t)(ok ? fq : 0.0);                          // 0 .. 4k-1 when clear
         q = q >= 4 * k ? q - 4 * k : q;
-        pix = dz > 0.0 ? 2 * mul24(k, k - 1) + q : 12 * N * N - 2 * mul24(k, k + 1) + q;
+        // north 2k(k-1) + q, south 12N^2 - 2k(k+1) + q: one product, no branch
+        const bool north = dz > 0.0;
+        const int32_t p2 = mul24(2 * k, north ? k - 1 : k + 1);
+        pix = (north ? p2 : 12 * N * N - p2) + q;
     }
     return ok;
 }
