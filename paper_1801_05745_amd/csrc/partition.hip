@@ -17,15 +17,19 @@
 //   2. level-1 partition by key >> s1 (MSD radix step, <= 512 buckets; its
 //      per-tile counts are sums of the reservations' counts when the key pass
 //      took them, else a pass over the keys);
-//   3. level-2 partition by cell block (key >> 14) inside each level-1 bucket;
-//   4. accumulate: one workgroup per 16384-cell block counts its keys with LDS
-//      atomics and adds the block into the map with coalesced 16-byte
-//      read-modify-writes (blocks without keys are skipped).
-// Each partition level works on super-tiles of 32768 keys: per-tile bucket
-// counts, their exclusive scan per bucket (every tile's write offset), a scan
-// of the bucket totals, then each super-tile ranked, sorted in LDS and
-// written as contiguous runs, with no global atomics.  Integer counts make the
-// result independent of every order involved.
+//   3. level 2, in place: each 32768-key super-tile of a level-1 bucket is
+//      sorted by cell block (key >> 14) in LDS and written back where it was
+//      read, as 16-bit cells, with the start of every block's run in the tile;
+//   4. accumulate: one workgroup per 16384-cell block counts the keys of its
+//      runs (one per super-tile of its level-1 bucket) with LDS atomics and
+//      adds the block into the map with coalesced 16-byte read-modify-writes
+//      (blocks without keys are skipped).
+// Level 1 works on super-tiles of 32768 keys: per-tile bucket counts, their
+// exclusive scan per bucket (every tile's write offset), a scan of the bucket
+// totals, then each super-tile ranked, sorted in LDS and written as contiguous
+// runs, with no global atomics.  Level 2 needs no counting pass: its runs stay
+// inside their super-tiles.  Integer counts make the result independent of
+// every order involved.
 #include "binning_core.hpp"
 
 #include <algorithm>
@@ -40,7 +44,6 @@ constexpr int kPartThreads = 256;
 constexpr int kMaxBins = 512;                    // buckets per partition level
 constexpr int kKeyWavesMax = 16 * kBinWaves;      // key-pass waves per compute unit, at most (per-wave state)
 constexpr int kAccThreads = 512;
-constexpr int kAccUnroll = 16;
 
 struct PartHeader {
     unsigned long long reserved;  // key slots reserved by the key pass of the current chunk
@@ -60,8 +63,8 @@ struct PartLayout {
     unsigned long long budget;  // keys every chunk but the last processes, at least
     int64_t hist_rows;      // super-tile rows of the per-tile histogram
     bool counted;           // the key pass counts the level-1 buckets (nb1 <= kHistBins)
-    size_t off_guard, off_hdr, off_wave, off_off1, off_tiles1, off_offb, off_tot, off_thist, off_hrows, off_keysa,
-        off_keysb, total;
+    size_t off_guard, off_hdr, off_wave, off_off1, off_tiles1, off_tot, off_thist, off_hrows, off_keysa, off_keysb,
+        total;
 };
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -103,12 +106,11 @@ static bool plan_layout(PartLayout &L, int64_t n, int64_t ncells, int img_bound,
     L.off_wave = o; o = align256(o + sizeof(int64_t) * (size_t)device_cus() * kKeyWavesMax);
     L.off_off1 = o; o = align256(o + sizeof(uint32_t) * (L.nb1 + 1));
     L.off_tiles1 = o; o = align256(o + sizeof(uint32_t) * (L.nb1 + 1));
-    L.off_offb = o; o = align256(o + sizeof(uint32_t) * (L.nblk + 1));
-    L.off_tot = o; o = align256(o + sizeof(uint32_t) * std::max<int64_t>(L.nb1, L.nblk));
+    L.off_tot = o; o = align256(o + sizeof(uint32_t) * L.nb1);
     const size_t fixed_head = o;
     unsigned long long margin, slack;
     claim_reserve(n, img_bound, margin, slack);
-    const int wide = std::max(L.nb1, L.nb2);
+    const int wide = std::max(L.nb1, L.nb2 + 1);  // level-1 counts, level-2 run starts (and the tile end)
     unsigned long long cap;
     if (want_keys > 0) {
         // two reservations of headroom: a layout re-derived from this one's byte count
@@ -289,7 +291,8 @@ struct PartStep {
     const PartHeader *hdr;      // level 1: reserved slots
     unsigned long long cap;
     int shift, nbins;
-    uint32_t *tile_hist;        // [ntiles][nbins]: counts, then offsets inside the bucket
+    uint32_t *tile_hist;        // level 1: [ntiles][nbins] counts, then offsets inside the bucket;
+                                // level 2: [ntiles][nbins + 1] run starts inside the tile, then its key count
     uint32_t *bucket_tot;       // [nseg * nbins]
     uint32_t *bucket_base;      // [nseg * nbins + 1] exclusive scan of bucket_tot
     int64_t max_tiles;          // rows allocated in tile_hist
@@ -407,22 +410,15 @@ __global__ __launch_bounds__(kHistBins) void l1_rows_kernel(PartStep ps, const u
     }
 }
 
-// one workgroup per global bucket g = seg * nbins + b: exclusive offsets of the
-// bucket's keys over the super-tiles of its segment, and the bucket total
+// level 1, one workgroup per bucket b: exclusive offsets of the bucket's keys
+// over the super-tiles, and the bucket total
 __global__ __launch_bounds__(256) void bucket_scan_kernel(PartStep ps) {
     __shared__ uint32_t wsum[4];
     if (!ps.hdr->active) return;
     const int64_t g = blockIdx.x;
-    const int seg = (int)(g / ps.nbins), b = (int)(g % ps.nbins);
+    const int b = (int)g;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int64_t t0, t1;
-    if (ps.level == 1) {
-        t0 = 0;
-        t1 = step_tiles(ps);
-    } else {
-        t0 = ps.seg_tiles[seg];
-        t1 = ps.seg_tiles[seg + 1];
-    }
+    const int64_t t0 = 0, t1 = step_tiles(ps);
     uint32_t carry = 0;
     for (int64_t base = t0; base < t1; base += 256) {
         const int64_t t = base + threadIdx.x;
@@ -443,8 +439,8 @@ __global__ __launch_bounds__(256) void bucket_scan_kernel(PartStep ps) {
     if (threadIdx.x == 0) ps.bucket_tot[g] = carry;
 }
 
-// exclusive scan of the bucket totals (one workgroup, running carry); for level 1
-// also the first super-tile of every level-2 segment.  Each thread scans kPer
+// exclusive scan of the level-1 bucket totals (one workgroup, running carry),
+// and the first super-tile of every level-2 segment.  Each thread scans kPer
 // consecutive totals serially; the thread sums are scanned across the wave
 // with shuffles and across the 16 waves through LDS: two barriers per
 // 1024 * kPer totals.
@@ -515,11 +511,14 @@ __global__ __launch_bounds__(1024) void bucket_base_kernel(const uint32_t *tot, 
 // a bucket-order scan, an LDS sort, then contiguous runs written at base + tile
 // offset + running count.  Key order inside a bucket is irrelevant to the
 // counts, so the nondeterministic order of the atomics is harmless.
+// kInPlace (level 2): the sorted tile goes back to the positions it came from
+// and the tile's row of tile_hist receives its bucket starts.
 constexpr int kScatThreads = 1024;  // 16 waves per compute unit: about 12 % faster than 512
 constexpr int kSub = kSuper;
-template <typename OutT>
+template <typename OutT, bool kInPlace = false>
 __global__ __launch_bounds__(kScatThreads, 1) void scatter_kernel(PartStep ps) {
     static_assert(sizeof(OutT) == 4 || sizeof(OutT) == 2, "full keys or 16-bit cell indices");
+    static_assert(!kInPlace || (kSub == kSuper && sizeof(OutT) == 2), "an in-place tile is one sub-tile of cells");
     static_assert(kBlockShift <= 16, "a cell index inside a block fits 16 bits");
     constexpr int kW = kScatThreads / 64;
     constexpr int kPer = kSub / kScatThreads;  // keys per thread per sub-tile
@@ -540,7 +539,7 @@ __global__ __launch_bounds__(kScatThreads, 1) void scatter_kernel(PartStep ps) {
         int64_t lo, hi;
         seg_range(ps, t, seg, lo, hi);
         const uint32_t bin0 = (uint32_t)seg * (uint32_t)ps.nbins;
-        if (tid < ps.nbins) {
+        if (!kInPlace && tid < ps.nbins) {
             gbase[tid] = ps.bucket_base[bin0 + tid] + ps.tile_hist[t * (int64_t)ps.nbins + tid];
             run[tid] = 0u;
         }
@@ -578,9 +577,11 @@ __global__ __launch_bounds__(kScatThreads, 1) void scatter_kernel(PartStep ps) {
             for (int k = 0; k < w; ++k) acc += wsum[k];
             if (tid < ps.nbins) {
                 soff[tid] = acc;
-                dst[tid] = gbase[tid] + run[tid] - acc;
+                if (!kInPlace) dst[tid] = gbase[tid] + run[tid] - acc;
             }
             if (tid == kScatThreads - 1) soff[ps.nbins] = acc + c;
+            if (kInPlace && tid <= ps.nbins)
+                ps.tile_hist[t * (int64_t)(ps.nbins + 1) + tid] = tid < ps.nbins ? acc : acc + c;
             lds_barrier();                                                  // 4
             // the keys placed in bucket order
             if (rem > 0) {
@@ -596,7 +597,7 @@ __global__ __launch_bounds__(kScatThreads, 1) void scatter_kernel(PartStep ps) {
                 for (int j = 0; j < kPer; ++j) {
                     const uint32_t sidx = (uint32_t)(j * kScatThreads + tid);
                     const uint32_t key = skeys[min(sidx, nv - 1u)];
-                    const uint32_t pos = dst[(key >> ps.shift) - bin0] + sidx;
+                    const uint32_t pos = (kInPlace ? (uint32_t)sub : dst[(key >> ps.shift) - bin0]) + sidx;
                     if (sidx < nv) {
                         if constexpr (sizeof(OutT) == 4)
                             ps.out[pos] = key;
@@ -606,36 +607,97 @@ __global__ __launch_bounds__(kScatThreads, 1) void scatter_kernel(PartStep ps) {
                 }
             }
             lds_barrier();                                                  // 6
-            if (tid < ps.nbins) run[tid] += soff[tid + 1] - soff[tid];
+            if (!kInPlace && tid < ps.nbins) run[tid] += soff[tid + 1] - soff[tid];
         }
     }
 }
 
-// 5. one workgroup per cell block: LDS histogram, then counts += histogram
-__global__ __launch_bounds__(kAccThreads) void accumulate_kernel(const uint16_t *cells, const uint32_t *offb,
-                                                                 int64_t nblk, int64_t ncells, uint32_t *counts,
-                                                                 const PartHeader *hdr) {
+// 5. one workgroup per cell block g = seg * nbins + b of level 2: the block's
+// keys are one run in each super-tile of level-1 bucket seg (run starts in the
+// tile's row of tile_hist).  Up to kAccThreads runs at a time are listed in LDS;
+// kLanes lanes read one run in aligned 16-byte words of 8 cells (kLanes near a
+// quarter of the mean run, kSuper / nbins cells, so one word per lane covers
+// most runs), a wave reads kRows * 64 / kLanes runs at once (kRows loads per
+// lane in flight), and the cells of each word that lie inside the run go into
+// the LDS histogram; finally counts += histogram.
+template <int kLanes>
+__global__ __launch_bounds__(kAccThreads) void accumulate_kernel(PartStep ps, const uint16_t *cells, int64_t ncells,
+                                                                 uint32_t *counts) {
+    static_assert(kLanes == 16 || kLanes == 32 || kLanes == 64, "lanes per run divide the wave");
+    constexpr int kW = kAccThreads / 64;
+    constexpr int kRows = kLanes == 64 ? 8 : 4;  // within 128 registers: two workgroups per compute unit
+    constexpr int kRunsPerWave = kRows * 64 / kLanes;
     __shared__ uint32_t h[kBlockCells];
-    if (!hdr->active) return;
-    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        const uint32_t lo = offb[blk], hi = offb[blk + 1];
-        if (lo == hi) continue;  // uniform over the block
+    __shared__ uint32_t rlo[kAccThreads], rhi[kAccThreads];  // the pass's runs: cells [lo, hi)
+    __shared__ uint32_t nkeys;
+    if (!ps.hdr->active) return;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int slot = lane / kLanes, sub = lane % kLanes;  // run slot in a row, lane inside the run
+    const uint4 *words = reinterpret_cast<const uint4 *>(cells);  // the buffer is 256-byte aligned
+    const int64_t stride = ps.nbins + 1;
+    const int64_t nblk = (int64_t)ps.nseg * ps.nbins;
+    for (int64_t g = blockIdx.x; g < nblk; g += gridDim.x) {
+        const int seg = (int)(g / ps.nbins), b = (int)(g % ps.nbins);
+        const int64_t t0 = ps.seg_tiles[seg], t1 = ps.seg_tiles[seg + 1];
+        if (t0 == t1) continue;  // uniform over the block: an empty level-1 bucket
         for (int j = threadIdx.x; j < kBlockCells; j += kAccThreads) h[j] = 0u;
-        lds_barrier();
-        // 16 key loads in flight per thread
-        for (uint32_t base = lo; base < hi; base += kAccThreads * kAccUnroll) {
-            uint32_t kk[kAccUnroll];
-#pragma unroll
-            for (int u = 0; u < kAccUnroll; ++u) {
-                const uint32_t i = base + u * kAccThreads + threadIdx.x;
-                kk[u] = i < hi ? (uint32_t)cells[i] : kNoKey;
+        if (threadIdx.x == 0) nkeys = 0u;
+        const uint32_t sbase = ps.seg_off[seg];
+        uint32_t mine = 0;  // cells this thread listed
+        for (int64_t tb = t0; tb < t1; tb += kAccThreads) {
+            const int64_t tt = tb + threadIdx.x;
+            uint32_t lo = 0u, hi = 0u;
+            if (tt < t1) {
+                const uint32_t *row = ps.tile_hist + tt * stride;
+                const uint32_t base = sbase + (uint32_t)(tt - t0) * (uint32_t)kSuper;
+                lo = base + row[b];
+                hi = base + row[b + 1];
             }
+            rlo[threadIdx.x] = lo;
+            rhi[threadIdx.x] = hi;
+            mine += hi - lo;
+            lds_barrier();  // the list is complete (and, on the first pass, h is clear)
+            const int nr = (int)(t1 - tb < kAccThreads ? t1 - tb : kAccThreads);
+            for (int r0 = w * kRunsPerWave; r0 < nr; r0 += kW * kRunsPerWave) {
+                // this lane's run in row p: r0 + p * (64 / kLanes) + slot
+                uint32_t clo[kRows], chi[kRows], w0[kRows], nw[kRows], longest = 0;
 #pragma unroll
-            for (int u = 0; u < kAccUnroll; ++u)
-                if (kk[u] != kNoKey) atomicAdd(&h[kk[u]], 1u);
+                for (int p = 0; p < kRows; ++p) {
+                    const int r = r0 + p * (64 / kLanes) + slot;
+                    clo[p] = r < nr ? rlo[r] : 0u;
+                    chi[p] = r < nr ? rhi[r] : 0u;
+                    w0[p] = clo[p] >> 3;
+                    nw[p] = chi[p] > clo[p] ? ((chi[p] + 7u) >> 3) - w0[p] : 0u;
+                    longest = max(longest, nw[p]);
+                }
+                for (uint32_t k = 0; wave_ballot(k < longest) != 0ull; k += kLanes) {
+                    uint4 v[kRows];
+#pragma unroll
+                    for (int p = 0; p < kRows; ++p) {
+                        const uint32_t kk = k + (uint32_t)sub;
+                        v[p] = kk < nw[p] ? words[w0[p] + kk] : make_uint4(0u, 0u, 0u, 0u);
+                    }
+#pragma unroll
+                    for (int p = 0; p < kRows; ++p) {
+                        // cells [e0, e0 + 8) of the word; those in [clo, chi) count
+                        const uint32_t e0 = (w0[p] + k + (uint32_t)sub) * 8u;
+                        const uint32_t qlo = clo[p] > e0 ? clo[p] - e0 : 0u;
+                        const uint32_t qhi = chi[p] > e0 ? min(chi[p] - e0, 8u) : 0u;
+                        const uint32_t m = ((1u << qhi) - 1u) & ~((1u << qlo) - 1u);
+                        const uint32_t x[4] = {v[p].x, v[p].y, v[p].z, v[p].w};
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            if (m & (1u << q)) atomicAdd(&h[(x[q >> 1] >> (16 * (q & 1))) & 0xFFFFu], 1u);
+                    }
+                }
+            }
+            lds_barrier();  // every wave is done with the list before the next pass rewrites it
         }
+        if (mine) atomicAdd(&nkeys, mine);
         lds_barrier();
-        const int64_t c0 = blk * kBlockCells;
+        if (nkeys == 0u) continue;  // uniform: a block without keys keeps its counts untouched
+        const int64_t c0 = g * kBlockCells;
         const int64_t cn = c0 + kBlockCells < ncells ? kBlockCells : ncells - c0;  // multiple of 4
         uint4 *dst = reinterpret_cast<uint4 *>(counts + c0);
         const int nq = (int)(cn / 4);
@@ -715,7 +777,6 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
     PartHeader *hdr = reinterpret_cast<PartHeader *>(ws + L.off_hdr);
     uint32_t *off1 = reinterpret_cast<uint32_t *>(ws + L.off_off1);
     uint32_t *tiles1 = reinterpret_cast<uint32_t *>(ws + L.off_tiles1);
-    uint32_t *offb = reinterpret_cast<uint32_t *>(ws + L.off_offb);
     uint32_t *tot = reinterpret_cast<uint32_t *>(ws + L.off_tot);
     uint32_t *thist = reinterpret_cast<uint32_t *>(ws + L.off_thist);
     uint32_t *keysa = reinterpret_cast<uint32_t *>(ws + L.off_keysa);
@@ -769,11 +830,15 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
     l2.seg_tiles = tiles1;
     l2.shift = kBlockShift;
     l2.nbins = L.nb2;
-    l2.bucket_base = offb;
+    l2.bucket_base = nullptr;  // in place: runs stay inside their super-tiles
+    l2.bucket_tot = nullptr;
 
     const unsigned hist_grid = resident_grid(tile_hist_kernel, kPartThreads, cus);
     const unsigned scat_grid = resident_grid(scatter_kernel<uint32_t>, kScatThreads, cus);
-    const unsigned acc_grid = resident_grid(accumulate_kernel, kAccThreads, cus);
+    // lanes per run near a quarter of the mean run (kSuper / nb2 cells): about one 8-cell word per lane
+    const int mean_run = kSuper / L.nb2;
+    auto acc = mean_run <= 64 ? accumulate_kernel<16> : (mean_run <= 128 ? accumulate_kernel<32> : accumulate_kernel<64>);
+    const unsigned acc_grid = resident_grid(acc, kAccThreads, cus);
     for (int k = 0; k < L.kmax; ++k) {
         hipLaunchKernelGGL(reset_chunk_kernel, dim3(1), dim3(64), 0, s, hdr, p.c.n, k == 0 ? 1 : 0);
         kp.margin = L.margin;
@@ -791,14 +856,11 @@ int launch_partitioned(BinParams p, const PartLayout &L, int img_bound, char *ws
         hipLaunchKernelGGL(bucket_scan_kernel, dim3((unsigned)L.nb1), dim3(256), 0, s, l1);
         hipLaunchKernelGGL(bucket_base_kernel, dim3(1), dim3(1024), 0, s, tot, (int64_t)L.nb1, off1, tiles1, hdr);
         hipLaunchKernelGGL(scatter_kernel<uint32_t>, dim3(scat_grid), dim3(kScatThreads), 0, s, l1);
-        // level 2: by cell block inside each level-1 bucket
-        hipLaunchKernelGGL(tile_hist_kernel, dim3(hist_grid), dim3(kPartThreads), 0, s, l2);
-        hipLaunchKernelGGL(bucket_scan_kernel, dim3((unsigned)L.nblk), dim3(256), 0, s, l2);
-        hipLaunchKernelGGL(bucket_base_kernel, dim3(1), dim3(1024), 0, s, tot, L.nblk, offb, (uint32_t *)nullptr, hdr);
-        hipLaunchKernelGGL(scatter_kernel<uint16_t>, dim3(scat_grid), dim3(kScatThreads), 0, s, l2);
+        // level 2: every super-tile of a level-1 bucket sorted by cell block, in place
+        hipLaunchKernelGGL((scatter_kernel<uint16_t, true>), dim3(scat_grid), dim3(kScatThreads), 0, s, l2);
         timer_mark(timer, UFALCON_PHASE_PARTITION, s);
-        hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)std::min<int64_t>(L.nblk, acc_grid)), dim3(kAccThreads), 0,
-                           s, reinterpret_cast<const uint16_t *>(keysa), offb, L.nblk, ncells, p.c.counts, hdr);
+        hipLaunchKernelGGL(acc, dim3((unsigned)std::min<int64_t>(L.nblk, acc_grid)), dim3(kAccThreads), 0, s, l2,
+                           reinterpret_cast<const uint16_t *>(keysa), ncells, p.c.counts);
         timer_mark(timer, UFALCON_PHASE_ACCUMULATE, s);
         if (k == 0 && fault_injected("partition_chunk")) {  // tests of error handling; never inside a capture
             hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
