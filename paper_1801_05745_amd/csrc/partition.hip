@@ -271,15 +271,16 @@ static int key_wgs_per_cu() {
 }
 
 // Partition steps.  Level 1: one segment keys[0, reserved) (with sentinels),
-// bucket = key >> shift.  Level 2: segment s = level-1 bucket s (keys with
-// key >> s1 == s), bucket = (key >> shift) - s * nbins; the global bucket
-// s * nbins + b is the cell block.  Each segment is cut into super-tiles of
-// kSuper keys; tile_hist writes the per-super-tile bucket counts, bucket_scan
-// turns them into per-super-tile write offsets inside each bucket (and bucket
-// totals), bucket_base scans the totals, and scatter writes every key at
-// base[bucket] + offset[tile][bucket] + its rank inside the super-tile, sorting
-// each super-tile in LDS so that each bucket's keys leave as contiguous runs.
-// No global atomics; ranks inside a sub-tile come from LDS atomics.
+// bucket = key >> shift, cut into super-tiles of kSuper keys; the per-tile
+// bucket counts (l1_rows or tile_hist) are scanned per bucket by bucket_scan
+// into per-tile write offsets (and bucket totals), bucket_base scans the
+// totals, and scatter writes every key at base[bucket] + offset[bucket][tile]
+// + its rank inside the super-tile, sorting each super-tile in LDS so that each
+// bucket's keys leave as contiguous runs.  Level 2: segment s = level-1 bucket
+// s (keys with key >> s1 == s), bucket = (key >> shift) - s * nbins, the global
+// bucket s * nbins + b being the cell block; each super-tile of a segment is
+// sorted in place and records where each bucket's run starts.  No global
+// atomics; ranks inside a sub-tile come from LDS atomics.
 struct PartStep {
     const uint32_t *in;
     uint32_t *out;              // level 1: full keys
@@ -291,11 +292,11 @@ struct PartStep {
     const PartHeader *hdr;      // level 1: reserved slots
     unsigned long long cap;
     int shift, nbins;
-    uint32_t *tile_hist;        // level 1: [ntiles][nbins] counts, then offsets inside the bucket;
+    uint32_t *tile_hist;        // level 1: [nbins][max_tiles] counts, then offsets inside the bucket;
                                 // level 2: [ntiles][nbins + 1] run starts inside the tile, then its key count
-    uint32_t *bucket_tot;       // [nseg * nbins]
-    uint32_t *bucket_base;      // [nseg * nbins + 1] exclusive scan of bucket_tot
-    int64_t max_tiles;          // rows allocated in tile_hist
+    uint32_t *bucket_tot;       // level 1: [nbins]
+    uint32_t *bucket_base;      // level 1: [nbins + 1] exclusive scan of bucket_tot
+    int64_t max_tiles;          // tiles allocated in tile_hist
 };
 
 __device__ __forceinline__ int64_t step_total(const PartStep &ps) {
@@ -381,11 +382,10 @@ __global__ __launch_bounds__(kPartThreads) void tile_hist_kernel(PartStep ps) {
                 wave_count(wh[w], (kk[u] >> ps.shift) - bin0, kk[u] != kNoKey);
         }
         lds_barrier();
-        uint32_t *row = ps.tile_hist + t * (int64_t)ps.nbins;
         for (int b = tid; b < ps.nbins; b += kPartThreads) {
             uint32_t c = 0;
             for (int k = 0; k < kW; ++k) c += wh[k][b];
-            row[b] = c;
+            ps.tile_hist[b * ps.max_tiles + t] = c;
         }
         lds_barrier();
     }
@@ -406,7 +406,7 @@ __global__ __launch_bounds__(kHistBins) void l1_rows_kernel(PartStep ps, const u
         const int64_t r1 = r0 + kPerTile < nres ? r0 + kPerTile : nres;
         uint32_t c = 0;
         for (int64_t r = r0; r < r1; ++r) c += hrows[r * kHistBins + b];
-        if (b < ps.nbins) ps.tile_hist[t * ps.nbins + b] = c;
+        if (b < ps.nbins) ps.tile_hist[b * ps.max_tiles + t] = c;
     }
 }
 
@@ -419,10 +419,11 @@ __global__ __launch_bounds__(256) void bucket_scan_kernel(PartStep ps) {
     const int b = (int)g;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t t0 = 0, t1 = step_tiles(ps);
+    uint32_t *col = ps.tile_hist + b * ps.max_tiles;  // the bucket's counts over the tiles, contiguous
     uint32_t carry = 0;
     for (int64_t base = t0; base < t1; base += 256) {
         const int64_t t = base + threadIdx.x;
-        const uint32_t v = t < t1 ? ps.tile_hist[t * (int64_t)ps.nbins + b] : 0u;
+        const uint32_t v = t < t1 ? col[t] : 0u;
         uint32_t x = v;  // inclusive scan inside the wave
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t y = __shfl_up(x, off, 64);
@@ -432,7 +433,7 @@ __global__ __launch_bounds__(256) void bucket_scan_kernel(PartStep ps) {
         __syncthreads();
         uint32_t before = carry;
         for (int k = 0; k < w; ++k) before += wsum[k];
-        if (t < t1) ps.tile_hist[t * (int64_t)ps.nbins + b] = before + x - v;
+        if (t < t1) col[t] = before + x - v;
         carry += wsum[0] + wsum[1] + wsum[2] + wsum[3];
         __syncthreads();
     }
@@ -540,7 +541,7 @@ __global__ __launch_bounds__(kScatThreads, 1) void scatter_kernel(PartStep ps) {
         seg_range(ps, t, seg, lo, hi);
         const uint32_t bin0 = (uint32_t)seg * (uint32_t)ps.nbins;
         if (!kInPlace && tid < ps.nbins) {
-            gbase[tid] = ps.bucket_base[bin0 + tid] + ps.tile_hist[t * (int64_t)ps.nbins + tid];
+            gbase[tid] = ps.bucket_base[bin0 + tid] + ps.tile_hist[tid * ps.max_tiles + t];
             run[tid] = 0u;
         }
         for (int64_t sub = lo; sub < hi; sub += kSub) {
