@@ -221,6 +221,9 @@ def log(msg):
 
 # ---------------------------------------------------------------- headline (batched, 16 realisations)
 
+TUNE_SAMPLE = 4  # realisations the headline's autotuner times each candidate on
+
+
 def batched16(dev, args, order=None, steps=None, warmup=None, plain_reps=2, roofline=True):
     import torch
 
@@ -259,7 +262,9 @@ def batched16(dev, args, order=None, steps=None, warmup=None, plain_reps=2, roof
 
     scalars()
     t0 = time.time()
-    tuning = uf.autotune_batch(items, nside, T=1, sample_items=2)
+    # four realisations: the persistent atomic kernel gains on longer batches, and a
+    # two-item sample under-rates it against the per-item partitioned pipeline
+    tuning = uf.autotune_batch(items, nside, T=1, sample_items=TUNE_SAMPLE)
     tune_s = time.time() - t0
     log(f"headline: autotuned in {tune_s:.1f} s -> {tuning['method']}")
     plan = uf.BatchPlan(items, nside, T=1, method="auto")
@@ -367,7 +372,7 @@ def batched16(dev, args, order=None, steps=None, warmup=None, plain_reps=2, roof
         "maps_per_s_batched": 16e3 / ms_per_step, "plain": plain,
         "batched_equals_plain": match,
         "tuning": {"method": tuning["method"], "tile": tuning["tile"], "persistent_wgs": tuning["persistent_wgs"],
-                   "candidates": tuning["candidates"], "tune_s": tune_s, "sample_items": 2},
+                   "candidates": tuning["candidates"], "tune_s": tune_s, "sample_items": TUNE_SAMPLE},
         "input_generation_s": gen_s,
     }
     if roofline and not args.no_plain:
