@@ -130,7 +130,7 @@ static bool plan_layout(PartLayout &L, int64_t n, int64_t ncells, int img_bound,
     cap = cap / kKeyChunk * kKeyChunk;
     // every chunk but the last must keep at least half of the buffer
     if (cap < 2 * (margin + slack) + kKeyChunk) return false;
-    L.hist_rows = (int64_t)(cap / kSuper) + L.nb1 + 2;
+    L.hist_rows = ((int64_t)(cap / kSuper) + L.nb1 + 2 + 15) / 16 * 16;  // whole groups of 16 tiles
     L.off_thist = o; o = align256(o + sizeof(uint32_t) * (size_t)wide * L.hist_rows);
     L.counted = L.nb1 <= kHistBins;
     L.off_hrows = o;
@@ -393,20 +393,31 @@ __global__ __launch_bounds__(kPartThreads) void tile_hist_kernel(PartStep ps) {
 
 // Level-1 bucket counts per super-tile from the key pass's per-reservation
 // counts (super-tile t holds reservations t * kSuper / kKeyChunk onwards): the
-// tile_hist of level 1 without reading the keys.
+// tile_hist of level 1 without reading the keys.  A workgroup takes kRowGroup
+// consecutive tiles, so that each bucket's counts leave as 16-byte stores
+// (max_tiles is a multiple of kRowGroup; counts past the last tile are zero).
 static_assert(kSuper % kKeyChunk == 0, "super-tiles are whole reservations");
+constexpr int kRowGroup = 16;
 __global__ __launch_bounds__(kHistBins) void l1_rows_kernel(PartStep ps, const uint16_t *hrows) {
     constexpr int kPerTile = kSuper / kKeyChunk;
     if (!ps.hdr->active) return;
     const int64_t nres = step_total(ps) / kKeyChunk;  // reserved slots come in whole reservations
-    const int64_t ntiles = step_tiles(ps);
+    const int64_t ngroups = (step_tiles(ps) + kRowGroup - 1) / kRowGroup;
     const int b = threadIdx.x;
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int64_t r0 = t * kPerTile;
-        const int64_t r1 = r0 + kPerTile < nres ? r0 + kPerTile : nres;
-        uint32_t c = 0;
-        for (int64_t r = r0; r < r1; ++r) c += hrows[r * kHistBins + b];
-        if (b < ps.nbins) ps.tile_hist[b * ps.max_tiles + t] = c;
+    for (int64_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
+        uint32_t c[kRowGroup];
+#pragma unroll
+        for (int i = 0; i < kRowGroup; ++i) {
+            const int64_t r0 = (gi * kRowGroup + i) * kPerTile;
+            const int64_t r1 = r0 + kPerTile < nres ? r0 + kPerTile : nres;
+            c[i] = 0u;
+            for (int64_t r = r0; r < r1; ++r) c[i] += hrows[r * kHistBins + b];
+        }
+        if (b < ps.nbins) {
+            uint4 *dst = reinterpret_cast<uint4 *>(ps.tile_hist + b * ps.max_tiles + gi * kRowGroup);
+#pragma unroll
+            for (int i = 0; i < kRowGroup / 4; ++i) dst[i] = make_uint4(c[4 * i], c[4 * i + 1], c[4 * i + 2], c[4 * i + 3]);
+        }
     }
 }
 
