@@ -132,6 +132,13 @@ int ufalcon_counts_to_i64(const uint32_t *counts, int64_t n, int64_t *out, int a
 size_t ufalcon_bin_shells_workspace_size(int64_t max_listed);
 size_t ufalcon_bin_shells_workspace_size_partitioned(int64_t n, int32_t n_rep, int32_t shells_in_range,
                                                      int64_t nside, int64_t max_keys);
+/* Keys one chunk of the partitioned accumulation takes at least with a workspace
+ * of `bytes` (host computation, no device call; the layout assumes all
+ * (2 n_rep + 1)^3 images can reach the range); 0 when that workspace selects
+ * the atomic path or an argument is out of range.  A workspace of
+ * ufalcon_bin_shells_workspace_size_partitioned(..., k) bytes holds at least k. */
+int64_t ufalcon_bin_shells_partition_capacity(int64_t n, int32_t n_rep, int32_t shells_in_range, int64_t nside,
+                                              size_t bytes);
 int ufalcon_bin_shells(const void *x, const void *y, const void *z, int64_t n, int dtype,
                        const double *observer, double box_L, int32_t n_rep,
                        const double *chi_edges, int32_t n_shells, int32_t shell_begin, int32_t shell_end,

@@ -74,6 +74,7 @@ _SIGS = {
     "ufalcon_counts_to_i64": (ctypes.c_int, [_P, _I64, _P, ctypes.c_int, _P]),
     "ufalcon_bin_shells_workspace_size": (_SZ, [_I64]),
     "ufalcon_bin_shells_workspace_size_partitioned": (_SZ, [_I64, _I32, _I32, _I64, _I64]),
+    "ufalcon_bin_shells_partition_capacity": (_I64, [_I64, _I32, _I32, _I64, _SZ]),
     "ufalcon_bin_shells": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, ctypes.POINTER(_D), _D, _I32,
                                           ctypes.POINTER(_D), _I32, _I32, _I32, _I64, _P, _P, _P, _SZ, _P]),
     "ufalcon_bin_shells_timed": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.c_int, ctypes.POINTER(_D), _D, _I32,
@@ -196,6 +197,13 @@ def bin_shells_workspace(max_listed: int = 1 << 20, device="cuda"):
 
 
 MAX_PARTITION_KEYS = 0xFFF00000 - (1 << 25)
+
+
+def partition_capacity(n, n_rep, shells_in_range, nside, nbytes):
+    """Keys one chunk of the partitioned accumulation takes at least with a workspace of
+    nbytes (0: that workspace selects the atomic path); a host computation."""
+    return int(load().ufalcon_bin_shells_partition_capacity(int(n), int(n_rep), int(shells_in_range), int(nside),
+                                                            int(nbytes)))
 
 
 def partition_workspace(n, n_rep, shells_in_range, nside, max_keys=None, device="cuda", cached=True):

@@ -121,7 +121,8 @@ static bool plan_layout(PartLayout &L, int64_t n, int64_t ncells, int img_bound,
         // level-1 counts + two key buffers
         const double per_key = 2.0 * sizeof(uint32_t) + (double)wide * sizeof(uint32_t) / kSuper +
                                (L.nb1 <= kHistBins ? (double)kHistBins * sizeof(uint16_t) / kKeyChunk : 0.0);
-        const size_t extra = sizeof(uint32_t) * (size_t)wide * (L.nb1 + 2) + 4096;
+        // the rows beyond cap / kSuper: nb1 + 2, and up to 15 more that round to whole groups of 16
+        const size_t extra = sizeof(uint32_t) * (size_t)wide * (L.nb1 + 2 + 15) + 4096;
         if (bytes < fixed_head + extra) return false;
         cap = (unsigned long long)((double)(bytes - fixed_head - extra) / per_key);
     }
@@ -919,6 +920,17 @@ size_t partitioned_workspace_size(int64_t n, int64_t ncells, int img_bound, int6
 }  // namespace ufx
 
 using namespace ufx;
+
+extern "C" int64_t ufalcon_bin_shells_partition_capacity(int64_t n, int32_t n_rep, int32_t shells_in_range,
+                                                         int64_t nside, size_t bytes) {
+    if (n < 0 || n_rep < 0 || n_rep > 64 || shells_in_range < 1 || nside < 1 || nside > UFALCON_MAX_NSIDE)
+        return 0;
+    const int side = 2 * n_rep + 1;
+    PartLayout L;
+    if (!plan_layout(L, n, (int64_t)shells_in_range * npix_of(nside), side * side * side, bytes, 0) || L.total > bytes)
+        return 0;
+    return (int64_t)L.budget;
+}
 
 extern "C" size_t ufalcon_bin_shells_workspace_size_partitioned(int64_t n, int32_t n_rep, int32_t shells_in_range,
                                                                 int64_t nside, int64_t max_keys) {

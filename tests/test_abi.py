@@ -208,6 +208,38 @@ def test_partitioned_workspace_sizes_exist():
                 assert lib.ufalcon_bin_shells_workspace_size_partitioned(n, R, 30, nside, n * (2 * R + 1) ** 3) > 0
 
 
+def test_partitioned_workspace_holds_what_it_was_sized_for():
+    # a workspace sized for k keys per chunk is re-planned from its byte count by
+    # every call (and by each item of a batch plan): that layout must fit in the
+    # bytes and still take at least k keys per chunk, up to the 32-bit offset cap
+    for n in (1, 1000, 1 << 20, 1 << 26, 1 << 28):
+        for R in (0, 1, 2, 3):
+            for shells, nside in ((1, 1), (30, 1024), (60, 1024), (4, 2048), (256, 512)):
+                k = min(n * (2 * R + 1) ** 3, uf.MAX_PARTITION_KEYS)
+                nbytes = uf.load().ufalcon_bin_shells_workspace_size_partitioned(n, R, shells, nside, k)
+                assert nbytes > 0
+                cap = uf.partition_capacity(n, R, shells, nside, nbytes)
+                # near the cap the claim margin comes off the chunk; the chunk loop takes the rest
+                assert cap >= k if k <= 1 << 31 else cap > 3 << 30, (n, R, shells, nside, k, cap)
+                # one byte less never selects a layout that overruns it
+                assert uf.partition_capacity(n, R, shells, nside, nbytes - 1) >= 0
+
+
+def test_partitioned_workspace_shared_by_a_batch():
+    # a batch plan sizes one workspace for its largest realisation (keys per chunk
+    # below the 32-bit cap) and re-plans every realisation, with its own shell and
+    # bucket counts, in it: each layout must fit and take its own keys per chunk
+    M = 1 << 20
+    for R in (1, 2):
+        for nside in (512, 1024):
+            items = [((64 + 3 * j) * M + 12345 * j, 20 + j % 41, int(1e9 + 4.7e7 * j)) for j in range(64)]
+            nbytes = max(uf.load().ufalcon_bin_shells_workspace_size_partitioned(n, R, b, nside, k)
+                         for n, b, k in items)
+            for n, b, k in items:
+                cap = uf.partition_capacity(n, R, b, nside, nbytes)
+                assert cap >= k, (n, R, b, nside, k, cap)
+
+
 def test_tuning_file_round_trip(tmp_path):
     # persisted autotuner choices: a file read into the cache is written back the same
     lines = ['{"arch":"gfx950","cus":256,"dtype":0,"nside":1024,"T":1,"items":16,"log2n":31,"max_rep":2,'
