@@ -162,6 +162,23 @@ def test_partitioned_path_several_chunks(ufalcon):
     assert uf.status_dict(st)["n_instances"] == int(ref.sum())
 
 
+@pytest.mark.parametrize("nside,R,max_keys", [(64, 1, 2_000_000), (256, 2, None)])
+def test_partitioned_path_cell_ordered(ufalcon, nside, R, max_keys):
+    # particles sorted by grid cell: neighbouring keys share buckets and cell
+    # blocks, so the partition's LDS ranks contend on few counters and the
+    # second level's runs are long and uneven (a super-tile leaves most blocks
+    # no key and a few thousands); with max_keys the particles run in chunks
+    L = 100.0
+    n = 400_003
+    x, y, z = synth.lognormal_box(n, L, seed=5, ngrid=64, dtype=torch.float32, order="cell")
+    edges = [5.0, 20.0, 40.0, 61.0, 90.0, 130.0, 180.0, 240.0][: 3 + 2 * R]
+    ws = uf.partition_workspace(n, R, len(edges) - 1, nside, max_keys=max_keys, device=DEV, cached=False)
+    got, st = _gpu_counts(x, y, z, edges, nside, L, R, workspace=ws, method="partition")
+    ref, _ = obin.bin_shells(x, y, z, (50.0,) * 3, L, R, edges, nside, threads=8)
+    assert np.array_equal(got, ref)
+    assert st["n_instances"] == int(ref.sum()) and st["n_fallback"] == 0
+
+
 @pytest.mark.parametrize("method", ["partition", "atomic"])
 def test_phase_timer_records_phases_without_changing_counts(ufalcon, method):
     L = 100.0
