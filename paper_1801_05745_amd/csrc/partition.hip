@@ -525,7 +525,13 @@ __global__ __launch_bounds__(1024) void bucket_base_kernel(const uint32_t *tot, 
 // offset + running count.  Key order inside a bucket is irrelevant to the
 // counts, so the nondeterministic order of the atomics is harmless.
 // kInPlace (level 2): the sorted tile goes back to the positions it came from
-// and the tile's row of tile_hist receives its bucket starts.
+// and the tile's row of tile_hist receives its bucket starts.  Each bucket's
+// count is split over 2^ss lane classes (lane mod 4, fewer when the buckets are
+// many: one counter per thread in the scan): the keys of a wave that share a
+// bucket, as spatially ordered particles' keys do, then contend on four LDS
+// counters rather than one (partition 42 % faster on cell-ordered particles,
+// 2 % slower on shuffled ones), and a bucket's classes stay adjacent in the
+// sorted order.
 constexpr int kScatThreads = 1024;  // 16 waves per compute unit: about 12 % faster than 512
 constexpr int kSub = kSuper;
 template <typename OutT, bool kInPlace = false>
@@ -535,17 +541,21 @@ __global__ __launch_bounds__(kScatThreads, 1) void scatter_kernel(PartStep ps) {
     static_assert(kBlockShift <= 16, "a cell index inside a block fits 16 bits");
     constexpr int kW = kScatThreads / 64;
     constexpr int kPer = kSub / kScatThreads;  // keys per thread per sub-tile
-    static_assert(kMaxBins <= kScatThreads, "one bucket per thread in the scan");
-    static_assert(kSub <= 65536 && kMaxBins <= 65536, "bucket and rank packed in 16-bit halves");
-    __shared__ uint32_t cnt[kMaxBins];       // keys per bucket in the sub-tile
-    __shared__ uint32_t gbase[kMaxBins];     // global start of this super-tile's run per bucket
-    __shared__ uint32_t run[kMaxBins];       // keys of the bucket written by earlier sub-tiles
-    __shared__ uint32_t soff[kMaxBins + 1];  // bucket start inside the sorted sub-tile
-    __shared__ uint32_t dst[kMaxBins];       // global position of sorted slot 0 of the bucket (mod 2^32)
+    static_assert(kMaxBins <= kScatThreads, "one counter per thread in the scan");
+    static_assert(kSub <= 65536 && kScatThreads <= 65536, "counter and rank packed in 16-bit halves");
+    __shared__ uint32_t cnt[kScatThreads];       // keys per (bucket, lane class) in the sub-tile
+    __shared__ uint32_t gbase[kMaxBins];         // global start of this super-tile's run per bucket
+    __shared__ uint32_t run[kMaxBins];           // keys of the bucket written by earlier sub-tiles
+    __shared__ uint32_t soff[kScatThreads + 1];  // (bucket, class) start inside the sorted sub-tile
+    __shared__ uint32_t dst[kMaxBins];           // global position of sorted slot 0 of the bucket (mod 2^32)
     __shared__ uint32_t skeys[kSub];
     __shared__ uint32_t wsum[kW];
     if (!ps.hdr->active) return;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    int ss = 0;  // lane classes per bucket: 2^ss
+    while (ss < 2 && (ps.nbins << (ss + 1)) <= kScatThreads) ++ss;
+    const int nsub = ps.nbins << ss;
+    const uint32_t cls = (uint32_t)lane & ((1u << ss) - 1u);
     const int64_t ntiles = step_tiles(ps);
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         int seg;
@@ -558,9 +568,9 @@ __global__ __launch_bounds__(kScatThreads, 1) void scatter_kernel(PartStep ps) {
         }
         for (int64_t sub = lo; sub < hi; sub += kSub) {
             const int64_t shi = sub + kSub < hi ? sub + kSub : hi;
-            if (tid < ps.nbins) cnt[tid] = 0u;
+            if (tid < nsub) cnt[tid] = 0u;
             lds_barrier();                                                  // 1
-            // rank pass; rk = bucket << 16 | rank inside the bucket, ~0 for no key.
+            // rank pass; rk = counter << 16 | rank at the counter, ~0 for no key.
             // Loads are unconditional at clamped indices so that all of them are in
             // flight together; a wave with no keys in the sub-tile skips them.
             const int64_t w0 = sub + (int64_t)w * kPer * 64;  // wave w: keys [w0, w0 + kPer 64)
@@ -573,13 +583,13 @@ __global__ __launch_bounds__(kScatThreads, 1) void scatter_kernel(PartStep ps) {
 #pragma unroll
                 for (int u = 0; u < kPer; ++u) {
                     const bool valid = u * 64 + lane < rem && kv[u] != kNoKey;
-                    const uint32_t bkt = (kv[u] >> ps.shift) - bin0;
-                    rk[u] = valid ? bkt << 16 | atomicAdd(&cnt[bkt], 1u) : ~0u;
+                    const uint32_t sb = ((kv[u] >> ps.shift) - bin0) << ss | cls;
+                    rk[u] = valid ? sb << 16 | atomicAdd(&cnt[sb], 1u) : ~0u;
                 }
             }
             lds_barrier();                                                  // 2
-            const uint32_t c = tid < ps.nbins ? cnt[tid] : 0u;
-            uint32_t x = c;  // inclusive scan within the wave, bucket order = thread order
+            const uint32_t c = tid < nsub ? cnt[tid] : 0u;
+            uint32_t x = c;  // inclusive scan within the wave, counter order = thread order
             for (int off = 1; off < 64; off <<= 1) {
                 const uint32_t y = __shfl_up(x, off, 64);
                 if (lane >= off) x += y;
@@ -588,22 +598,22 @@ __global__ __launch_bounds__(kScatThreads, 1) void scatter_kernel(PartStep ps) {
             lds_barrier();                                                  // 3
             uint32_t acc = x - c;
             for (int k = 0; k < w; ++k) acc += wsum[k];
-            if (tid < ps.nbins) {
-                soff[tid] = acc;
-                if (!kInPlace) dst[tid] = gbase[tid] + run[tid] - acc;
-            }
-            if (tid == kScatThreads - 1) soff[ps.nbins] = acc + c;
-            if (kInPlace && tid <= ps.nbins)
-                ps.tile_hist[t * (int64_t)(ps.nbins + 1) + tid] = tid < ps.nbins ? acc : acc + c;
+            if (tid < nsub) soff[tid] = acc;
+            if (tid == kScatThreads - 1) soff[nsub] = acc + c;
             lds_barrier();                                                  // 4
-            // the keys placed in bucket order
+            // per bucket: its first class's start; the keys placed in counter order
+            if (tid <= ps.nbins) {
+                const uint32_t start = soff[tid << ss];  // soff[nsub]: the sub-tile's key count
+                if (!kInPlace && tid < ps.nbins) dst[tid] = gbase[tid] + run[tid] - start;
+                if (kInPlace) ps.tile_hist[t * (int64_t)(ps.nbins + 1) + tid] = start;
+            }
             if (rem > 0) {
 #pragma unroll
                 for (int u = 0; u < kPer; ++u)
                     if (rk[u] != ~0u) skeys[soff[rk[u] >> 16] + (rk[u] & 0xFFFFu)] = kv[u];
             }
             lds_barrier();                                                  // 5
-            const uint32_t nv = soff[ps.nbins];
+            const uint32_t nv = soff[nsub];
             if (nv > 0) {
                 // unrolled, reads at clamped indices, so that the LDS reads overlap
 #pragma unroll 8
@@ -620,7 +630,7 @@ __global__ __launch_bounds__(kScatThreads, 1) void scatter_kernel(PartStep ps) {
                 }
             }
             lds_barrier();                                                  // 6
-            if (!kInPlace && tid < ps.nbins) run[tid] += soff[tid + 1] - soff[tid];
+            if (!kInPlace && tid < ps.nbins) run[tid] += soff[(tid + 1) << ss] - soff[tid << ss];
         }
     }
 }
