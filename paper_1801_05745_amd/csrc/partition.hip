@@ -18,8 +18,9 @@
 //      per-tile counts are sums of the reservations' counts when the key pass
 //      took them, else a pass over the keys);
 //   3. level 2, in place: each 32768-key super-tile of a level-1 bucket is
-//      sorted by cell block (key >> 14) in LDS and written back where it was
-//      read, as 16-bit cells, with the start of every block's run in the tile;
+//      sorted by cell block (key >> 14) in LDS and written, as 16-bit cells,
+//      at the positions it was read from (in a 16-bit view of the other key
+//      buffer), with the start of every block's run in the tile;
 //   4. accumulate: one workgroup per 16384-cell block counts the keys of its
 //      runs (one per super-tile of its level-1 bucket) with LDS atomics and
 //      adds the block into the map with coalesced 16-byte read-modify-writes
@@ -524,8 +525,9 @@ __global__ __launch_bounds__(1024) void bucket_base_kernel(const uint32_t *tot, 
 // a bucket-order scan, an LDS sort, then contiguous runs written at base + tile
 // offset + running count.  Key order inside a bucket is irrelevant to the
 // counts, so the nondeterministic order of the atomics is harmless.
-// kInPlace (level 2): the sorted tile goes back to the positions it came from
-// and the tile's row of tile_hist receives its bucket starts.  Each bucket's
+// kInPlace (level 2): the sorted tile is written at the positions it was read
+// from (16-bit cells, in out16) and the tile's row of tile_hist receives its
+// bucket starts.  Each bucket's
 // count is split over 2^ss lane classes (lane mod 4, fewer when the buckets are
 // many: one counter per thread in the scan): the keys of a wave that share a
 // bucket, as spatially ordered particles' keys do, then contend on four LDS
