@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import ctypes
 import json
+import math
 import os
 from dataclasses import dataclass
 
@@ -199,6 +200,24 @@ def bin_shells_workspace(max_listed: int = 1 << 20, device="cuda"):
 MAX_PARTITION_KEYS = 0xFFF00000 - (1 << 25)
 
 
+def expected_keys(n, chi_edges, box_L, n_rep, shell_begin=0, shell_end=None, headroom=1.25):
+    """Keys a binning call of n particles is expected to emit: a particle uniform in
+    [0, L)^3 has on average V / L^3 images in the shell range (section 2.4), V the
+    volume between the range's radii, fewer when the range leaves the replicated
+    boxes; here with 25 % headroom, at most n (2 n_rep + 1)^3, and n without a box.
+    A partitioned workspace sized for it takes most calls in one chunk; a set with
+    more keys (strong clustering near the range's edges) runs in further chunks,
+    with the same counts."""
+    side = 2 * int(n_rep) + 1
+    if box_L <= 0.0:
+        return int(n)
+    e = [float(v) for v in chi_edges]
+    hi = e[len(e) - 1 if shell_end is None else int(shell_end)]
+    lo = e[int(shell_begin)]
+    per = min(4.0 / 3.0 * math.pi * (hi ** 3 - lo ** 3) / box_L ** 3 * headroom, float(side ** 3))
+    return int(min(n * side ** 3, math.ceil(n * per) + (1 << 20)))
+
+
 def partition_capacity(n, n_rep, shells_in_range, nside, nbytes):
     """Keys one chunk of the partitioned accumulation takes at least with a workspace of
     nbytes (0: that workspace selects the atomic path); a host computation."""
@@ -336,6 +355,8 @@ def bin_shells(x, y, z, chi_edges, nside, observer=None, box_L=0.0, n_rep=0, she
     if workspace is None:
         if method == "partition":
             workspace = partition_workspace(x.numel(), n_rep, int(shell_end) - int(shell_begin), nside,
+                                            max_keys=expected_keys(x.numel(), chi_edges, box_L, n_rep, shell_begin,
+                                                                   shell_end),
                                             device=x.device)
         elif method == "atomic":
             workspace = bin_shells_workspace(device=x.device)

@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_1801_05745_amd as uf
@@ -240,6 +241,30 @@ def test_partitioned_workspace_shared_by_a_batch():
                 assert cap >= k, (n, R, b, nside, k, cap)
 
 
+def test_expected_keys_is_the_mean_image_count_with_headroom():
+    # particles uniform in the box: the mean number of images inside the shell
+    # range is the range's volume over L^3 (brute force over the images)
+    rng = np.random.default_rng(4)
+    L, R, edges = 100.0, 1, [20.0, 55.0, 90.0, 140.0]
+    p = rng.random((200_000, 3)) * L - L / 2  # relative to the observer at the centre
+    s = np.array([(a, b, c) for a in range(-R, R + 1) for b in range(-R, R + 1) for c in range(-R, R + 1)]) * L
+    inside = 0
+    for off in s:
+        r = np.sqrt(((p + off) ** 2).sum(axis=1))
+        inside += int(((r >= edges[0]) & (r < edges[-1])).sum())
+    mean = inside / len(p)
+    v = 4 / 3 * np.pi * (edges[-1] ** 3 - edges[0] ** 3) / L ** 3
+    assert abs(mean - v) < 0.01 * v
+    n = 10_000_000
+    k = uf.expected_keys(n, edges, L, R)
+    assert n * v * 1.2 < k <= n * v * 1.25 + (1 << 20) + 1
+    # bounded by the images there are, and by one key per particle without a box
+    assert uf.expected_keys(n, [0.0, 1e4], L, R) == n * 27
+    assert uf.expected_keys(n, edges, 0.0, 0) == n
+    # a sub-range of shells expects fewer
+    assert uf.expected_keys(n, edges, L, R, 1, 2) < k
+
+
 def test_tuning_file_round_trip(tmp_path):
     # persisted autotuner choices: a file read into the cache is written back the same
     lines = ['{"arch":"gfx950","cus":256,"dtype":0,"nside":1024,"T":1,"items":16,"log2n":31,"max_rep":2,'
@@ -286,7 +311,6 @@ def test_fault_injection_switch(monkeypatch):
 
 def test_stream_checkpoint_files(tmp_path):
     """The resumable state of a chunked run: one whole state on disk at any time."""
-    import numpy as np
     import torch
 
     prefix = tmp_path / "run"
